@@ -65,8 +65,8 @@ def lib():
         L.or_counters.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_ulonglong)]
         L.or_face4.restype = ctypes.c_double
         L.or_face4.argtypes = [ctypes.c_double] * 4
-        L.or_smooth5.restype = ctypes.c_int
-        L.or_smooth5.argtypes = [_D]
+        L.or_smooth_weight.restype = ctypes.c_double
+        L.or_smooth_weight.argtypes = [_D]
         L.or_riemann.restype = ctypes.c_int
         L.or_riemann.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]
         L.or_ppb_pencil.restype = ctypes.c_int
@@ -195,9 +195,10 @@ def face4(am, a, b, bp) -> float:
     return lib().or_face4(am, a, b, bp)
 
 
-def smooth5(q) -> int:
+def smooth_weight(q) -> float:
+    """Weight of the unconstrained parabola for a 5-cell window."""
     q = np.ascontiguousarray(q, dtype=np.float64)
-    return lib().or_smooth5(q.ctypes.data_as(_D))
+    return lib().or_smooth_weight(q.ctypes.data_as(_D))
 
 
 def riemann(L, R, rho0f=0.0, p0f=0.0, gamma=1.4):

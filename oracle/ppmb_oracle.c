@@ -63,7 +63,8 @@ typedef struct {
     double base[6];       /* kind 1: rho, p.  kinds 2,3: rho_b, p_b, s_b, s_i, f_jump, s_end */
     int    heat_kind;     /* 0 none, 1 layer in z, 2 ball in r */
     double heat[3];       /* Q0, extent, z0 (kind 1) */
-    int    smooth_detect; /* 1: 5-cell smoothness test gates the constraints; 0: always constrain */
+    int    smooth_detect; /* 1: 5-cell smoothness test gates the constraints (the method);
+                             0: always constrain; 2: never constrain (ablations) */
 } or_params;
 
 typedef struct {
@@ -293,19 +294,25 @@ double or_face4(double am, double a, double b, double bp)
 }
 
 /* Sec. 1: smoothness judged on the 5 cells centred on the cell of interest.
-   [reading] The three second differences in the window are all zero, or all
-   of one strict sign with max <= 2 min in magnitude. */
-int or_smooth5(const double q[5])
+   [reading] With the three second differences D in the window: the data is
+   smooth (weight 1, no constraints) when all D are zero, or all share one
+   strict sign with max|D| <= 2 min|D|; not smooth (weight 0, constraints
+   applied) when their signs differ or max|D| >= 3 min|D|; the weight falls
+   linearly in between, so that the reconstruction depends continuously on
+   the data.  Returns the weight of the unconstrained parabola. */
+double or_smooth_weight(const double q[5])
 {
     double d[3];
     for (int k = 0; k < 3; ++k) d[k] = (q[k] + q[k + 2]) - 2.0 * q[k + 1];
-    if (d[0] == 0.0 && d[1] == 0.0 && d[2] == 0.0) return 1;
+    if (d[0] == 0.0 && d[1] == 0.0 && d[2] == 0.0) return 1.0;
     int pos = d[0] > 0.0 && d[1] > 0.0 && d[2] > 0.0;
     int neg = d[0] < 0.0 && d[1] < 0.0 && d[2] < 0.0;
-    if (!pos && !neg) return 0;
+    if (!pos && !neg) return 0.0;
     double a0 = fabs(d[0]), a1 = fabs(d[1]), a2 = fabs(d[2]);
     double mx = fmax(a0, fmax(a1, a2)), mn = fmin(a0, fmin(a1, a2));
-    return mx <= 2.0 * mn;
+    if (mx <= 2.0 * mn) return 1.0;
+    if (mx >= 3.0 * mn) return 0.0;
+    return (3.0 * mn - mx) / mn;
 }
 
 /* van Leer limited slope (CW84 eq. 1.8) */
@@ -638,17 +645,18 @@ static void pencil_update(pencil *pc, double dt, double dx, double gamma, int de
         for (int q = 0; q < 5; ++q)
             sm[q][J] = limited_slope(Q[q][J - 1], Q[q][J], Q[q][J + 1]);
     /* (4) parabolas, cells -2..n+1; constraints only where the 5-cell
-       window is not smooth (Sec. 1) */
+       window is not smooth (Sec. 1), blended in over the graded band */
     for (int J = 2; J <= m - 3; ++J) {
         for (int q = 0; q < 5; ++q) {
             double win[5] = { Q[q][J - 2], Q[q][J - 1], Q[q][J], Q[q][J + 1], Q[q][J + 2] };
-            int smooth = detect ? or_smooth5(win) : 0;
-            double l, r;
-            if (smooth) { l = qf[q][J - 1]; r = qf[q][J]; }
-            else {
-                l = face_limited(Q[q][J - 1], Q[q][J], sm[q][J - 1], sm[q][J]);
-                r = face_limited(Q[q][J], Q[q][J + 1], sm[q][J], sm[q][J + 1]);
-                constrain_parabola(Q[q][J], &l, &r);
+            double ws = detect == 1 ? or_smooth_weight(win) : (detect == 2 ? 1.0 : 0.0);
+            double l = qf[q][J - 1], r = qf[q][J];
+            if (ws < 1.0) {
+                double lc = face_limited(Q[q][J - 1], Q[q][J], sm[q][J - 1], sm[q][J]);
+                double rc = face_limited(Q[q][J], Q[q][J + 1], sm[q][J], sm[q][J + 1]);
+                constrain_parabola(Q[q][J], &lc, &rc);
+                if (ws > 0.0) { lc = lc + ws * (l - lc); rc = rc + ws * (r - rc); }
+                l = lc; r = rc;
                 if (J >= NG && J < NG + n) pc->unsmooth++;
             }
             qL[q][J] = l; qR[q][J] = r;

@@ -38,27 +38,44 @@ def test_interface_value_not_exact_on_quartic():
 
 
 @pytest.mark.parametrize("q,expect", [
-    ([1.0, 1.0, 1.0, 1.0, 1.0], 1),                 # constant
-    ([0.0, 1.0, 2.0, 3.0, 4.0], 1),                 # linear: all second differences 0
-    ([4.0, 1.0, 0.0, 1.0, 4.0], 1),                 # parabola: equal second differences
-    ([0.0, 0.0, 0.0, 1.0, 1.0], 0),                 # jump inside the window
-    ([0.0, 1.0, 0.0, 1.0, 0.0], 0),                 # odd-even oscillation
-    ([0.0, 0.0, 1.0, 0.0, 0.0], 0),                 # spike: |D| ratio 2 -> but signs differ
+    ([1.0, 1.0, 1.0, 1.0, 1.0], 1.0),               # constant
+    ([0.0, 1.0, 2.0, 3.0, 4.0], 1.0),               # linear: all second differences 0
+    ([4.0, 1.0, 0.0, 1.0, 4.0], 1.0),               # parabola: equal second differences
+    ([0.0, 0.0, 0.0, 1.0, 1.0], 0.0),               # jump inside the window
+    ([0.0, 1.0, 0.0, 1.0, 0.0], 0.0),               # odd-even oscillation
+    ([0.0, 0.0, 1.0, 0.0, 0.0], 0.0),               # spike: second differences change sign
+    ([0.0, 1.0, 3.0, 6.0, 10.0], 1.0),              # D = 1, 1, 1
+    ([0.0, 1.0, 3.0, 7.0, 13.0], 1.0),              # D = 1, 2, 2: ratio 2 is smooth
+    ([0.0, 1.0, 3.0, 7.5, 14.0], 0.5),              # D = 1, 2.5, 2: ratio 2.5, halfway
+    ([0.0, 1.0, 3.0, 8.0, 15.0], 0.0),              # D = 1, 3, 2: ratio 3 is not smooth
 ])
-def test_smoothness_detector_cases(q, expect):
-    assert oracle.smooth5(np.array(q)) == expect
+def test_smoothness_weight_cases(q, expect):
+    assert oracle.smooth_weight(np.array(q)) == expect
+
+
+def test_smoothness_weight_is_continuous_and_symmetric():
+    # the weight varies continuously through the graded band, and is the same
+    # for the mirrored and the negated window
+    xs = np.linspace(7.0, 8.0, 201)
+    w = [oracle.smooth_weight(np.array([0.0, 1.0, 3.0, x, 2 * x - 1.0])) for x in xs]
+    assert max(abs(a - b) for a, b in zip(w[1:], w[:-1])) <= 0.011
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        q = np.cumsum(np.cumsum(rng.uniform(0.5, 1.5, 5)))
+        a = oracle.smooth_weight(q)
+        assert oracle.smooth_weight(q[::-1]) == a and oracle.smooth_weight(-q) == a
 
 
 def test_smoothness_sinusoid_extremum_is_smooth():
     # a sampled sinusoid with >= 6 cells per wavelength is smooth at its crest
     for ppw in (6, 8, 16, 64):
         x = np.arange(-2, 3) * (2 * math.pi / ppw)
-        assert oracle.smooth5(np.cos(x)) == 1
+        assert oracle.smooth_weight(np.cos(x)) == 1.0
 
 
 def test_smoothness_kink_not_smooth():
     x = np.arange(-2, 3) * 0.1
-    assert oracle.smooth5(np.abs(x)) == 0
+    assert oracle.smooth_weight(np.abs(x)) == 0.0
 
 
 def collision_pstar(rho, p, U, g):
