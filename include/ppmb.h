@@ -1,0 +1,207 @@
+/*
+ * ppmb.h -- C ABI of the MI355X (gfx950) PPM + PPB library.
+ *
+ * The library advances the directionally split 3-D PPM gas-dynamics step
+ * coupled to PPB multifluid advection of Woodward, Lin, Mao, Andrassy &
+ * Herwig (arXiv 1810.13416):
+ *   - Sec. 1: cell-interface values one order higher than the parabola;
+ *     monotonicity constraints only where a 5-cell smoothness test fails;
+ *     a hydrostatic base state subtracted out so that the sweeps can run in
+ *     32-bit arithmetic; PPB moment-conserving advection of the entrained
+ *     fluid fraction fv;
+ *   - Sec. 3: gravity tapered to zero a few cells inside an impenetrable
+ *     confining sphere inscribed in the cube;
+ *   - Sec. 4: fv carried as its cell average and 9 lowest moments, all
+ *     updated by 1-D passes; the pass stencil reaches 4 cells.
+ *
+ * Conventions (every entry point):
+ *   - Returns ppmb_status; 0 (PPMB_OK) is success.  No C++ exception crosses
+ *     the ABI.  ppmb_last_error() gives a text for the last failure of a
+ *     context.
+ *   - Grids are x-fastest structure-of-arrays: field q of cell (i, j, k) sits
+ *     at element q * ncell + (k * ny + j) * nx + i, ncell = nx * ny * nz.
+ *   - Host pointers are named host_*; device pointers dev_*.  The library
+ *     never frees memory it did not allocate.
+ *   - Calls that take a context enqueue work on the context's HIP stream and
+ *     return without waiting, unless documented as synchronising.
+ *     Asynchronous HIP errors surface at the next synchronising call.
+ *   - A context is used by one host thread at a time.
+ *
+ * The 15 evolving fields, in order:
+ *   0 rho'  1 m_x  2 m_y  3 m_z  4 E'       (conserved perturbations of the
+ *          base state: rho' = rho - rho0, m = rho u, E' = E - p0/(gamma-1))
+ *   5 f0  6 fx  7 fy  8 fz  9 fxx 10 fyy 11 fzz 12 fxy 13 fyz 14 fzx
+ *          (fv as coefficients of the orthogonal basis 1, x, y, z, P2(x),
+ *           P2(y), P2(z), xy, yz, zx on the unit cell, P2(s) = s^2 - 1/12)
+ * Primitive exchange arrays (set/get state) hold instead
+ *   0 rho' 1 u_x 2 u_y 3 u_z 4 p'  followed by the same 10 fv coefficients.
+ */
+#ifndef PPMB_H
+#define PPMB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PPMB_OK = 0,
+    PPMB_ERR_INVALID = -1,      /* bad argument, shape or call order */
+    PPMB_ERR_NOMEM = -2,        /* device allocation failed */
+    PPMB_ERR_HIP = -3,          /* a HIP runtime call or kernel failed */
+    PPMB_ERR_NONPHYSICAL = -4,  /* non-positive density or pressure, or NaN, found */
+    PPMB_ERR_UNSUPPORTED = -6   /* a combination the library does not implement */
+} ppmb_status;
+
+typedef enum {
+    PPMB_FP64 = 0,              /* state, sweeps and reductions in FP64 */
+    PPMB_FP32 = 1               /* state and sweeps in FP32; base state
+                                   integration, dt and totals in FP64, and
+                                   an FP64 re-solve of Riemann problems whose
+                                   FP32 iteration has not converged (Sec. 1:
+                                   32-bit sweeps on perturbations) */
+} ppmb_precision;
+
+enum { PPMB_BC_PERIODIC = 0, PPMB_BC_REFLECT = 1 };
+enum { PPMB_GRAV_NONE = 0, PPMB_GRAV_CONST = 1, PPMB_GRAV_RADIAL = 2 };
+enum { PPMB_BASE_NONE = 0, PPMB_BASE_CONST = 1, PPMB_BASE_POLY_Z = 2, PPMB_BASE_POLY_R = 3 };
+enum { PPMB_HEAT_NONE = 0, PPMB_HEAT_LAYER_Z = 1, PPMB_HEAT_BALL = 2 };
+enum { PPMB_NFIELDS = 15 };
+
+/* Grid and physics.  Cell (i, j, k) has centre origin + (index + 1/2) dx.
+ *   bc[d]        boundary on both ends of axis d: periodic or reflecting
+ *   sphere       1: cells whose centre lies at r >= sphere_r from the origin
+ *                of coordinates are solid (Sec. 3 confining sphere); faces
+ *                between fluid and solid cells are reflecting walls
+ *   grav_kind    CONST: grav[0..2] is the acceleration vector.
+ *                RADIAL: g = -grav[0] r_hat * (r/grav[1] for r < grav[1],
+ *                else (grav[1]/r)^2), times a taper falling linearly from 1
+ *                at r = grav[2] to 0 at r = grav[3] (Sec. 3)
+ *   heat_kind    LAYER_Z: energy source heat[0] * h((z - heat[2]) / heat[1]);
+ *                BALL: heat[0] * h(r / heat[1]); h = 1 below 1/2, smoothstep
+ *                down to 0 at 1
+ *   smooth_detect 1: the 5-cell smoothness test gates the constraints (the
+ *                method); 0: constraints everywhere; 2: no constraints
+ *                (the last two for comparison) */
+typedef struct {
+    int    n[3];
+    double dx;
+    double origin[3];
+    int    bc[3];
+    double gamma;
+    int    sphere;
+    double sphere_r;
+    int    grav_kind;
+    double grav[4];
+    int    heat_kind;
+    double heat[3];
+    int    smooth_detect;
+} ppmb_grid;
+
+typedef struct ppmb_ctx ppmb_ctx;
+
+/* Create a context for one grid on `hip_stream` (a hipStream_t; NULL = the
+ * null stream).  Allocates the library's own device buffers: the FP64 base
+ * state (2 fields), its copy in the working precision, reduction buffers and
+ * counters.  The state itself is caller memory bound with
+ * ppmb_bind_state().  Errors: INVALID for n < 1, dx <= 0, gamma <= 1 or an
+ * unknown kind; NOMEM; HIP. */
+ppmb_status ppmb_create(const ppmb_grid *grid, ppmb_precision prec, void *hip_stream,
+                        ppmb_ctx **out);
+
+/* Synchronise the stream, then free the library's buffers and the context. */
+ppmb_status ppmb_destroy(ppmb_ctx *ctx);
+
+/* Bytes the caller must provide per state buffer: 15 * ncell * elem_size
+ * (elem_size 8 for FP64, 4 for FP32). */
+ppmb_status ppmb_state_bytes(const ppmb_ctx *ctx, size_t *bytes, size_t *elem_size);
+
+/* Bind two caller-owned device buffers of ppmb_state_bytes() each.  Passes
+ * read one and write the other (ping-pong); ppmb_current_state() names the
+ * one holding the latest state.  The caller keeps both alive until destroy
+ * and must not touch them while work is queued.  Errors: INVALID for NULL
+ * or identical pointers. */
+ppmb_status ppmb_bind_state(ppmb_ctx *ctx, void *dev_buf_a, void *dev_buf_b);
+ppmb_status ppmb_current_state(const ppmb_ctx *ctx, void **dev_state);
+
+/* Hydrostatic base state (Sec. 1: the initial state is saved on the grid and
+ * subtracted out).  kind NONE: no base (plain form, the state is the full
+ * state).  CONST: rho0 = params[0], p0 = params[1].  POLY_Z / POLY_R:
+ * piecewise polytrope in hydrostatic balance with the grid's gravity along z
+ * (constant gravity) or r (radial gravity): rho0 = params[0] and
+ * p0 = params[1] at s = params[2]; the density jumps by the factor params[4]
+ * at continuous pressure at s = params[3]; tables reach s = params[5].
+ * Integrated on the GPU in FP64 (RK4, 8 steps per cell width, segments split
+ * at the jump and every kink of g), then written to the base fields.
+ * Synchronising.  Call before ppmb_set_state. */
+ppmb_status ppmb_set_base_state(ppmb_ctx *ctx, int kind, const double params[6]);
+
+/* Copy the FP64 base fields (rho0, p0; ncell each) to host memory.
+ * Synchronising. */
+ppmb_status ppmb_get_base(ppmb_ctx *ctx, double *host_rho0, double *host_p0);
+
+/* Set the state from 15 FP64 host arrays of primitive perturbations
+ * (rho', u_x, u_y, u_z, p', then the 10 fv coefficients), converted on the
+ * GPU to the conserved perturbation fields of the working precision.
+ * Synchronising (the host arrays may be reused on return). */
+ppmb_status ppmb_set_state(ppmb_ctx *ctx, const double *const host_prim[15]);
+
+/* Same, from 15 FP64 device arrays (ncell each). */
+ppmb_status ppmb_set_state_device(ppmb_ctx *ctx, const double *const dev_prim[15]);
+
+/* Read the state back as 15 FP64 host arrays of primitive perturbations.
+ * Synchronising. */
+ppmb_status ppmb_get_state(ppmb_ctx *ctx, double *const host_prim[15]);
+
+/* Conserved fields (the stored representation, widened to FP64) for
+ * checkpoints; set_conserved rounds to the working precision.
+ * Synchronising. */
+ppmb_status ppmb_get_conserved(ppmb_ctx *ctx, double *const host_cons[15]);
+ppmb_status ppmb_set_conserved(ppmb_ctx *ctx, const double *const host_cons[15]);
+
+/* CFL time step dt = cfl * dx / max over fluid cells and axes of |u_d| + c,
+ * computed in FP64 from the stored state.  Synchronising.  Errors:
+ * NONPHYSICAL if a fluid cell has rho <= 0, p <= 0 or a NaN. */
+ppmb_status ppmb_compute_dt(ppmb_ctx *ctx, double cfl, double *dt_out);
+
+/* One step of size dt: three 1-D passes, x,y,z on even steps and z,y,x on
+ * odd steps, then the heating source.  Asynchronous. */
+ppmb_status ppmb_step(ppmb_ctx *ctx, double dt);
+
+/* `nsteps` steps, each taking dt from the CFL condition of the state at its
+ * start, computed on the device: no host synchronisation.  The dt of the
+ * last step is readable with ppmb_last_dt().  Asynchronous. */
+ppmb_status ppmb_step_auto(ppmb_ctx *ctx, double cfl, int nsteps);
+ppmb_status ppmb_last_dt(ppmb_ctx *ctx, double *dt_out);   /* synchronising */
+
+/* One 1-D pass along `axis` (0, 1, 2) with step dt; `heat` = 1 adds the
+ * heating source for dt to the updated cells.  Does not advance the step
+ * counter.  Asynchronous. */
+ppmb_status ppmb_pass(ppmb_ctx *ctx, int axis, double dt, int heat);
+
+/* Step counter (its parity selects the pass order); set it when resuming a
+ * checkpoint. */
+ppmb_status ppmb_get_nstep(const ppmb_ctx *ctx, long *nstep);
+ppmb_status ppmb_set_nstep(ppmb_ctx *ctx, long nstep);
+
+/* Conserved totals over fluid cells in FP64 with a fixed reduction tree
+ * (bitwise reproducible): out = { mass, p_x, p_y, p_z, total energy (base
+ * included), fv volume, min f0, max f0 }.  Synchronising. */
+ppmb_status ppmb_reduce_totals(ppmb_ctx *ctx, double out[8]);
+
+/* Event counters since create: { fv limiter activations that changed a
+ * profile by more than round-off, unsmooth (cell, variable) pairs
+ * constrained, Riemann problems re-solved in FP64 (FP32) or not converged
+ * (FP64), steps }.  Synchronising. */
+ppmb_status ppmb_counters(ppmb_ctx *ctx, unsigned long long out[4]);
+
+ppmb_status ppmb_synchronize(ppmb_ctx *ctx);
+const char *ppmb_status_string(ppmb_status s);
+const char *ppmb_last_error(const ppmb_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPMB_H */

@@ -1,0 +1,394 @@
+// ppmb_aux.hip -- FP64 base-state integration, state conversions, the CFL
+// time-step reduction and the conserved-total reduction (gfx950).
+//
+// Built with -ffp-contract=off: none of this is on the per-pass hot path,
+// and uncontracted FP64 keeps these results reproducible bit for bit.
+#include "ppmb_internal.h"
+
+#include <cmath>
+
+namespace ppmb {
+
+// ---------------------------------------------------------------------
+// Base state (Sec. 1: the initial hydrostatic state is saved on the grid
+// and subtracted out).  dp/ds = rho(p, s) g_s(s), rho = (p/K)^(1/gamma),
+// K jumping at the entropy step so that rho jumps by f at continuous p.
+// ---------------------------------------------------------------------
+
+enum { MAXSEG = 6, HDR = 1 + 6 * MAXSEG };
+
+__device__ double base_gs(const Geom &g, int kind, double s)
+{
+    if (kind == 2) return g.grav_kind == 1 ? g.grav[2] : 0.0;
+    if (g.grav_kind != 2) return 0.0;
+    double rc = g.grav[1];
+    double shape = (s < rc) ? s / rc : (rc * rc) / (s * s);
+    return -g.grav[0] * shape * grav_taper(g, s);
+}
+
+__device__ double base_rhs(const Geom &g, int kind, double K, double s, double p)
+{
+    return pow(p / K, 1.0 / g.gamma) * base_gs(g, kind, s);
+}
+
+__device__ double rk4(const Geom &g, int kind, double K, double s, double p, double h)
+{
+    double k1 = base_rhs(g, kind, K, s, p);
+    double k2 = base_rhs(g, kind, K, s + 0.5 * h, p + 0.5 * h * k1);
+    double k3 = base_rhs(g, kind, K, s + 0.5 * h, p + 0.5 * h * k2);
+    double k4 = base_rhs(g, kind, K, s + h, p + h * k3);
+    return p + h * (k1 + 2.0 * k2 + 2.0 * k3 + k4) / 6.0;
+}
+
+struct BaseParams { double v[6]; };
+
+// One thread: segment the interval [s_b, s_end] at the entropy jump and at
+// every kink of the gravity profile, then RK4 with 8 steps per cell width.
+// Table: [nseg, then per segment s0, s1, h, K, m, node offset], then nodes.
+__global__ void base_table_kernel(Geom g, int kind, BaseParams bp, double *tab, long len)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double rho_b = bp.v[0], p_b = bp.v[1], s_b = bp.v[2], s_i = bp.v[3], f = bp.v[4],
+                 s_end = bp.v[5];
+    const double K1 = p_b / pow(rho_b, g.gamma);
+    const double K2 = K1 * pow(f, -g.gamma);
+    const double hmax = g.dx / 8.0;
+    double br[MAXSEG + 1];
+    int nb = 0;
+    br[nb++] = s_b;
+    double cand[4] = { s_i, 0.0, 0.0, 0.0 };
+    int nc = 1;
+    if (kind == 3 && g.grav_kind == 2) { cand[1] = g.grav[1]; cand[2] = g.grav[2]; cand[3] = g.grav[3]; nc = 4; }
+    for (int q = 0; q < nc; ++q) {
+        double c = cand[q];
+        if (!(c > s_b && c < s_end)) continue;
+        bool dup = false;
+        for (int r = 0; r < nb; ++r) dup = dup || (br[r] == c);
+        if (dup) continue;
+        int at = nb;
+        while (at > 1 && br[at - 1] > c) { br[at] = br[at - 1]; --at; }
+        br[at] = c;
+        ++nb;
+    }
+    br[nb++] = s_end;
+    const int nseg = nb - 1;
+    tab[0] = nseg;
+    long off = HDR;
+    double p = p_b;
+    for (int sg = 0; sg < nseg; ++sg) {
+        double a = br[sg], b = br[sg + 1];
+        int m = (int)ceil((b - a) / hmax);
+        if (m < 1) m = 1;
+        double h = (b - a) / m;
+        double K = (a >= s_i) ? K2 : K1;
+        double *hd = tab + 1 + 6 * sg;
+        hd[0] = a; hd[1] = b; hd[2] = h; hd[3] = K; hd[4] = m; hd[5] = (double)off;
+        if (off + m + 1 > len) { tab[0] = -1.0; return; }
+        tab[off] = p;
+        for (int q = 0; q < m; ++q) tab[off + q + 1] = rk4(g, kind, K, a + q * h, tab[off + q], h);
+        p = tab[off + m];
+        off += m + 1;
+    }
+}
+
+// Cell values: one RK4 step from the nearest node below each cell centre.
+__global__ void base_fill_kernel(Geom g, int kind, BaseParams bp, const double *tab, long len,
+                                 double *rho0, double *p0)
+{
+    long nc = (long)g.n[0] * g.n[1] * g.n[2];
+    // a table that did not fit leaves nseg = -1: write NaN, read nothing
+    const int nseg_all = (kind == 2 || kind == 3) ? (int)tab[0] : 1;
+    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
+        if (kind == 0 || kind == 1) {
+            rho0[c] = (kind == 1) ? bp.v[0] : 0.0;
+            p0[c] = (kind == 1) ? bp.v[1] : 0.0;
+            continue;
+        }
+        int i = (int)(c % g.n[0]);
+        int j = (int)((c / g.n[0]) % g.n[1]);
+        int k = (int)(c / ((long)g.n[0] * g.n[1]));
+        double x = centre(g, 0, i), y = centre(g, 1, j), z = centre(g, 2, k);
+        double s = (kind == 2) ? z : sqrt(r2_exact(x, y, z));
+        if (nseg_all < 1 || nseg_all > MAXSEG) { rho0[c] = NAN; p0[c] = NAN; continue; }
+        int sg = 0;
+        while (sg < nseg_all - 1 && s >= tab[1 + 6 * sg + 1]) ++sg;
+        const double *hd = tab + 1 + 6 * sg;
+        double s0 = hd[0], h = hd[2], K = hd[3];
+        int m = (int)hd[4];
+        long off = (long)hd[5];
+        int q = (int)floor((s - s0) / h);
+        if (q < 0) q = 0;
+        if (q > m - 1) q = m - 1;
+        if (off < HDR || off + q >= len) { rho0[c] = NAN; p0[c] = NAN; continue; }
+        double sq = s0 + q * h;
+        double pv = rk4(g, kind, K, sq, tab[off + q], s - sq);
+        p0[c] = pv;
+        rho0[c] = pow(pv / K, 1.0 / g.gamma);
+    }
+}
+
+hipError_t launch_base_state(const Geom &g, int kind, const double *params, double *table,
+                             long table_len, double *rho0, double *p0, hipStream_t st)
+{
+    BaseParams bp;
+    for (int q = 0; q < 6; ++q) bp.v[q] = params ? params[q] : 0.0;
+    if (kind == 2 || kind == 3)
+        hipLaunchKernelGGL(base_table_kernel, dim3(1), dim3(64), 0, st, g, kind, bp, table, table_len);
+    hipLaunchKernelGGL(base_fill_kernel, dim3(4096), dim3(256), 0, st, g, kind, bp, table, table_len, rho0, p0);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// Conversions
+// ---------------------------------------------------------------------
+
+struct PrimPtrs { const double *p[NF]; };
+struct OutPtrs { double *p[NF]; };
+
+template <typename T>
+__global__ void prim_to_cons_kernel(long nc, double gm1, PrimPtrs P, const double *rho0, T *S)
+{
+    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
+        double rho = rho0[c] + P.p[0][c];
+        double u = P.p[1][c], v = P.p[2][c], w = P.p[3][c];
+        S[RHO * nc + c] = T(P.p[0][c]);
+        S[MX * nc + c] = T(rho * u);
+        S[MY * nc + c] = T(rho * v);
+        S[MZ * nc + c] = T(rho * w);
+        S[EN * nc + c] = T(P.p[4][c] / gm1 + 0.5 * rho * ((u * u + v * v) + w * w));
+        for (int q = 5; q < NF; ++q) S[q * nc + c] = T(P.p[q][c]);
+    }
+}
+
+template <typename T>
+__global__ void cons_to_prim_kernel(long nc, double gm1, const T *S, const double *rho0, double *out)
+{
+    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
+        double rp = S[RHO * nc + c], mx = S[MX * nc + c], my = S[MY * nc + c], mz = S[MZ * nc + c];
+        double e = S[EN * nc + c];
+        double rho = rho0[c] + rp;
+        double u = mx / rho, v = my / rho, w = mz / rho;
+        out[0 * nc + c] = rp;
+        out[1 * nc + c] = u;
+        out[2 * nc + c] = v;
+        out[3 * nc + c] = w;
+        out[4 * nc + c] = gm1 * (e - 0.5 * (mx * u + my * v + mz * w));
+        for (int q = 5; q < NF; ++q) out[q * nc + c] = S[q * nc + c];
+    }
+}
+
+template <typename A, typename B>
+__global__ void convert_kernel(const A *src, B *dst, long count)
+{
+    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < count; c += (long)gridDim.x * blockDim.x)
+        dst[c] = B(src[c]);
+}
+
+template <typename T>
+hipError_t launch_prim_to_cons(const Geom &g, const double *const *prim, const double *rho0,
+                               T *state, hipStream_t st)
+{
+    PrimPtrs P;
+    for (int q = 0; q < NF; ++q) P.p[q] = prim[q];
+    long nc = (long)g.n[0] * g.n[1] * g.n[2];
+    hipLaunchKernelGGL((prim_to_cons_kernel<T>), dim3(4096), dim3(256), 0, st, nc, g.gamma - 1.0, P, rho0, state);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cons_to_prim(const Geom &g, const T *state, const double *rho0, double *prim,
+                               hipStream_t st)
+{
+    long nc = (long)g.n[0] * g.n[1] * g.n[2];
+    hipLaunchKernelGGL((cons_to_prim_kernel<T>), dim3(4096), dim3(256), 0, st, nc, g.gamma - 1.0, state, rho0, prim);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_widen(const T *src, double *dst, long count, hipStream_t st)
+{
+    hipLaunchKernelGGL((convert_kernel<T, double>), dim3(4096), dim3(256), 0, st, src, dst, count);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_narrow(const double *src, T *dst, long count, hipStream_t st)
+{
+    hipLaunchKernelGGL((convert_kernel<double, T>), dim3(4096), dim3(256), 0, st, src, dst, count);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// CFL time step: dt = cfl dx / max over fluid cells and axes of |u_d| + c,
+// all in FP64.  The maximum is order independent, so it is exact.
+// ---------------------------------------------------------------------
+
+__global__ void cfl_reset_kernel(unsigned long long *work)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) work[0] = 0ull;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cfl_kernel(Geom g, const T *S, const double *rho0,
+                                                  const double *p0, unsigned long long *work)
+{
+    const long nc = (long)g.n[0] * g.n[1] * g.n[2];
+    const double gm1 = g.gamma - 1.0;
+    double smax = 0.0;
+    bool bad = false;
+    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
+        if (g.sphere) {
+            int i = (int)(c % g.n[0]);
+            int j = (int)((c / g.n[0]) % g.n[1]);
+            int k = (int)(c / ((long)g.n[0] * g.n[1]));
+            if (solid_at(g, centre(g, 0, i), centre(g, 1, j), centre(g, 2, k))) continue;
+        }
+        double mx = S[MX * nc + c], my = S[MY * nc + c], mz = S[MZ * nc + c];
+        double rho = rho0[c] + (double)S[RHO * nc + c];
+        double u = mx / rho, v = my / rho, w = mz / rho;
+        double pp = gm1 * ((double)S[EN * nc + c] - 0.5 * (mx * u + my * v + mz * w));
+        double p = p0[c] + pp;
+        double cs = sqrt(g.gamma * p / rho);
+        double s = fmax(fabs(u), fmax(fabs(v), fabs(w))) + cs;
+        if (!(rho > 0.0) || !(p > 0.0) || !(s == s) || s > 1e300) bad = true;
+        else if (s > smax) smax = s;
+    }
+    // wave64 max, then one atomic per wave (positive doubles order like their bits)
+    for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_down(smax, off));
+    unsigned long long b = __ballot(bad);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&work[0], (unsigned long long)__double_as_longlong(smax));
+        if (b) atomicOr(&work[1], 1ull);
+    }
+}
+
+__global__ void cfl_finish_kernel(const unsigned long long *work, double cfl, double dx, double *dtp)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double smax = __longlong_as_double((long long)work[0]);
+        dtp[0] = cfl * dx / smax;
+    }
+}
+
+template <typename T>
+hipError_t launch_cfl(const Geom &g, const T *state, const double *rho0, const double *p0,
+                      unsigned long long *work, double cfl, double *dtp, hipStream_t st)
+{
+    hipLaunchKernelGGL(cfl_reset_kernel, dim3(1), dim3(64), 0, st, work);
+    hipLaunchKernelGGL((cfl_kernel<T>), dim3(2048), dim3(256), 0, st, g, state, rho0, p0, work);
+    hipLaunchKernelGGL(cfl_finish_kernel, dim3(1), dim3(64), 0, st, work, cfl, g.dx, dtp);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// Totals: 6 sums and min / max of f0 over fluid cells.  Each thread walks
+// a fixed stride of cells, each block reduces by a fixed tree, one final
+// block reduces the block partials by a fixed tree: bitwise reproducible.
+// ---------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void totals_kernel(Geom g, const T *S, const double *rho0,
+                                                     const double *p0, double *partials)
+{
+    __shared__ double sh[8][256];
+    const long nc = (long)g.n[0] * g.n[1] * g.n[2];
+    const double gm1 = g.gamma - 1.0;
+    double acc[8] = { 0, 0, 0, 0, 0, 0, INFINITY, -INFINITY };
+    for (long c = blockIdx.x * 256L + threadIdx.x; c < nc; c += (long)kTotalsBlocks * 256) {
+        if (g.sphere) {
+            int i = (int)(c % g.n[0]);
+            int j = (int)((c / g.n[0]) % g.n[1]);
+            int k = (int)(c / ((long)g.n[0] * g.n[1]));
+            if (solid_at(g, centre(g, 0, i), centre(g, 1, j), centre(g, 2, k))) continue;
+        }
+        double f0 = S[F0 * nc + c];
+        acc[0] += rho0[c] + (double)S[RHO * nc + c];
+        acc[1] += (double)S[MX * nc + c];
+        acc[2] += (double)S[MY * nc + c];
+        acc[3] += (double)S[MZ * nc + c];
+        acc[4] += p0[c] / gm1 + (double)S[EN * nc + c];
+        acc[5] += f0;
+        acc[6] = fmin(acc[6], f0);
+        acc[7] = fmax(acc[7], f0);
+    }
+    for (int q = 0; q < 8; ++q) sh[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int q = 0; q < 6; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+            sh[6][threadIdx.x] = fmin(sh[6][threadIdx.x], sh[6][threadIdx.x + w]);
+            sh[7][threadIdx.x] = fmax(sh[7][threadIdx.x], sh[7][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 8; ++q) partials[blockIdx.x * 8 + q] = sh[q][0];
+}
+
+__global__ __launch_bounds__(1024) void totals_finish_kernel(const double *partials, double dv, double *out)
+{
+    __shared__ double sh[8][kTotalsBlocks];
+    for (int q = 0; q < 8; ++q) sh[q][threadIdx.x] = partials[threadIdx.x * 8 + q];
+    __syncthreads();
+    for (int w = kTotalsBlocks / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int q = 0; q < 6; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+            sh[6][threadIdx.x] = fmin(sh[6][threadIdx.x], sh[6][threadIdx.x + w]);
+            sh[7][threadIdx.x] = fmax(sh[7][threadIdx.x], sh[7][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 6; ++q) out[q] = sh[q][0] * dv;
+        out[6] = sh[6][0];
+        out[7] = sh[7][0];
+    }
+}
+
+template <typename T>
+hipError_t launch_totals(const Geom &g, const T *state, const double *rho0, const double *p0,
+                         double *partials, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL((totals_kernel<T>), dim3(kTotalsBlocks), dim3(256), 0, st, g, state, rho0, p0, partials);
+    hipLaunchKernelGGL(totals_finish_kernel, dim3(1), dim3(kTotalsBlocks), 0, st, partials,
+                       g.dx * g.dx * g.dx, out);
+    return hipGetLastError();
+}
+
+__global__ void set_scalar_kernel(double *dst, double v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = v;
+}
+
+__global__ void zero_u64_kernel(unsigned long long *dst, int count)
+{
+    for (int q = threadIdx.x; q < count; q += blockDim.x) dst[q] = 0ull;
+}
+
+hipError_t launch_set_scalar(double *dst, double v, hipStream_t st)
+{
+    hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(64), 0, st, dst, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long *dst, int count, hipStream_t st)
+{
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, dst, count);
+    return hipGetLastError();
+}
+
+#define PPMB_INST(T)                                                                              \
+    template hipError_t launch_prim_to_cons<T>(const Geom &, const double *const *, const double *, \
+                                               T *, hipStream_t);                                 \
+    template hipError_t launch_cons_to_prim<T>(const Geom &, const T *, const double *, double *,  \
+                                               hipStream_t);                                      \
+    template hipError_t launch_widen<T>(const T *, double *, long, hipStream_t);                   \
+    template hipError_t launch_narrow<T>(const double *, T *, long, hipStream_t);                  \
+    template hipError_t launch_cfl<T>(const Geom &, const T *, const double *, const double *,     \
+                                      unsigned long long *, double, double *, hipStream_t);       \
+    template hipError_t launch_totals<T>(const Geom &, const T *, const double *, const double *,  \
+                                         double *, double *, hipStream_t);
+PPMB_INST(float)
+PPMB_INST(double)
+
+}  // namespace ppmb

@@ -1,0 +1,389 @@
+// ppmb_dev.h -- device building blocks of the 1-D PPM + PPB pass (gfx950).
+//
+// Each function is one step of the pass as the paper describes it in words
+// (Sec. 1, Sec. 4), with the formulas of the canonical PPM paper (Colella &
+// Woodward 1984, "CW84") where the paper defers to its references.  All are
+// templated on the working precision T (float or double).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ppmb {
+
+enum { NG = 4, NF = 15 };
+enum { RHO = 0, MX = 1, MY = 2, MZ = 3, EN = 4, F0 = 5, FX = 6, FY = 7, FZ = 8,
+       FXX = 9, FYY = 10, FZZ = 11, FXY = 12, FYZ = 13, FZX = 14 };
+
+// Grid and physics parameters, passed by value to every kernel.
+struct Geom {
+    int    n[3];
+    double dx;
+    double origin[3];
+    int    bc[3];
+    double gamma;
+    int    sphere;
+    double sphere_r;
+    int    grav_kind;
+    double grav[4];
+    int    heat_kind;
+    double heat[3];
+    int    smooth_detect;
+};
+
+template <typename T> __device__ __forceinline__ T tabs(T a) { return a < T(0) ? -a : a; }
+template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return b < a ? b : a; }
+template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a < b ? b : a; }
+
+// ---------------------------------------------------------------------
+// Geometry: ghost mapping, gravity, heating, confining sphere
+// ---------------------------------------------------------------------
+
+// Source cell of pencil index j on an axis of n cells; flip = -1 when the
+// cell is seen through an odd number of reflecting walls.
+__device__ __forceinline__ int bc_source(int j, int n, int bc, int &flip)
+{
+    flip = 1;
+    if (bc == 0) {
+        int k = j % n;
+        return k < 0 ? k + n : k;
+    }
+    int p = 2 * n;
+    int k = j % p;
+    if (k < 0) k += p;
+    if (k < n) return k;
+    flip = -1;
+    return p - 1 - k;
+}
+
+// Cell-centre coordinate (FP64).
+__device__ __forceinline__ double centre(const Geom &g, int axis, int i)
+{
+    return g.origin[axis] + ((double)i + 0.5) * g.dx;
+}
+
+// |x|^2 evaluated without contraction so that the solid test agrees
+// bit for bit with any IEEE implementation of the same expression.
+__device__ __forceinline__ double r2_exact(double x, double y, double z)
+{
+    return __dadd_rn(__dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y)), __dmul_rn(z, z));
+}
+
+// Sec. 3: cells outside the inscribed sphere are solid.
+__device__ __forceinline__ bool solid_at(const Geom &g, double x, double y, double z)
+{
+    if (!g.sphere) return false;
+    return sqrt(r2_exact(x, y, z)) >= g.sphere_r;
+}
+
+// Sec. 3: gravity falls to zero a few cells before the sphere; linear taper.
+__device__ __forceinline__ double grav_taper(const Geom &g, double r)
+{
+    if (r <= g.grav[2]) return 1.0;
+    if (r >= g.grav[3]) return 0.0;
+    return (g.grav[3] - r) / (g.grav[3] - g.grav[2]);
+}
+
+// Component `axis` of the gravitational acceleration at a cell centre.
+template <typename T>
+__device__ __forceinline__ T gravity(const Geom &g, int axis, double x, double y, double z)
+{
+    if (g.grav_kind == 1) return T(g.grav[axis]);
+    if (g.grav_kind == 2) {
+        double r = sqrt(r2_exact(x, y, z));
+        double rc = g.grav[1];
+        double h = (r < rc) ? 1.0 / rc : (rc * rc) / (r * r * r);
+        double xd = axis == 0 ? x : (axis == 1 ? y : z);
+        return T(-g.grav[0] * xd * h * grav_taper(g, r));
+    }
+    return T(0);
+}
+
+// Heating profile: full below half the extent, smoothstep to zero at it.
+__device__ __forceinline__ double heat_shape(double xi)
+{
+    if (xi <= 0.5) return 1.0;
+    if (xi >= 1.0) return 0.0;
+    double t = 2.0 * xi - 1.0;
+    return 1.0 - t * t * (3.0 - 2.0 * t);
+}
+
+__device__ __forceinline__ double heating(const Geom &g, double x, double y, double z)
+{
+    if (g.heat_kind == 1) return g.heat[0] * heat_shape((z - g.heat[2]) / g.heat[1]);
+    if (g.heat_kind == 2) return g.heat[0] * heat_shape(sqrt(r2_exact(x, y, z)) / g.heat[1]);
+    return 0.0;
+}
+
+// ---------------------------------------------------------------------
+// PPM reconstruction (Sec. 1)
+// ---------------------------------------------------------------------
+
+// Interface value one order higher than the parabola: the 4th-order value
+// from the four cell averages around the face (CW84 eq. 1.6, uniform grid).
+template <typename T>
+__device__ __forceinline__ T face4(T am, T a, T b, T bp)
+{
+    return (T(7) * (a + b) - (am + bp)) * T(1.0 / 12.0);
+}
+
+// 5-cell smoothness judgment (Sec. 1), graded: weight 1 (no constraints)
+// when the three second differences in the window are all zero, or share
+// one strict sign with max <= 2 min in magnitude; weight 0 when their signs
+// differ or max >= 3 min; linear in between, so that the reconstruction
+// depends continuously on the data.  Returns the weight of the
+// unconstrained parabola.
+template <typename T>
+__device__ __forceinline__ T smooth_weight(T q0, T q1, T q2, T q3, T q4)
+{
+    T d0 = (q0 + q2) - T(2) * q1;
+    T d1 = (q1 + q3) - T(2) * q2;
+    T d2 = (q2 + q4) - T(2) * q3;
+    if (d0 == T(0) && d1 == T(0) && d2 == T(0)) return T(1);
+    bool same = (d0 > T(0) && d1 > T(0) && d2 > T(0)) || (d0 < T(0) && d1 < T(0) && d2 < T(0));
+    if (!same) return T(0);
+    T a0 = tabs(d0), a1 = tabs(d1), a2 = tabs(d2);
+    T mx = tmax(a0, tmax(a1, a2)), mn = tmin(a0, tmin(a1, a2));
+    if (mx <= T(2) * mn) return T(1);
+    if (mx >= T(3) * mn) return T(0);
+    return (T(3) * mn - mx) / mn;
+}
+
+// van Leer limited slope (CW84 eq. 1.8).
+template <typename T>
+__device__ __forceinline__ T limited_slope(T qm, T q, T qp)
+{
+    T dl = q - qm, dr = qp - q;
+    T dc = T(0.5) * (qp - qm);
+    T m = tmin(tabs(dc), tmin(T(2) * tabs(dl), T(2) * tabs(dr)));
+    m = dc > T(0) ? m : -m;
+    return (dl * dr > T(0)) ? m : T(0);
+}
+
+// Face value from limited slopes, symmetric in the two cells at the face.
+template <typename T>
+__device__ __forceinline__ T face_limited(T qa, T qb, T sa, T sb)
+{
+    return T(0.5) * (qa + qb) - (sb - sa) * T(1.0 / 6.0);
+}
+
+// CW84 eq. 1.10: extremum and overshoot constraints on the edge values.
+template <typename T>
+__device__ __forceinline__ void constrain(T q, T &qL, T &qR)
+{
+    if ((qR - q) * (q - qL) <= T(0)) { qL = q; qR = q; return; }
+    T dq = qR - qL;
+    T q6 = T(6) * (q - T(0.5) * (qL + qR));
+    if (dq * q6 > dq * dq) qL = T(3) * q - T(2) * qR;
+    else if (dq * q6 < -(dq * dq)) qR = T(3) * q - T(2) * qL;
+}
+
+// Averages of the parabola over the last / first fraction y of the cell.
+template <typename T>
+__device__ __forceinline__ T avg_right(T qR, T dq, T q6, T y)
+{
+    return qR - (T(0.5) * y) * (dq - (T(1) - T(2.0 / 3.0) * y) * q6);
+}
+template <typename T>
+__device__ __forceinline__ T avg_left(T qL, T dq, T q6, T y)
+{
+    return qL + (T(0.5) * y) * (dq + (T(1) - T(2.0 / 3.0) * y) * q6);
+}
+
+// ---------------------------------------------------------------------
+// Riemann solver on the pressure perturbation (CW84 Sec. 2)
+// ---------------------------------------------------------------------
+
+// State at a face: rho', u, v, w, p'.
+template <typename T> struct St { T r, u, v, w, p; };
+
+// Newton iterations of the two-shock approximation.  p0f cancels from every
+// pressure difference; the full pressures only set the wave impedances.
+// Stops once the pre-update velocity residual |u*_R - u*_L| is at most
+// tol (cL + cR); returns whether that happened within `maxit` iterations.
+template <typename T>
+__device__ __forceinline__ bool two_shock(const St<T> &L, const St<T> &R, T rL, T rR, T pL, T pR,
+                                          T p0f, T CL, T CR, T gamma, int maxit, T tol,
+                                          T &ps, T &us, T &WL, T &WR)
+{
+    const T A = (gamma + T(1)) / (T(2) * gamma);
+    T cs = CL / rL + CR / rR;
+    T pfl = T(1e-10) * tmin(pL, pR) - p0f;
+    ps = (CR * L.p + CL * R.p + CL * CR * (L.u - R.u)) / (CL + CR);
+    if (ps < pfl) ps = pfl;
+    for (int it = 0; it < maxit; ++it) {
+        WL = CL * sqrt(T(1) + A * (ps - L.p) / pL);
+        WR = CR * sqrt(T(1) + A * (ps - R.p) / pR);
+        T uLs = L.u - (ps - L.p) / WL;
+        T uRs = R.u + (ps - R.p) / WR;
+        T ZL = T(2) * WL * WL * WL / (WL * WL + CL * CL);
+        T ZR = T(2) * WR * WR * WR / (WR * WR + CR * CR);
+        T du = uRs - uLs;
+        us = (ZL * uLs + ZR * uRs) / (ZL + ZR);
+        ps = ps - ZL * ZR * du / (ZL + ZR);
+        if (ps < pfl) ps = pfl;
+        if (tabs(du) <= tol * cs) return true;
+    }
+    return false;
+}
+
+// Sample the face state by the sign of u* and the speed of the wave on
+// that side (CW84 Sec. 2).
+template <typename T>
+__device__ __forceinline__ St<T> sample(const St<T> &L, const St<T> &R, T rL, T rR, T ps, T us,
+                                        T WL, T WR)
+{
+    St<T> f;
+    if (us >= T(0)) {
+        if (L.u - WL / rL >= T(0)) return L;
+        T X = rL * (ps - L.p) / (WL * WL);
+        f.r = L.r + rL * X / (T(1) - X);
+        f.u = us; f.v = L.v; f.w = L.w; f.p = ps;
+    } else {
+        if (R.u + WR / rR <= T(0)) return R;
+        T X = rR * (ps - R.p) / (WR * WR);
+        f.r = R.r + rR * X / (T(1) - X);
+        f.u = us; f.v = R.v; f.w = R.w; f.p = ps;
+    }
+    return f;
+}
+
+// Full solve.  FP64: Newton to a velocity residual of 1e-13 (cL + cR), at
+// most 20 iterations.  FP32: two iterations, then, if the residual is still
+// above 1e-5, the FP64 solve from the same states (counted in `refined`).
+__device__ __forceinline__ St<double> riemann64(const St<double> &L, const St<double> &R,
+                                                double r0f, double p0f, double gamma, bool &bad)
+{
+    double rL = r0f + L.r, rR = r0f + R.r, pL = p0f + L.p, pR = p0f + R.p;
+    double CL = sqrt(gamma * pL * rL), CR = sqrt(gamma * pR * rR);
+    double ps, us, WL = CL, WR = CR;
+    bad = !two_shock<double>(L, R, rL, rR, pL, pR, p0f, CL, CR, gamma, 20, 1e-13, ps, us, WL, WR);
+    return sample<double>(L, R, rL, rR, ps, us, WL, WR);
+}
+
+template <typename T> struct Solver;
+
+template <> struct Solver<double> {
+    __device__ static St<double> solve(const St<double> &L, const St<double> &R, double r0f,
+                                       double p0f, double gamma, bool &counted)
+    {
+        return riemann64(L, R, r0f, p0f, gamma, counted);
+    }
+};
+
+template <> struct Solver<float> {
+    __device__ static St<float> solve(const St<float> &L, const St<float> &R, float r0f,
+                                      float p0f, float gamma, bool &counted)
+    {
+        float rL = r0f + L.r, rR = r0f + R.r, pL = p0f + L.p, pR = p0f + R.p;
+        float CL = sqrtf(gamma * pL * rL), CR = sqrtf(gamma * pR * rR);
+        float ps, us, WL = CL, WR = CR;
+        bool ok = two_shock<float>(L, R, rL, rR, pL, pR, p0f, CL, CR, gamma, 2, 1e-5f, ps, us, WL, WR);
+        counted = false;
+        if (!ok) {
+            counted = true;
+            St<double> Ld{L.r, L.u, L.v, L.w, L.p}, Rd{R.r, R.u, R.v, R.w, R.p};
+            bool bad;
+            St<double> f = riemann64(Ld, Rd, (double)r0f, (double)p0f, (double)gamma, bad);
+            return St<float>{(float)f.r, (float)f.u, (float)f.v, (float)f.w, (float)f.p};
+        }
+        return sample<float>(L, R, rL, rR, ps, us, WL, WR);
+    }
+};
+
+// ---------------------------------------------------------------------
+// PPB (Sec. 1, Sec. 4): Lagrange-remap transport of fv and its moments
+// ---------------------------------------------------------------------
+
+// Constraint applied almost never (Sec. 1): scale the slope and curvature
+// along the pass so that a0 + a1 s + a2 (s^2 - 1/12) stays in [0, 1] on the
+// cell.  Returns true when the profile changed by more than round-off.
+template <typename T>
+__device__ __forceinline__ bool fv_limit(T a0, T &a1, T &a2)
+{
+    T gm = a0 - T(0.5) * a1 + a2 * T(1.0 / 6.0);
+    T gp = a0 + T(0.5) * a1 + a2 * T(1.0 / 6.0);
+    T lo = tmin(gm, gp), hi = tmax(gm, gp);
+    if (a2 != T(0)) {
+        T sv = -a1 / (T(2) * a2);
+        if (sv > T(-0.5) && sv < T(0.5)) {
+            T gv = a0 + a1 * sv + a2 * (sv * sv - T(1.0 / 12.0));
+            lo = tmin(lo, gv);
+            hi = tmax(hi, gv);
+        }
+    }
+    T th = T(1);
+    if (hi > T(1)) th = tmin(th, (T(1) - a0) / (hi - a0));
+    if (lo < T(0)) th = tmin(th, a0 / (a0 - lo));
+    if (!(th < T(1))) return false;
+    if (th < T(0)) th = T(0);
+    T s1 = tabs(a1) + tabs(a2);
+    a1 *= th;
+    a2 *= th;
+    return (T(1) - th) * s1 > T(1e-9);
+}
+
+// Pass-local fv coefficients: q[0..2] quadratic along the pass, q[3..4] and
+// q[5..6] transverse slopes varying linearly along it, q[7..9] constants.
+struct PPBIdx { int f[10]; };
+
+// Moments about the face of the donor slab crossing it.  sig = u* dt/dx at
+// the face; the donor has Lagrangian length L and coefficients q (odd-in-s
+// entries flipped by the caller for a donor on the right).  Slab integrals
+// over s = 1/2 - t + t u, u in [0, 1], t = |sig| / L.
+template <typename T>
+__device__ __forceinline__ void slab(const T *q, T sig, T L, T *G)
+{
+    T t = tabs(sig) / L;
+    T h = T(0.5) - t;
+    T al0 = q[0] + q[1] * h + q[2] * (h * h - T(1.0 / 12.0));
+    T al1 = t * (q[1] + T(2) * q[2] * h);
+    T al2 = q[2] * (t * t);
+    T I0 = al0 + al1 * T(0.5) + al2 * T(1.0 / 3.0);
+    T I1 = al0 * T(0.5) + al1 * T(1.0 / 3.0) + al2 * T(0.25);
+    T I2 = al0 * T(1.0 / 3.0) + al1 * T(0.25) + al2 * T(0.2);
+    T s2 = sig * sig, s3 = s2 * sig;
+    G[0] = sig * I0;
+    G[1] = s2 * I1;
+    G[2] = s3 * I2;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        T b0 = q[3 + 2 * p], b1 = q[4 + 2 * p];
+        T be0 = b0 + b1 * h;
+        T be1 = b1 * t;
+        G[3 + 2 * p] = sig * (be0 + be1 * T(0.5));
+        G[4 + 2 * p] = s2 * (be0 * T(0.5) + be1 * T(1.0 / 3.0));
+    }
+    G[7] = sig * q[7];
+    G[8] = sig * q[8];
+    G[9] = sig * q[9];
+}
+
+// New coefficients of a cell: its Lagrangian content about the cell centre
+// (length L, centre offset dl, stretch ds = L - 1) minus the slab leaving
+// through the right face (GR) plus the one entering through the left (GL),
+// both shifted from the face to the centre.
+template <typename T>
+__device__ __forceinline__ void ppb_update(const T *q, T ds, T dl, const T *GL, const T *GR, T *o)
+{
+    T L = T(1) + ds;
+    T a0 = q[0], a1 = q[1], a2 = q[2];
+    T M0 = L * a0;
+    T M1 = L * (dl * a0 + L * a1 * T(1.0 / 12.0));
+    T M2 = L * (dl * dl * a0 + dl * L * a1 * T(1.0 / 6.0) + L * L * a2 * T(1.0 / 180.0)
+                + a0 * ds * (T(2) + ds) * T(1.0 / 12.0));
+    o[0] = M0 - (GR[0] - GL[0]);
+    o[1] = T(12) * (M1 - (GR[1] - GL[1]) - T(0.5) * (GR[0] + GL[0]));
+    o[2] = T(180) * (M2 - (GR[2] - GL[2]) - (GR[1] + GL[1]) - (GR[0] - GL[0]) * T(1.0 / 6.0));
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        int b = 3 + 2 * p;
+        T b0 = q[b], b1 = q[b + 1];
+        T N0 = L * b0;
+        T N1 = L * (dl * b0 + L * b1 * T(1.0 / 12.0));
+        o[b] = N0 - (GR[b] - GL[b]);
+        o[b + 1] = T(12) * (N1 - (GR[b + 1] - GL[b + 1]) - T(0.5) * (GR[b] + GL[b]));
+    }
+#pragma unroll
+    for (int c = 7; c < 10; ++c) o[c] = L * q[c] - (GR[c] - GL[c]);
+}
+
+}  // namespace ppmb

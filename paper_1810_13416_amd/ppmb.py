@@ -1,0 +1,258 @@
+"""Python binding of libppmb (ctypes): argument marshalling only.
+
+Every step of the PPM + PPB pass, the base-state integration, the CFL and
+total reductions and the state conversions run in the HIP library; PyTorch
+only provides device memory and the stream.  There is no CPU fallback: if
+the library or a GPU is missing, constructing a `Sim` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libppmb.so")
+
+FP64, FP32 = 0, 1
+NFIELDS = 15
+
+# every entry point declared in include/ppmb.h
+EXPORTS = ("ppmb_create", "ppmb_destroy", "ppmb_state_bytes", "ppmb_bind_state",
+           "ppmb_current_state", "ppmb_set_base_state", "ppmb_get_base", "ppmb_set_state",
+           "ppmb_set_state_device", "ppmb_get_state", "ppmb_get_conserved",
+           "ppmb_set_conserved", "ppmb_compute_dt", "ppmb_step", "ppmb_step_auto",
+           "ppmb_last_dt", "ppmb_pass", "ppmb_get_nstep", "ppmb_set_nstep",
+           "ppmb_reduce_totals", "ppmb_counters", "ppmb_synchronize", "ppmb_status_string",
+           "ppmb_last_error")
+
+
+class PPMBError(RuntimeError):
+    pass
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("dx", ctypes.c_double), ("origin", ctypes.c_double * 3),
+                ("bc", ctypes.c_int * 3), ("gamma", ctypes.c_double), ("sphere", ctypes.c_int),
+                ("sphere_r", ctypes.c_double), ("grav_kind", ctypes.c_int),
+                ("grav", ctypes.c_double * 4), ("heat_kind", ctypes.c_int),
+                ("heat", ctypes.c_double * 3), ("smooth_detect", ctypes.c_int)]
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_DD = ctypes.POINTER(_D)
+_V = ctypes.c_void_p
+_lib = None
+
+
+def load():
+    """Load libppmb.so (built by paper_1810_13416_amd.build); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise PPMBError(f"{LIB_PATH} is not built; run `python -m paper_1810_13416_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    i, d, p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+    sig = {
+        "ppmb_create": [ctypes.POINTER(Grid), i, p, ctypes.POINTER(p)],
+        "ppmb_destroy": [p],
+        "ppmb_state_bytes": [p, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
+        "ppmb_bind_state": [p, p, p],
+        "ppmb_current_state": [p, ctypes.POINTER(p)],
+        "ppmb_set_base_state": [p, i, _D],
+        "ppmb_get_base": [p, _D, _D],
+        "ppmb_set_state": [p, _DD],
+        "ppmb_set_state_device": [p, _DD],
+        "ppmb_get_state": [p, _DD],
+        "ppmb_get_conserved": [p, _DD],
+        "ppmb_set_conserved": [p, _DD],
+        "ppmb_compute_dt": [p, d, _D],
+        "ppmb_step": [p, d],
+        "ppmb_step_auto": [p, d, i],
+        "ppmb_last_dt": [p, _D],
+        "ppmb_pass": [p, i, d, i],
+        "ppmb_get_nstep": [p, ctypes.POINTER(ctypes.c_long)],
+        "ppmb_set_nstep": [p, ctypes.c_long],
+        "ppmb_reduce_totals": [p, _D],
+        "ppmb_counters": [p, ctypes.POINTER(ctypes.c_ulonglong)],
+        "ppmb_synchronize": [p],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.ppmb_status_string.argtypes = [i]
+    L.ppmb_status_string.restype = ctypes.c_char_p
+    L.ppmb_last_error.argtypes = [p]
+    L.ppmb_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def grid_of(params) -> Grid:
+    g = Grid()
+    g.n[:] = [int(v) for v in params.n]
+    g.dx = float(params.dx)
+    g.origin[:] = [float(v) for v in params.origin]
+    g.bc[:] = [int(v) for v in params.bc]
+    g.gamma = float(params.gamma)
+    g.sphere = int(params.sphere)
+    g.sphere_r = float(params.sphere_r)
+    g.grav_kind = int(params.grav_kind)
+    g.grav[:] = [float(v) for v in params.grav]
+    g.heat_kind = int(params.heat_kind)
+    g.heat[:] = [float(v) for v in params.heat]
+    g.smooth_detect = int(params.smooth_detect)
+    return g
+
+
+def _ptrs(arrs):
+    return (_D * len(arrs))(*[a.ctypes.data_as(_D) for a in arrs])
+
+
+class Sim:
+    """One grid on one GPU stream.
+
+    params: a GridParams-like object (n, dx, origin, bc, gamma, sphere,
+    sphere_r, grav_kind, grav, heat_kind, heat, smooth_detect, base_kind,
+    base).  precision: FP64 or FP32.  The two state buffers are torch
+    tensors on `device`; the library ping-pongs between them."""
+
+    def __init__(self, params, precision=FP64, device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise PPMBError("no GPU: the PPM+PPB path runs only in the HIP library")
+        self.torch = torch
+        self.L = load()
+        self.params = params
+        self.precision = precision
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._grid = grid_of(params)
+        h = ctypes.c_void_p()
+        self._check(self.L.ppmb_create(ctypes.byref(self._grid), precision,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                    None)
+        self.h = h
+        nbytes = ctypes.c_size_t()
+        esz = ctypes.c_size_t()
+        self._check(self.L.ppmb_state_bytes(self.h, ctypes.byref(nbytes), ctypes.byref(esz)))
+        dtype = torch.float64 if precision == FP64 else torch.float32
+        count = nbytes.value // esz.value
+        self.buffers = [torch.empty(count, dtype=dtype, device=self.device) for _ in range(2)]
+        self._check(self.L.ppmb_bind_state(self.h, ctypes.c_void_p(self.buffers[0].data_ptr()),
+                                           ctypes.c_void_p(self.buffers[1].data_ptr())))
+        self.set_base_state(int(getattr(params, "base_kind", 0)), getattr(params, "base", (0.0,) * 6))
+
+    # -- plumbing --------------------------------------------------------
+    def _check(self, status, h="self"):
+        if status != 0:
+            hh = self.h if h == "self" else None
+            msg = self.L.ppmb_status_string(status).decode()
+            if hh:
+                msg += ": " + self.L.ppmb_last_error(hh).decode()
+            raise PPMBError(f"ppmb error {status}: {msg}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ppmb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.params.n[2], self.params.n[1], self.params.n[0])
+
+    # -- API -------------------------------------------------------------
+    def set_base_state(self, kind, params6):
+        arr = np.ascontiguousarray(params6, dtype=np.float64)
+        self._check(self.L.ppmb_set_base_state(self.h, int(kind), arr.ctypes.data_as(_D)))
+
+    def base(self):
+        r = np.empty(self.shape)
+        p = np.empty(self.shape)
+        self._check(self.L.ppmb_get_base(self.h, r.ctypes.data_as(_D), p.ctypes.data_as(_D)))
+        return r, p
+
+    def set_state(self, state):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in state]
+        self._check(self.L.ppmb_set_state(self.h, _ptrs(arrs)))
+
+    def set_state_device(self, tensors):
+        ptrs = (_D * NFIELDS)(*[ctypes.cast(t.data_ptr(), _D) for t in tensors])
+        self._check(self.L.ppmb_set_state_device(self.h, ptrs))
+
+    def get_state(self):
+        out = [np.empty(self.shape) for _ in range(NFIELDS)]
+        self._check(self.L.ppmb_get_state(self.h, _ptrs(out)))
+        return out
+
+    def get_conserved(self):
+        out = [np.empty(self.shape) for _ in range(NFIELDS)]
+        self._check(self.L.ppmb_get_conserved(self.h, _ptrs(out)))
+        return out
+
+    def set_conserved(self, cons):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in cons]
+        self._check(self.L.ppmb_set_conserved(self.h, _ptrs(arrs)))
+
+    def dt(self, cfl):
+        v = ctypes.c_double()
+        self._check(self.L.ppmb_compute_dt(self.h, float(cfl), ctypes.byref(v)))
+        return v.value
+
+    def step(self, dt):
+        self._check(self.L.ppmb_step(self.h, float(dt)))
+
+    def step_auto(self, cfl, nsteps):
+        self._check(self.L.ppmb_step_auto(self.h, float(cfl), int(nsteps)))
+
+    def last_dt(self):
+        v = ctypes.c_double()
+        self._check(self.L.ppmb_last_dt(self.h, ctypes.byref(v)))
+        return v.value
+
+    def run(self, nsteps, cfl):
+        for _ in range(nsteps):
+            self.step(self.dt(cfl))
+
+    def pass_(self, axis, dt, heat=0):
+        self._check(self.L.ppmb_pass(self.h, int(axis), float(dt), int(heat)))
+
+    @property
+    def nstep(self):
+        v = ctypes.c_long()
+        self._check(self.L.ppmb_get_nstep(self.h, ctypes.byref(v)))
+        return v.value
+
+    @nstep.setter
+    def nstep(self, v):
+        self._check(self.L.ppmb_set_nstep(self.h, int(v)))
+
+    def totals(self):
+        out = np.zeros(8)
+        self._check(self.L.ppmb_reduce_totals(self.h, out.ctypes.data_as(_D)))
+        return out
+
+    def counters(self):
+        out = (ctypes.c_ulonglong * 4)()
+        self._check(self.L.ppmb_counters(self.h, out))
+        return [int(v) for v in out]
+
+    def synchronize(self):
+        self._check(self.L.ppmb_synchronize(self.h))
+
+    def current_state_tensor(self):
+        p = ctypes.c_void_p()
+        self._check(self.L.ppmb_current_state(self.h, ctypes.byref(p)))
+        for b in self.buffers:
+            if b.data_ptr() == p.value:
+                return b
+        raise PPMBError("current state is not one of the bound buffers")

@@ -1,0 +1,94 @@
+"""Host-only checks of the C ABI: the library builds, loads and exports every
+entry point the header declares, and the binding's grid struct matches the
+header's layout.  No GPU call is made."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ppmb.h")
+
+
+def _lib_path():
+    from paper_1810_13416_amd import ppmb
+    if not os.path.exists(ppmb.LIB_PATH):
+        from paper_1810_13416_amd import build
+        build.build()
+    return ppmb.LIB_PATH
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ppmb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    from paper_1810_13416_amd import ppmb
+    assert set(declared_functions()) == set(ppmb.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(_lib_path())
+    missing = [f for f in declared_functions() if not hasattr(L, f)]
+    assert not missing, missing
+
+
+def test_library_has_no_torch_dependency():
+    out = subprocess.run(["ldd", _lib_path()], capture_output=True, text=True).stdout
+    assert "torch" not in out and "c10" not in out
+
+
+def test_status_strings_without_gpu():
+    L = ctypes.CDLL(_lib_path())
+    L.ppmb_status_string.restype = ctypes.c_char_p
+    L.ppmb_status_string.argtypes = [ctypes.c_int]
+    assert L.ppmb_status_string(0) == b"ok"
+    assert L.ppmb_status_string(-4) == b"non-physical state"
+
+
+def test_grid_struct_layout_matches_header():
+    from paper_1810_13416_amd.ppmb import Grid
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "ppmb.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(ppmb_grid), offsetof(ppmb_grid, dx),
+         offsetof(ppmb_grid, gamma), offsetof(ppmb_grid, sphere_r), offsetof(ppmb_grid, grav),
+         offsetof(ppmb_grid, heat), offsetof(ppmb_grid, smooth_detect));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        vals = [int(v) for v in subprocess.check_output([exe]).split()]
+    got = [ctypes.sizeof(Grid), Grid.dx.offset, Grid.gamma.offset, Grid.sphere_r.offset,
+           Grid.grav.offset, Grid.heat.offset, Grid.smooth_detect.offset]
+    assert vals == got
+
+
+def test_binding_refuses_to_run_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    from paper_1810_13416_amd import ppmb, problems
+    with pytest.raises(ppmb.PPMBError):
+        ppmb.Sim(problems.uniform().params)
+
+
+def test_product_path_does_not_import_oracle():
+    pkg = os.path.join(ROOT, "paper_1810_13416_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "ppmb_oracle" not in text, f
