@@ -196,6 +196,64 @@ ppmb_status ppmb_reduce_totals(ppmb_ctx *ctx, double out[8]);
  * (FP64), steps }.  Synchronising. */
 ppmb_status ppmb_counters(ppmb_ctx *ctx, unsigned long long out[4]);
 
+/* ---- Batched bricks ------------------------------------------------------
+ * A batch advances many independent bricks of different sizes together
+ * (each with its own grid, boundaries, base state and CFL time step): every
+ * stage of a step is ONE kernel launch covering all bricks, through a table
+ * mapping each block to its brick.  The single-grid calls above act on
+ * brick 0 of a context; ppmb_create makes a batch of one.
+ *
+ * ppmb_batch_create: nbricks grids (ppmb_grid each); the library allocates
+ * both state arenas (15 * sum of cells * elem_size bytes each).  Errors as
+ * ppmb_create; INVALID for nbricks < 1. */
+ppmb_status ppmb_batch_create(int nbricks, const ppmb_grid *grids, ppmb_precision prec,
+                              void *hip_stream, ppmb_ctx **out);
+ppmb_status ppmb_brick_count(const ppmb_ctx *ctx, int *nbricks);
+
+/* Per-brick versions of set_base_state, get_base, set_state, get_state,
+ * get_conserved, reduce_totals and last_dt; `brick` in [0, nbricks), else
+ * INVALID.  Same semantics and synchronisation as the single-grid calls. */
+ppmb_status ppmb_brick_set_base_state(ppmb_ctx *ctx, int brick, int kind, const double params[6]);
+ppmb_status ppmb_brick_get_base(ppmb_ctx *ctx, int brick, double *host_rho0, double *host_p0);
+ppmb_status ppmb_brick_set_state(ppmb_ctx *ctx, int brick, const double *const host_prim[15]);
+ppmb_status ppmb_brick_get_state(ppmb_ctx *ctx, int brick, double *const host_prim[15]);
+ppmb_status ppmb_brick_get_conserved(ppmb_ctx *ctx, int brick, double *const host_cons[15]);
+ppmb_status ppmb_brick_totals(ppmb_ctx *ctx, int brick, double out[8]);
+ppmb_status ppmb_brick_last_dt(ppmb_ctx *ctx, int brick, double *dt_out);
+
+/* `nsteps` steps of every brick, each brick's dt from its own CFL condition
+ * computed on the device.  mode 0: one launch per stage for all bricks;
+ * 1: the same launches captured once (two steps: both pass orders) into a
+ * HIP graph and replayed (recaptured if the arena, step parity or cfl
+ * changed); 2: one launch per stage and brick (for comparison).  All three
+ * give bitwise identical states.  Asynchronous.  Mode 1 needs a stream other
+ * than the null stream (graph capture). */
+ppmb_status ppmb_batch_step(ppmb_ctx *ctx, double cfl, int nsteps, int mode);
+
+/* Launch shape of the pass kernels: waves per block of the marching kernel
+ * (y and z passes) and of the lanes-along-x kernel (x pass), each 1, 2 or 4.
+ * Changes no result bit.  Synchronising. */
+ppmb_status ppmb_set_pass_shape(ppmb_ctx *ctx, int march_waves, int x_waves);
+ppmb_status ppmb_get_pass_shape(const ppmb_ctx *ctx, int *march_waves, int *x_waves);
+
+/* Autotuner: times every launch shape (waves per block 1, 2, 4 for each of
+ * the two pass kernels) on this context's bricks, `reps` passes per axis
+ * and shape, with the current dt, reading the current state and writing the
+ * spare arena (the state, step count and counters are left as they were),
+ * and selects the fastest.  If cache_path is not NULL, a line keyed by
+ * precision, brick count and total cells is read from it (no timing when
+ * present) or appended to it.  out_shape receives {march_waves, x_waves}.
+ * Synchronising. */
+ppmb_status ppmb_autotune(ppmb_ctx *ctx, double cfl, int reps, const char *cache_path, int out_shape[2]);
+
+/* Per-pass timing.  While enabled, every pass kernel is bracketed by HIP
+ * events recorded on the context's stream (the kernel's own stream).
+ * ppmb_profile_read() synchronises, returns per axis the number of timed
+ * pass kernels and their summed duration in milliseconds, and clears the
+ * record.  Errors: INVALID for NULL arguments; HIP. */
+ppmb_status ppmb_profile_enable(ppmb_ctx *ctx, int enable);
+ppmb_status ppmb_profile_read(ppmb_ctx *ctx, double ms[3], long count[3]);
+
 ppmb_status ppmb_synchronize(ppmb_ctx *ctx);
 const char *ppmb_status_string(ppmb_status s);
 const char *ppmb_last_error(const ppmb_ctx *ctx);

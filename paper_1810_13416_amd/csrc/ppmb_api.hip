@@ -1,8 +1,10 @@
 // ppmb_api.hip -- host runtime behind the C ABI declared in include/ppmb.h.
 //
-// A context owns the FP64 base state, its working-precision copy, the
-// reduction buffers and the event counters; the two state buffers are the
-// caller's.  Every call enqueues on the context's stream.
+// A context holds a batch of bricks (a single grid is a batch of one): the
+// brick table, the FP64 base state and its working-precision copy, the
+// per-brick time steps, reduction buffers, event counters and the block maps
+// that let one kernel launch cover every brick of a pass.  The two state
+// arenas are the caller's for a single grid and the library's for a batch.
 #include "../../include/ppmb.h"
 #include "ppmb_internal.h"
 
@@ -15,25 +17,40 @@
 using namespace ppmb;
 
 struct ppmb_ctx {
-    Geom g{};
     ppmb_precision prec = PPMB_FP64;
     hipStream_t stream = nullptr;
-    long ncell = 0;
     size_t esz = 8;
+    int nb = 0;                         // bricks
+    std::vector<Brick> hb;              // brick table (host copy)
+    Brick *db = nullptr;                // brick table (device)
+    long total_state = 0;               // elements per state arena (15 * sum ncell)
+    long total_base = 0;                // elements per base arena (2 * sum ncell)
     void *buf[2] = { nullptr, nullptr };
+    bool owns_state = false;
     int cur = 0;
-    double *base64 = nullptr;       // rho0, p0 (FP64)
-    void *baseT = nullptr;          // rho0, p0 in the working precision (FP32 only)
-    double *table = nullptr;        // base-state RK4 nodes
+    double *base64 = nullptr;           // rho0, p0 per brick (FP64)
+    void *baseT = nullptr;              // the same in FP32 (FP32 contexts only)
+    double *table = nullptr;            // base-state RK4 nodes (reused brick by brick)
     long table_len = 0;
-    double *dt_dev = nullptr;       // [0] current dt
-    unsigned long long *cnt = nullptr;    // [0..2] event counters, [3] unused
-    unsigned long long *work = nullptr;   // [0] smax bits, [1] non-physical flag
-    double *partials = nullptr;     // totals block partials
-    double *out8 = nullptr;         // totals result
+    double *dt = nullptr;               // per-brick dt
+    unsigned long long *cnt = nullptr;  // [0..2] event counters
+    unsigned long long *work = nullptr; // per brick: smax bits, non-physical flag
+    double *partials = nullptr;         // totals block partials
+    double *out8 = nullptr;             // totals result
+    PassShape shape{ 1, 4 };
+    BlockMap *pmap[3] = { nullptr, nullptr, nullptr };   // per pass axis
+    std::vector<int> pfirst[3];         // first block of each brick (+ total at the end)
+    BlockMap *cmap = nullptr;           // CFL reduction
+    std::vector<int> cfirst;
     long nstep = 0;
     unsigned long long steps = 0;
-    bool base_set = false;
+    bool profiling = false;
+    struct Timed { hipEvent_t a, b; int axis; };
+    std::vector<Timed> timed;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int gkey_cur = -1, gkey_par = -1;
+    double gkey_cfl = 0.0;
     std::string err;
 };
 
@@ -55,17 +72,277 @@ static ppmb_status hipfail(ppmb_ctx *c, hipError_t e, const char *where)
         if (e_ != hipSuccess) return hipfail((ctx), e_, #expr);      \
     } while (0)
 
-template <typename T>
-static T *cur_state(ppmb_ctx *c) { return static_cast<T *>(c->buf[c->cur]); }
+#define TRY(expr)                                                    \
+    do {                                                             \
+        ppmb_status s_ = (expr);                                     \
+        if (s_ != PPMB_OK) return s_;                                \
+    } while (0)
 
-static const void *base_rho(ppmb_ctx *c)
+template <typename T>
+static T *arena(ppmb_ctx *c, int which) { return static_cast<T *>(c->buf[which]); }
+
+static void free_graph(ppmb_ctx *c)
 {
-    return c->prec == PPMB_FP64 ? (const void *)c->base64 : c->baseT;
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->gkey_cur = c->gkey_par = -1;
 }
-static const void *base_p(ppmb_ctx *c)
+
+static void free_maps(ppmb_ctx *c)
 {
-    return c->prec == PPMB_FP64 ? (const void *)(c->base64 + c->ncell)
-                                : (const void *)((const float *)c->baseT + c->ncell);
+    for (int d = 0; d < 3; ++d) { hipFree(c->pmap[d]); c->pmap[d] = nullptr; }
+    hipFree(c->cmap);
+    c->cmap = nullptr;
+}
+
+static ppmb_status upload_map(ppmb_ctx *c, const std::vector<BlockMap> &m, BlockMap **dst)
+{
+    if (hipMalloc(dst, sizeof(BlockMap) * (m.empty() ? 1 : m.size())) != hipSuccess)
+        return fail(c, PPMB_ERR_NOMEM, "block map allocation");
+    HIPCHK(c, hipMemcpy(*dst, m.data(), sizeof(BlockMap) * m.size(), hipMemcpyHostToDevice));
+    return PPMB_OK;
+}
+
+// Block maps: every pass launch and the CFL launch cover all bricks; a
+// per-brick launch covers the slice [first[b], first[b + 1]).
+static ppmb_status build_maps(ppmb_ctx *c)
+{
+    free_graph(c);
+    free_maps(c);
+    for (int d = 0; d < 3; ++d) {
+        std::vector<BlockMap> m;
+        c->pfirst[d].assign(c->nb + 1, 0);
+        for (int b = 0; b < c->nb; ++b) {
+            c->pfirst[d][b] = (int)m.size();
+            int n = pass_blocks(c->hb[b].g, d, c->shape);
+            for (int l = 0; l < n; ++l) m.push_back(BlockMap{ b, l });
+        }
+        c->pfirst[d][c->nb] = (int)m.size();
+        if (m.size() > 0x7fffffff) return fail(c, PPMB_ERR_INVALID, "too many blocks");
+        TRY(upload_map(c, m, &c->pmap[d]));
+    }
+    std::vector<BlockMap> m;
+    c->cfirst.assign(c->nb + 1, 0);
+    for (int b = 0; b < c->nb; ++b) {
+        c->cfirst[b] = (int)m.size();
+        int n = cfl_blocks(c->hb[b].ncell);
+        for (int l = 0; l < n; ++l) m.push_back(BlockMap{ b, l });
+    }
+    c->cfirst[c->nb] = (int)m.size();
+    return upload_map(c, m, &c->cmap);
+}
+
+static ppmb_status check_grid(const ppmb_grid *grid)
+{
+    if (!grid) return PPMB_ERR_INVALID;
+    for (int d = 0; d < 3; ++d) {
+        if (grid->n[d] < 1) return PPMB_ERR_INVALID;
+        if (grid->bc[d] != PPMB_BC_PERIODIC && grid->bc[d] != PPMB_BC_REFLECT) return PPMB_ERR_INVALID;
+    }
+    if (!(grid->dx > 0.0) || !(grid->gamma > 1.0)) return PPMB_ERR_INVALID;
+    if (grid->grav_kind < 0 || grid->grav_kind > 2 || grid->heat_kind < 0 || grid->heat_kind > 2)
+        return PPMB_ERR_INVALID;
+    if (grid->smooth_detect < 0 || grid->smooth_detect > 2) return PPMB_ERR_INVALID;
+    if ((long)grid->n[0] * grid->n[1] * grid->n[2] > (1L << 34)) return PPMB_ERR_INVALID;
+    return PPMB_OK;
+}
+
+static Geom geom_of(const ppmb_grid *grid)
+{
+    Geom g{};
+    for (int d = 0; d < 3; ++d) { g.n[d] = grid->n[d]; g.origin[d] = grid->origin[d]; g.bc[d] = grid->bc[d]; }
+    g.dx = grid->dx;
+    g.gamma = grid->gamma;
+    g.sphere = grid->sphere;
+    g.sphere_r = grid->sphere_r;
+    g.grav_kind = grid->grav_kind;
+    for (int q = 0; q < 4; ++q) g.grav[q] = grid->grav[q];
+    g.heat_kind = grid->heat_kind;
+    for (int q = 0; q < 3; ++q) g.heat[q] = grid->heat[q];
+    g.smooth_detect = grid->smooth_detect;
+    return g;
+}
+
+static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_precision prec,
+                                 void *hip_stream, bool own_state, ppmb_ctx **out)
+{
+    if (!grids || !out || nbricks < 1) return PPMB_ERR_INVALID;
+    *out = nullptr;
+    if (prec != PPMB_FP64 && prec != PPMB_FP32) return PPMB_ERR_INVALID;
+    for (int b = 0; b < nbricks; ++b) TRY(check_grid(&grids[b]));
+    ppmb_ctx *c = new ppmb_ctx();
+    c->prec = prec;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->esz = prec == PPMB_FP64 ? 8 : 4;
+    c->nb = nbricks;
+    long off = 0, boff = 0, maxspan = 0;
+    for (int b = 0; b < nbricks; ++b) {
+        Brick B{};
+        B.g = geom_of(&grids[b]);
+        B.ncell = (long)B.g.n[0] * B.g.n[1] * B.g.n[2];
+        B.off = off;
+        B.boff = boff;
+        B.dti = b;
+        off += (long)NF * B.ncell;
+        boff += 2 * B.ncell;
+        long span = (long)(4.0 * (B.g.n[0] + B.g.n[1] + B.g.n[2]) * 8.0) + 64;
+        if (span > maxspan) maxspan = span;
+        c->hb.push_back(B);
+    }
+    c->total_state = off;
+    c->total_base = boff;
+    c->table_len = 64 + 2 * maxspan;
+    hipError_t e = hipMalloc(&c->db, sizeof(Brick) * nbricks);
+    if (e == hipSuccess) e = hipMalloc(&c->base64, sizeof(double) * boff);
+    if (e == hipSuccess && prec == PPMB_FP32) e = hipMalloc(&c->baseT, sizeof(float) * boff);
+    if (e == hipSuccess) e = hipMalloc(&c->table, sizeof(double) * c->table_len);
+    if (e == hipSuccess) e = hipMalloc(&c->dt, sizeof(double) * nbricks);
+    if (e == hipSuccess) e = hipMalloc(&c->cnt, sizeof(unsigned long long) * 4);
+    if (e == hipSuccess) e = hipMalloc(&c->work, sizeof(unsigned long long) * 2 * nbricks);
+    if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * 8 * kTotalsBlocks);
+    if (e == hipSuccess) e = hipMalloc(&c->out8, sizeof(double) * 8);
+    if (e == hipSuccess && own_state) {
+        e = hipMalloc(&c->buf[0], c->esz * off);
+        if (e == hipSuccess) e = hipMalloc(&c->buf[1], c->esz * off);
+        c->owns_state = true;
+    }
+    if (e != hipSuccess) {
+        ppmb_destroy(c);
+        return PPMB_ERR_NOMEM;
+    }
+    ppmb_status st = PPMB_OK;
+    if (hipMemcpy(c->db, c->hb.data(), sizeof(Brick) * nbricks, hipMemcpyHostToDevice) != hipSuccess ||
+        launch_zero_u64(c->cnt, 4, c->stream) != hipSuccess ||
+        launch_zero_u64(c->work, 2 * nbricks, c->stream) != hipSuccess)
+        st = PPMB_ERR_HIP;
+    if (st == PPMB_OK) st = build_maps(c);
+    // base state NONE until set
+    double zero[6] = { 0, 0, 0, 0, 0, 0 };
+    for (int b = 0; st == PPMB_OK && b < nbricks; ++b)
+        if (launch_base_state(c->hb[b].g, PPMB_BASE_NONE, zero, c->table, c->table_len,
+                              c->base64 + c->hb[b].boff, c->base64 + c->hb[b].boff + c->hb[b].ncell,
+                              c->stream) != hipSuccess)
+            st = PPMB_ERR_HIP;
+    if (st == PPMB_OK && prec == PPMB_FP32 &&
+        launch_narrow<float>(c->base64, static_cast<float *>(c->baseT), boff, c->stream) != hipSuccess)
+        st = PPMB_ERR_HIP;
+    if (st == PPMB_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = PPMB_ERR_HIP;
+    if (st != PPMB_OK) {
+        ppmb_destroy(c);
+        return st;
+    }
+    *out = c;
+    return PPMB_OK;
+}
+
+static ppmb_status need_state(ppmb_ctx *c)
+{
+    if (!c->buf[0] || !c->buf[1]) return fail(c, PPMB_ERR_INVALID, "state buffers not bound");
+    return PPMB_OK;
+}
+
+static ppmb_status check_brick(ppmb_ctx *c, int b)
+{
+    if (b < 0 || b >= c->nb) return fail(c, PPMB_ERR_INVALID, "brick index out of range");
+    return need_state(c);
+}
+
+// ---------------------------------------------------------------------
+// enqueue helpers
+// ---------------------------------------------------------------------
+
+static ppmb_status enqueue_cfl(ppmb_ctx *c, double cfl, int b0, int b1)
+{
+    const int f0 = c->cfirst[b0], f1 = c->cfirst[b1];
+    if (c->prec == PPMB_FP64)
+        HIPCHK(c, launch_cfl<double>(c->db, b0, b1 - b0, c->cmap + f0, f1 - f0, arena<double>(c, c->cur),
+                                     c->base64, c->work, cfl, c->dt, c->stream));
+    else
+        HIPCHK(c, launch_cfl<float>(c->db, b0, b1 - b0, c->cmap + f0, f1 - f0, arena<float>(c, c->cur),
+                                    c->base64, c->work, cfl, c->dt, c->stream));
+    return PPMB_OK;
+}
+
+// One pass along `axis` for bricks [b0, b1), reading arena `from`.
+static ppmb_status enqueue_pass(ppmb_ctx *c, int axis, int heat, int b0, int b1, int from)
+{
+    const int f0 = c->pfirst[axis][b0], f1 = c->pfirst[axis][b1];
+    ppmb_ctx::Timed tm{ nullptr, nullptr, axis };
+    if (c->profiling) {
+        HIPCHK(c, hipEventCreate(&tm.a));
+        HIPCHK(c, hipEventCreate(&tm.b));
+        HIPCHK(c, hipEventRecord(tm.a, c->stream));
+    }
+    hipError_t e;
+    if (c->prec == PPMB_FP64)
+        e = launch_sweep<double>(axis, c->shape, c->db, c->pmap[axis] + f0, f1 - f0, arena<double>(c, from),
+                                 arena<double>(c, 1 - from), c->base64, c->dt, c->cnt, heat, c->stream);
+    else
+        e = launch_sweep<float>(axis, c->shape, c->db, c->pmap[axis] + f0, f1 - f0, arena<float>(c, from),
+                                arena<float>(c, 1 - from), static_cast<const float *>(c->baseT), c->dt,
+                                c->cnt, heat, c->stream);
+    if (e != hipSuccess) return hipfail(c, e, "sweep launch");
+    if (c->profiling) {
+        HIPCHK(c, hipEventRecord(tm.b, c->stream));
+        c->timed.push_back(tm);
+    }
+    return PPMB_OK;
+}
+
+static bool any_heat(ppmb_ctx *c)
+{
+    for (auto &B : c->hb)
+        if (B.g.heat_kind != PPMB_HEAT_NONE) return true;
+    return false;
+}
+
+// Three passes (x,y,z on even steps, z,y,x on odd) for bricks [b0, b1).
+static ppmb_status enqueue_passes(ppmb_ctx *c, int b0, int b1, int from)
+{
+    const int heat = any_heat(c) ? 1 : 0;
+    const int order[2][3] = { { 0, 1, 2 }, { 2, 1, 0 } };
+    const int *o = order[c->nstep & 1];
+    for (int p = 0; p < 3; ++p) {
+        TRY(enqueue_pass(c, o[p], p == 2 ? heat : 0, b0, b1, from));
+        from = 1 - from;
+    }
+    return PPMB_OK;
+}
+
+// One step of every brick: a launch per stage covering all bricks
+// (batched) or one launch per stage and brick (per_brick).
+static ppmb_status enqueue_step(ppmb_ctx *c, bool with_cfl, double cfl, bool per_brick)
+{
+    if (per_brick) {
+        for (int b = 0; b < c->nb; ++b) {
+            if (with_cfl) TRY(enqueue_cfl(c, cfl, b, b + 1));
+            TRY(enqueue_passes(c, b, b + 1, c->cur));
+        }
+    } else {
+        if (with_cfl) TRY(enqueue_cfl(c, cfl, 0, c->nb));
+        TRY(enqueue_passes(c, 0, c->nb, c->cur));
+    }
+    c->cur = 1 - c->cur;           // three passes: the state ends in the other arena
+    c->nstep++;
+    c->steps++;
+    return PPMB_OK;
+}
+
+static ppmb_status check_flag(ppmb_ctx *c)
+{
+    std::vector<unsigned long long> w(2 * c->nb);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(w.data(), c->work, sizeof(unsigned long long) * w.size(), hipMemcpyDeviceToHost));
+    bool bad = false;
+    for (int b = 0; b < c->nb; ++b) bad = bad || w[2 * b + 1];
+    if (bad) {
+        HIPCHK(c, launch_zero_u64(c->work, 2 * c->nb, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return fail(c, PPMB_ERR_NONPHYSICAL, "non-positive density or pressure, or NaN, in a fluid cell");
+    }
+    return PPMB_OK;
 }
 
 extern "C" {
@@ -87,76 +364,28 @@ const char *ppmb_last_error(const ppmb_ctx *ctx) { return ctx ? ctx->err.c_str()
 
 ppmb_status ppmb_create(const ppmb_grid *grid, ppmb_precision prec, void *hip_stream, ppmb_ctx **out)
 {
-    if (!grid || !out) return PPMB_ERR_INVALID;
-    *out = nullptr;
-    for (int d = 0; d < 3; ++d) {
-        if (grid->n[d] < 1) return PPMB_ERR_INVALID;
-        if (grid->bc[d] != PPMB_BC_PERIODIC && grid->bc[d] != PPMB_BC_REFLECT) return PPMB_ERR_INVALID;
-    }
-    if (!(grid->dx > 0.0) || !(grid->gamma > 1.0)) return PPMB_ERR_INVALID;
-    if (prec != PPMB_FP64 && prec != PPMB_FP32) return PPMB_ERR_INVALID;
-    if (grid->grav_kind < 0 || grid->grav_kind > 2 || grid->heat_kind < 0 || grid->heat_kind > 2)
-        return PPMB_ERR_INVALID;
-    long nc = (long)grid->n[0] * grid->n[1] * grid->n[2];
-    if (nc > (1L << 34)) return PPMB_ERR_INVALID;
-    ppmb_ctx *c = new ppmb_ctx();
-    Geom &g = c->g;
-    for (int d = 0; d < 3; ++d) { g.n[d] = grid->n[d]; g.origin[d] = grid->origin[d]; g.bc[d] = grid->bc[d]; }
-    g.dx = grid->dx;
-    g.gamma = grid->gamma;
-    g.sphere = grid->sphere;
-    g.sphere_r = grid->sphere_r;
-    g.grav_kind = grid->grav_kind;
-    for (int q = 0; q < 4; ++q) g.grav[q] = grid->grav[q];
-    g.heat_kind = grid->heat_kind;
-    for (int q = 0; q < 3; ++q) g.heat[q] = grid->heat[q];
-    g.smooth_detect = grid->smooth_detect;
-    c->prec = prec;
-    c->stream = static_cast<hipStream_t>(hip_stream);
-    c->ncell = nc;
-    c->esz = prec == PPMB_FP64 ? 8 : 4;
-    // base-state table: at most (span / (dx/8)) + 2 nodes per segment
-    double span = 4.0 * (grid->n[0] + grid->n[1] + grid->n[2]) * grid->dx + 16.0;
-    c->table_len = 64 + (long)(span / (grid->dx / 8.0)) * 2 + 64;
-    hipError_t e = hipMalloc(&c->base64, sizeof(double) * 2 * nc);
-    if (e == hipSuccess && prec == PPMB_FP32) e = hipMalloc(&c->baseT, sizeof(float) * 2 * nc);
-    if (e == hipSuccess) e = hipMalloc(&c->table, sizeof(double) * c->table_len);
-    if (e == hipSuccess) e = hipMalloc(&c->dt_dev, sizeof(double) * 2);
-    if (e == hipSuccess) e = hipMalloc(&c->cnt, sizeof(unsigned long long) * 4);
-    if (e == hipSuccess) e = hipMalloc(&c->work, sizeof(unsigned long long) * 2);
-    if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * 8 * kTotalsBlocks);
-    if (e == hipSuccess) e = hipMalloc(&c->out8, sizeof(double) * 8);
-    if (e != hipSuccess) {
-        ppmb_destroy(c);
-        return PPMB_ERR_NOMEM;
-    }
-    if (launch_zero_u64(c->cnt, 4, c->stream) != hipSuccess || launch_zero_u64(c->work, 2, c->stream) != hipSuccess) {
-        ppmb_destroy(c);
-        return PPMB_ERR_HIP;
-    }
-    // base state NONE until set
-    double zero[6] = { 0, 0, 0, 0, 0, 0 };
-    if (launch_base_state(g, PPMB_BASE_NONE, zero, c->table, c->table_len, c->base64, c->base64 + nc, c->stream) != hipSuccess) {
-        ppmb_destroy(c);
-        return PPMB_ERR_HIP;
-    }
-    if (prec == PPMB_FP32 &&
-        launch_narrow<float>(c->base64, static_cast<float *>(c->baseT), 2 * nc, c->stream) != hipSuccess) {
-        ppmb_destroy(c);
-        return PPMB_ERR_HIP;
-    }
-    *out = c;
-    return PPMB_OK;
+    return create_common(1, grid, prec, hip_stream, false, out);
+}
+
+ppmb_status ppmb_batch_create(int nbricks, const ppmb_grid *grids, ppmb_precision prec, void *hip_stream,
+                              ppmb_ctx **out)
+{
+    return create_common(nbricks, grids, prec, hip_stream, true, out);
 }
 
 ppmb_status ppmb_destroy(ppmb_ctx *c)
 {
     if (!c) return PPMB_ERR_INVALID;
     hipStreamSynchronize(c->stream);
+    for (auto &t : c->timed) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
+    free_graph(c);
+    free_maps(c);
+    if (c->owns_state) { hipFree(c->buf[0]); hipFree(c->buf[1]); }
+    hipFree(c->db);
     hipFree(c->base64);
     hipFree(c->baseT);
     hipFree(c->table);
-    hipFree(c->dt_dev);
+    hipFree(c->dt);
     hipFree(c->cnt);
     hipFree(c->work);
     hipFree(c->partials);
@@ -168,7 +397,7 @@ ppmb_status ppmb_destroy(ppmb_ctx *c)
 ppmb_status ppmb_state_bytes(const ppmb_ctx *c, size_t *bytes, size_t *elem_size)
 {
     if (!c || !bytes) return PPMB_ERR_INVALID;
-    *bytes = (size_t)NF * c->ncell * c->esz;
+    *bytes = (size_t)c->total_state * c->esz;
     if (elem_size) *elem_size = c->esz;
     return PPMB_OK;
 }
@@ -176,7 +405,9 @@ ppmb_status ppmb_state_bytes(const ppmb_ctx *c, size_t *bytes, size_t *elem_size
 ppmb_status ppmb_bind_state(ppmb_ctx *c, void *a, void *b)
 {
     if (!c) return PPMB_ERR_INVALID;
+    if (c->owns_state) return fail(c, PPMB_ERR_INVALID, "bind_state: a batch owns its state arenas");
     if (!a || !b || a == b) return fail(c, PPMB_ERR_INVALID, "bind_state: two distinct device buffers required");
+    free_graph(c);
     c->buf[0] = a;
     c->buf[1] = b;
     c->cur = 0;
@@ -190,22 +421,27 @@ ppmb_status ppmb_current_state(const ppmb_ctx *c, void **dev_state)
     return PPMB_OK;
 }
 
-ppmb_status ppmb_set_base_state(ppmb_ctx *c, int kind, const double params[6])
+ppmb_status ppmb_brick_set_base_state(ppmb_ctx *c, int brick, int kind, const double params[6])
 {
     if (!c) return PPMB_ERR_INVALID;
+    if (brick < 0 || brick >= c->nb) return fail(c, PPMB_ERR_INVALID, "brick index out of range");
+    const Brick &B = c->hb[brick];
     if (kind < 0 || kind > 3) return fail(c, PPMB_ERR_INVALID, "set_base_state: unknown kind");
     if (kind != PPMB_BASE_NONE && !params) return fail(c, PPMB_ERR_INVALID, "set_base_state: params required");
-    if (kind == PPMB_BASE_POLY_Z && c->g.grav_kind != PPMB_GRAV_CONST)
+    if (kind == PPMB_BASE_POLY_Z && B.g.grav_kind != PPMB_GRAV_CONST)
         return fail(c, PPMB_ERR_INVALID, "POLY_Z needs constant gravity");
-    if (kind == PPMB_BASE_POLY_R && c->g.grav_kind != PPMB_GRAV_RADIAL)
+    if (kind == PPMB_BASE_POLY_R && B.g.grav_kind != PPMB_GRAV_RADIAL)
         return fail(c, PPMB_ERR_INVALID, "POLY_R needs radial gravity");
-    if ((kind == PPMB_BASE_POLY_Z || kind == PPMB_BASE_POLY_R) &&
-        (!(params[0] > 0) || !(params[1] > 0) || !(params[4] > 0) || !(params[5] > params[2])))
+    const bool poly = kind == PPMB_BASE_POLY_Z || kind == PPMB_BASE_POLY_R;
+    if (poly && (!(params[0] > 0) || !(params[1] > 0) || !(params[4] > 0) || !(params[5] > params[2])))
         return fail(c, PPMB_ERR_INVALID, "set_base_state: bad polytrope parameters");
-    if (kind == PPMB_BASE_POLY_Z || kind == PPMB_BASE_POLY_R) {
-        double hmax = c->g.dx / 8.0;
-        long need = 64 + (long)((params[5] - params[2]) / hmax) + 16;
+    if (poly) {
+        double hmax = B.g.dx / 8.0;
+        double span = (params[5] - params[2]) / hmax;
+        if (span > 1e8) return fail(c, PPMB_ERR_INVALID, "set_base_state: table too long");
+        long need = 64 + (long)span + 16;
         if (need > c->table_len) {
+            HIPCHK(c, hipStreamSynchronize(c->stream));
             hipFree(c->table);
             c->table = nullptr;
             c->table_len = need;
@@ -213,46 +449,57 @@ ppmb_status ppmb_set_base_state(ppmb_ctx *c, int kind, const double params[6])
                 return fail(c, PPMB_ERR_NOMEM, "set_base_state: table allocation");
         }
     }
-    HIPCHK(c, launch_base_state(c->g, kind, params, c->table, c->table_len, c->base64,
-                                c->base64 + c->ncell, c->stream));
+    double *r0 = c->base64 + B.boff;
+    HIPCHK(c, launch_base_state(B.g, kind, params, c->table, c->table_len, r0, r0 + B.ncell, c->stream));
     if (c->prec == PPMB_FP32)
-        HIPCHK(c, launch_narrow<float>(c->base64, static_cast<float *>(c->baseT), 2 * c->ncell, c->stream));
+        HIPCHK(c, launch_narrow<float>(r0, static_cast<float *>(c->baseT) + B.boff, 2 * B.ncell, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (kind == PPMB_BASE_POLY_Z || kind == PPMB_BASE_POLY_R) {
+    if (poly) {
         double nseg = 0;
         HIPCHK(c, hipMemcpy(&nseg, c->table, sizeof(double), hipMemcpyDeviceToHost));
         if (nseg < 1) return fail(c, PPMB_ERR_INVALID, "set_base_state: table overflow");
     }
-    c->base_set = true;
+    return PPMB_OK;
+}
+
+ppmb_status ppmb_set_base_state(ppmb_ctx *c, int kind, const double params[6])
+{
+    return ppmb_brick_set_base_state(c, 0, kind, params);
+}
+
+ppmb_status ppmb_brick_get_base(ppmb_ctx *c, int brick, double *host_rho0, double *host_p0)
+{
+    if (!c || !host_rho0 || !host_p0) return PPMB_ERR_INVALID;
+    if (brick < 0 || brick >= c->nb) return fail(c, PPMB_ERR_INVALID, "brick index out of range");
+    const Brick &B = c->hb[brick];
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(host_rho0, c->base64 + B.boff, sizeof(double) * B.ncell, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(host_p0, c->base64 + B.boff + B.ncell, sizeof(double) * B.ncell, hipMemcpyDeviceToHost));
     return PPMB_OK;
 }
 
 ppmb_status ppmb_get_base(ppmb_ctx *c, double *host_rho0, double *host_p0)
 {
-    if (!c || !host_rho0 || !host_p0) return PPMB_ERR_INVALID;
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(host_rho0, c->base64, sizeof(double) * c->ncell, hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(host_p0, c->base64 + c->ncell, sizeof(double) * c->ncell, hipMemcpyDeviceToHost));
-    return PPMB_OK;
+    return ppmb_brick_get_base(c, 0, host_rho0, host_p0);
 }
 
-static ppmb_status need_state(ppmb_ctx *c)
+static ppmb_status set_state_dev(ppmb_ctx *c, int brick, const double *const dev_prim[15])
 {
-    if (!c->buf[0] || !c->buf[1]) return fail(c, PPMB_ERR_INVALID, "state buffers not bound");
+    TRY(check_brick(c, brick));
+    const Brick &B = c->hb[brick];
+    for (int q = 0; q < NF; ++q)
+        if (!dev_prim[q]) return fail(c, PPMB_ERR_INVALID, "set_state: null field");
+    if (c->prec == PPMB_FP64)
+        HIPCHK(c, launch_prim_to_cons<double>(B.g, dev_prim, c->base64 + B.boff, arena<double>(c, c->cur) + B.off, c->stream));
+    else
+        HIPCHK(c, launch_prim_to_cons<float>(B.g, dev_prim, c->base64 + B.boff, arena<float>(c, c->cur) + B.off, c->stream));
     return PPMB_OK;
 }
 
 ppmb_status ppmb_set_state_device(ppmb_ctx *c, const double *const dev_prim[15])
 {
     if (!c || !dev_prim) return PPMB_ERR_INVALID;
-    if (need_state(c) != PPMB_OK) return PPMB_ERR_INVALID;
-    for (int q = 0; q < NF; ++q)
-        if (!dev_prim[q]) return fail(c, PPMB_ERR_INVALID, "set_state: null field");
-    if (c->prec == PPMB_FP64)
-        HIPCHK(c, launch_prim_to_cons<double>(c->g, dev_prim, c->base64, cur_state<double>(c), c->stream));
-    else
-        HIPCHK(c, launch_prim_to_cons<float>(c->g, dev_prim, c->base64, cur_state<float>(c), c->stream));
-    return PPMB_OK;
+    return set_state_dev(c, 0, dev_prim);
 }
 
 // FP64 device staging of 15 fields for host transfers, freed on return
@@ -261,41 +508,72 @@ struct Staging {
     ~Staging() { if (p) hipFree(p); }
 };
 
-ppmb_status ppmb_set_state(ppmb_ctx *c, const double *const host_prim[15])
+ppmb_status ppmb_brick_set_state(ppmb_ctx *c, int brick, const double *const host_prim[15])
 {
     if (!c || !host_prim) return PPMB_ERR_INVALID;
-    if (need_state(c) != PPMB_OK) return PPMB_ERR_INVALID;
+    TRY(check_brick(c, brick));
+    const long n = c->hb[brick].ncell;
     Staging st;
-    if (hipMalloc(&st.p, sizeof(double) * NF * c->ncell) != hipSuccess)
+    if (hipMalloc(&st.p, sizeof(double) * NF * n) != hipSuccess)
         return fail(c, PPMB_ERR_NOMEM, "set_state: staging");
     const double *dev[NF];
     for (int q = 0; q < NF; ++q) {
         if (!host_prim[q]) return fail(c, PPMB_ERR_INVALID, "set_state: null field");
-        HIPCHK(c, hipMemcpyAsync(st.p + q * c->ncell, host_prim[q], sizeof(double) * c->ncell,
-                                 hipMemcpyHostToDevice, c->stream));
-        dev[q] = st.p + q * c->ncell;
+        HIPCHK(c, hipMemcpyAsync(st.p + q * n, host_prim[q], sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+        dev[q] = st.p + q * n;
     }
-    ppmb_status s = ppmb_set_state_device(c, dev);
-    if (s != PPMB_OK) return s;
+    TRY(set_state_dev(c, brick, dev));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PPMB_OK;
+}
+
+ppmb_status ppmb_set_state(ppmb_ctx *c, const double *const host_prim[15])
+{
+    return ppmb_brick_set_state(c, 0, host_prim);
+}
+
+ppmb_status ppmb_brick_get_state(ppmb_ctx *c, int brick, double *const host_prim[15])
+{
+    if (!c || !host_prim) return PPMB_ERR_INVALID;
+    TRY(check_brick(c, brick));
+    const Brick &B = c->hb[brick];
+    const long n = B.ncell;
+    Staging st;
+    if (hipMalloc(&st.p, sizeof(double) * NF * n) != hipSuccess)
+        return fail(c, PPMB_ERR_NOMEM, "get_state: staging");
+    if (c->prec == PPMB_FP64)
+        HIPCHK(c, launch_cons_to_prim<double>(B.g, arena<double>(c, c->cur) + B.off, c->base64 + B.boff, st.p, c->stream));
+    else
+        HIPCHK(c, launch_cons_to_prim<float>(B.g, arena<float>(c, c->cur) + B.off, c->base64 + B.boff, st.p, c->stream));
+    for (int q = 0; q < NF; ++q) {
+        if (!host_prim[q]) return fail(c, PPMB_ERR_INVALID, "get_state: null field");
+        HIPCHK(c, hipMemcpyAsync(host_prim[q], st.p + q * n, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PPMB_OK;
 }
 
 ppmb_status ppmb_get_state(ppmb_ctx *c, double *const host_prim[15])
 {
-    if (!c || !host_prim) return PPMB_ERR_INVALID;
-    if (need_state(c) != PPMB_OK) return PPMB_ERR_INVALID;
+    return ppmb_brick_get_state(c, 0, host_prim);
+}
+
+ppmb_status ppmb_brick_get_conserved(ppmb_ctx *c, int brick, double *const host_cons[15])
+{
+    if (!c || !host_cons) return PPMB_ERR_INVALID;
+    TRY(check_brick(c, brick));
+    const Brick &B = c->hb[brick];
+    const long n = B.ncell;
     Staging st;
-    if (hipMalloc(&st.p, sizeof(double) * NF * c->ncell) != hipSuccess)
-        return fail(c, PPMB_ERR_NOMEM, "get_state: staging");
+    if (hipMalloc(&st.p, sizeof(double) * NF * n) != hipSuccess)
+        return fail(c, PPMB_ERR_NOMEM, "get_conserved: staging");
     if (c->prec == PPMB_FP64)
-        HIPCHK(c, launch_cons_to_prim<double>(c->g, cur_state<double>(c), c->base64, st.p, c->stream));
+        HIPCHK(c, launch_widen<double>(arena<double>(c, c->cur) + B.off, st.p, NF * n, c->stream));
     else
-        HIPCHK(c, launch_cons_to_prim<float>(c->g, cur_state<float>(c), c->base64, st.p, c->stream));
+        HIPCHK(c, launch_widen<float>(arena<float>(c, c->cur) + B.off, st.p, NF * n, c->stream));
     for (int q = 0; q < NF; ++q) {
-        if (!host_prim[q]) return fail(c, PPMB_ERR_INVALID, "get_state: null field");
-        HIPCHK(c, hipMemcpyAsync(host_prim[q], st.p + q * c->ncell, sizeof(double) * c->ncell,
-                                 hipMemcpyDeviceToHost, c->stream));
+        if (!host_cons[q]) return fail(c, PPMB_ERR_INVALID, "get_conserved: null field");
+        HIPCHK(c, hipMemcpyAsync(host_cons[q], st.p + q * n, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PPMB_OK;
@@ -303,147 +581,123 @@ ppmb_status ppmb_get_state(ppmb_ctx *c, double *const host_prim[15])
 
 ppmb_status ppmb_get_conserved(ppmb_ctx *c, double *const host_cons[15])
 {
-    if (!c || !host_cons) return PPMB_ERR_INVALID;
-    if (need_state(c) != PPMB_OK) return PPMB_ERR_INVALID;
-    Staging st;
-    if (hipMalloc(&st.p, sizeof(double) * NF * c->ncell) != hipSuccess)
-        return fail(c, PPMB_ERR_NOMEM, "get_conserved: staging");
-    if (c->prec == PPMB_FP64)
-        HIPCHK(c, launch_widen<double>(cur_state<double>(c), st.p, NF * c->ncell, c->stream));
-    else
-        HIPCHK(c, launch_widen<float>(cur_state<float>(c), st.p, NF * c->ncell, c->stream));
-    for (int q = 0; q < NF; ++q) {
-        if (!host_cons[q]) return fail(c, PPMB_ERR_INVALID, "get_conserved: null field");
-        HIPCHK(c, hipMemcpyAsync(host_cons[q], st.p + q * c->ncell, sizeof(double) * c->ncell,
-                                 hipMemcpyDeviceToHost, c->stream));
-    }
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    return PPMB_OK;
+    return ppmb_brick_get_conserved(c, 0, host_cons);
 }
 
 ppmb_status ppmb_set_conserved(ppmb_ctx *c, const double *const host_cons[15])
 {
     if (!c || !host_cons) return PPMB_ERR_INVALID;
-    if (need_state(c) != PPMB_OK) return PPMB_ERR_INVALID;
+    TRY(check_brick(c, 0));
+    const Brick &B = c->hb[0];
+    const long n = B.ncell;
     Staging st;
-    if (hipMalloc(&st.p, sizeof(double) * NF * c->ncell) != hipSuccess)
+    if (hipMalloc(&st.p, sizeof(double) * NF * n) != hipSuccess)
         return fail(c, PPMB_ERR_NOMEM, "set_conserved: staging");
     for (int q = 0; q < NF; ++q) {
         if (!host_cons[q]) return fail(c, PPMB_ERR_INVALID, "set_conserved: null field");
-        HIPCHK(c, hipMemcpyAsync(st.p + q * c->ncell, host_cons[q], sizeof(double) * c->ncell,
-                                 hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(st.p + q * n, host_cons[q], sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
     }
     if (c->prec == PPMB_FP64)
-        HIPCHK(c, launch_narrow<double>(st.p, cur_state<double>(c), NF * c->ncell, c->stream));
+        HIPCHK(c, launch_narrow<double>(st.p, arena<double>(c, c->cur) + B.off, NF * n, c->stream));
     else
-        HIPCHK(c, launch_narrow<float>(st.p, cur_state<float>(c), NF * c->ncell, c->stream));
+        HIPCHK(c, launch_narrow<float>(st.p, arena<float>(c, c->cur) + B.off, NF * n, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return PPMB_OK;
-}
-
-static ppmb_status enqueue_cfl(ppmb_ctx *c, double cfl)
-{
-    if (c->prec == PPMB_FP64)
-        HIPCHK(c, launch_cfl<double>(c->g, cur_state<double>(c), c->base64, c->base64 + c->ncell,
-                                     c->work, cfl, c->dt_dev, c->stream));
-    else
-        HIPCHK(c, launch_cfl<float>(c->g, cur_state<float>(c), c->base64, c->base64 + c->ncell,
-                                    c->work, cfl, c->dt_dev, c->stream));
-    return PPMB_OK;
-}
-
-static ppmb_status check_flag(ppmb_ctx *c)
-{
-    unsigned long long w[2];
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(w, c->work, sizeof(w), hipMemcpyDeviceToHost));
-    if (w[1]) {
-        HIPCHK(c, launch_zero_u64(c->work + 1, 1, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        return fail(c, PPMB_ERR_NONPHYSICAL, "non-positive density or pressure, or NaN, in a fluid cell");
-    }
     return PPMB_OK;
 }
 
 ppmb_status ppmb_compute_dt(ppmb_ctx *c, double cfl, double *dt_out)
 {
     if (!c || !dt_out || !(cfl > 0)) return PPMB_ERR_INVALID;
-    if (need_state(c) != PPMB_OK) return PPMB_ERR_INVALID;
-    ppmb_status s = enqueue_cfl(c, cfl);
-    if (s != PPMB_OK) return s;
-    s = check_flag(c);
-    if (s != PPMB_OK) return s;
-    HIPCHK(c, hipMemcpy(dt_out, c->dt_dev, sizeof(double), hipMemcpyDeviceToHost));
-    return PPMB_OK;
-}
-
-static ppmb_status enqueue_pass(ppmb_ctx *c, int axis, int heat)
-{
-    hipError_t e;
-    if (c->prec == PPMB_FP64)
-        e = launch_sweep<double>(c->g, axis, static_cast<const double *>(c->buf[c->cur]),
-                                 static_cast<double *>(c->buf[1 - c->cur]),
-                                 static_cast<const double *>(base_rho(c)),
-                                 static_cast<const double *>(base_p(c)), c->dt_dev, c->cnt, heat, c->stream);
-    else
-        e = launch_sweep<float>(c->g, axis, static_cast<const float *>(c->buf[c->cur]),
-                                static_cast<float *>(c->buf[1 - c->cur]),
-                                static_cast<const float *>(base_rho(c)),
-                                static_cast<const float *>(base_p(c)), c->dt_dev, c->cnt, heat, c->stream);
-    if (e != hipSuccess) return hipfail(c, e, "sweep launch");
-    c->cur = 1 - c->cur;
-    return PPMB_OK;
-}
-
-static ppmb_status enqueue_step(ppmb_ctx *c)
-{
-    const int heat = c->g.heat_kind != PPMB_HEAT_NONE;
-    const int order[2][3] = { { 0, 1, 2 }, { 2, 1, 0 } };
-    const int *o = order[c->nstep & 1];
-    for (int p = 0; p < 3; ++p) {
-        ppmb_status s = enqueue_pass(c, o[p], p == 2 ? heat : 0);
-        if (s != PPMB_OK) return s;
-    }
-    c->nstep++;
-    c->steps++;
+    TRY(need_state(c));
+    TRY(enqueue_cfl(c, cfl, 0, c->nb));
+    TRY(check_flag(c));
+    HIPCHK(c, hipMemcpy(dt_out, c->dt, sizeof(double), hipMemcpyDeviceToHost));
     return PPMB_OK;
 }
 
 ppmb_status ppmb_step(ppmb_ctx *c, double dt)
 {
     if (!c || !(dt > 0) || !std::isfinite(dt)) return PPMB_ERR_INVALID;
-    if (need_state(c) != PPMB_OK) return PPMB_ERR_INVALID;
-    HIPCHK(c, launch_set_scalar(c->dt_dev, dt, c->stream));
-    return enqueue_step(c);
+    TRY(need_state(c));
+    for (int b = 0; b < c->nb; ++b) HIPCHK(c, launch_set_scalar(c->dt + b, dt, c->stream));
+    return enqueue_step(c, false, 0.0, false);
 }
 
 ppmb_status ppmb_step_auto(ppmb_ctx *c, double cfl, int nsteps)
 {
     if (!c || !(cfl > 0) || nsteps < 0) return PPMB_ERR_INVALID;
-    if (need_state(c) != PPMB_OK) return PPMB_ERR_INVALID;
-    for (int s = 0; s < nsteps; ++s) {
-        ppmb_status r = enqueue_cfl(c, cfl);
-        if (r != PPMB_OK) return r;
-        r = enqueue_step(c);
-        if (r != PPMB_OK) return r;
-    }
+    TRY(need_state(c));
+    for (int s = 0; s < nsteps; ++s) TRY(enqueue_step(c, true, cfl, false));
     return PPMB_OK;
 }
 
-ppmb_status ppmb_last_dt(ppmb_ctx *c, double *dt_out)
+// Two steps (an even and an odd pass order) captured once into a hipGraph
+// and replayed; recaptured when the arena, the step parity or cfl differ
+// from the captured ones.
+static ppmb_status graph_steps(ppmb_ctx *c, double cfl, int nsteps)
 {
-    if (!c || !dt_out) return PPMB_ERR_INVALID;
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(dt_out, c->dt_dev, sizeof(double), hipMemcpyDeviceToHost));
+    int pairs = nsteps / 2;
+    if (pairs > 0) {
+        if (!c->gexec || c->gkey_cur != c->cur || c->gkey_par != (int)(c->nstep & 1) || c->gkey_cfl != cfl) {
+            free_graph(c);
+            const int cur0 = c->cur;
+            const long ns0 = c->nstep;
+            const unsigned long long st0 = c->steps;
+            const bool prof = c->profiling;
+            c->profiling = false;
+            HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            ppmb_status s = enqueue_step(c, true, cfl, false);
+            if (s == PPMB_OK) s = enqueue_step(c, true, cfl, false);
+            hipError_t e = hipStreamEndCapture(c->stream, &c->graph);
+            c->profiling = prof;
+            c->cur = cur0;
+            c->nstep = ns0;
+            c->steps = st0;
+            if (s != PPMB_OK) return s;
+            HIPCHK(c, e);
+            HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+            c->gkey_cur = cur0;
+            c->gkey_par = (int)(ns0 & 1);
+            c->gkey_cfl = cfl;
+        }
+        for (int p = 0; p < pairs; ++p) {
+            HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+            c->nstep += 2;
+            c->steps += 2;
+        }
+    }
+    if (nsteps % 2) TRY(enqueue_step(c, true, cfl, false));
     return PPMB_OK;
 }
+
+ppmb_status ppmb_batch_step(ppmb_ctx *c, double cfl, int nsteps, int mode)
+{
+    if (!c || !(cfl > 0) || nsteps < 0 || mode < 0 || mode > 2) return PPMB_ERR_INVALID;
+    TRY(need_state(c));
+    if (mode == 1) return graph_steps(c, cfl, nsteps);
+    for (int s = 0; s < nsteps; ++s) TRY(enqueue_step(c, true, cfl, mode == 2));
+    return PPMB_OK;
+}
+
+ppmb_status ppmb_brick_last_dt(ppmb_ctx *c, int brick, double *dt_out)
+{
+    if (!c || !dt_out) return PPMB_ERR_INVALID;
+    if (brick < 0 || brick >= c->nb) return fail(c, PPMB_ERR_INVALID, "brick index out of range");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(dt_out, c->dt + brick, sizeof(double), hipMemcpyDeviceToHost));
+    return PPMB_OK;
+}
+
+ppmb_status ppmb_last_dt(ppmb_ctx *c, double *dt_out) { return ppmb_brick_last_dt(c, 0, dt_out); }
 
 ppmb_status ppmb_pass(ppmb_ctx *c, int axis, double dt, int heat)
 {
     if (!c || axis < 0 || axis > 2 || !(dt > 0)) return PPMB_ERR_INVALID;
-    if (need_state(c) != PPMB_OK) return PPMB_ERR_INVALID;
-    HIPCHK(c, launch_set_scalar(c->dt_dev, dt, c->stream));
-    return enqueue_pass(c, axis, heat ? (c->g.heat_kind != PPMB_HEAT_NONE) : 0);
+    TRY(need_state(c));
+    for (int b = 0; b < c->nb; ++b) HIPCHK(c, launch_set_scalar(c->dt + b, dt, c->stream));
+    TRY(enqueue_pass(c, axis, heat ? (any_heat(c) ? 1 : 0) : 0, 0, c->nb, c->cur));
+    c->cur = 1 - c->cur;
+    return PPMB_OK;
 }
 
 ppmb_status ppmb_get_nstep(const ppmb_ctx *c, long *nstep)
@@ -460,20 +714,23 @@ ppmb_status ppmb_set_nstep(ppmb_ctx *c, long nstep)
     return PPMB_OK;
 }
 
-ppmb_status ppmb_reduce_totals(ppmb_ctx *c, double out[8])
+ppmb_status ppmb_brick_totals(ppmb_ctx *c, int brick, double out[8])
 {
     if (!c || !out) return PPMB_ERR_INVALID;
-    if (need_state(c) != PPMB_OK) return PPMB_ERR_INVALID;
+    TRY(check_brick(c, brick));
+    const Brick &B = c->hb[brick];
     if (c->prec == PPMB_FP64)
-        HIPCHK(c, launch_totals<double>(c->g, cur_state<double>(c), c->base64, c->base64 + c->ncell,
-                                        c->partials, c->out8, c->stream));
+        HIPCHK(c, launch_totals<double>(B.g, arena<double>(c, c->cur) + B.off, c->base64 + B.boff,
+                                        c->base64 + B.boff + B.ncell, c->partials, c->out8, c->stream));
     else
-        HIPCHK(c, launch_totals<float>(c->g, cur_state<float>(c), c->base64, c->base64 + c->ncell,
-                                       c->partials, c->out8, c->stream));
+        HIPCHK(c, launch_totals<float>(B.g, arena<float>(c, c->cur) + B.off, c->base64 + B.boff,
+                                       c->base64 + B.boff + B.ncell, c->partials, c->out8, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(out, c->out8, sizeof(double) * 8, hipMemcpyDeviceToHost));
     return PPMB_OK;
 }
+
+ppmb_status ppmb_reduce_totals(ppmb_ctx *c, double out[8]) { return ppmb_brick_totals(c, 0, out); }
 
 ppmb_status ppmb_counters(ppmb_ctx *c, unsigned long long out[4])
 {
@@ -482,6 +739,138 @@ ppmb_status ppmb_counters(ppmb_ctx *c, unsigned long long out[4])
     HIPCHK(c, hipMemcpy(out, c->cnt, sizeof(unsigned long long) * 3, hipMemcpyDeviceToHost));
     out[3] = c->steps;
     return PPMB_OK;
+}
+
+ppmb_status ppmb_set_pass_shape(ppmb_ctx *c, int march_waves, int x_waves)
+{
+    if (!c) return PPMB_ERR_INVALID;
+    auto ok = [](int w) { return w == 1 || w == 2 || w == 4; };
+    if (!ok(march_waves) || !ok(x_waves)) return fail(c, PPMB_ERR_INVALID, "pass shape: waves per block must be 1, 2 or 4");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->shape = PassShape{ march_waves, x_waves };
+    return build_maps(c);
+}
+
+ppmb_status ppmb_get_pass_shape(const ppmb_ctx *c, int *march_waves, int *x_waves)
+{
+    if (!c || !march_waves || !x_waves) return PPMB_ERR_INVALID;
+    *march_waves = c->shape.march_waves;
+    *x_waves = c->shape.x_waves;
+    return PPMB_OK;
+}
+
+ppmb_status ppmb_brick_count(const ppmb_ctx *c, int *nbricks)
+{
+    if (!c || !nbricks) return PPMB_ERR_INVALID;
+    *nbricks = c->nb;
+    return PPMB_OK;
+}
+
+static std::string tune_key(const ppmb_ctx *c)
+{
+    long cells = 0;
+    for (auto &B : c->hb) cells += B.ncell;
+    char k[128];
+    snprintf(k, sizeof k, "gfx950 %s bricks=%d cells=%ld", c->prec == PPMB_FP64 ? "fp64" : "fp32", c->nb, cells);
+    return k;
+}
+
+ppmb_status ppmb_autotune(ppmb_ctx *c, double cfl, int reps, const char *cache_path, int out_shape[2])
+{
+    if (!c || !out_shape || !(cfl > 0) || reps < 1) return PPMB_ERR_INVALID;
+    TRY(need_state(c));
+    const std::string key = tune_key(c);
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "r");
+        if (f) {
+            char line[256];
+            int mw = 0, xw = 0;
+            while (fgets(line, sizeof line, f)) {
+                char kbuf[200];
+                if (sscanf(line, "%199[^|]| %d %d", kbuf, &mw, &xw) == 3 && key == std::string(kbuf)) {
+                    fclose(f);
+                    TRY(ppmb_set_pass_shape(c, mw, xw));
+                    out_shape[0] = mw;
+                    out_shape[1] = xw;
+                    return PPMB_OK;
+                }
+            }
+            fclose(f);
+        }
+    }
+    unsigned long long saved[3];
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(saved, c->cnt, sizeof saved, hipMemcpyDeviceToHost));
+    TRY(enqueue_cfl(c, cfl, 0, c->nb));
+    TRY(check_flag(c));
+    const bool prof = c->profiling;
+    c->profiling = false;
+    const int cand[3] = { 1, 2, 4 };
+    float best_m = 1e30f, best_x = 1e30f;
+    int bm = c->shape.march_waves, bx = c->shape.x_waves;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    ppmb_status st = PPMB_OK;
+    for (int a = 0; a < 3 && st == PPMB_OK; ++a) {
+        st = ppmb_set_pass_shape(c, cand[a], cand[a]);
+        float tm = 0.f, tx = 0.f;
+        for (int axis = 0; axis < 3 && st == PPMB_OK; ++axis) {
+            st = enqueue_pass(c, axis, 0, 0, c->nb, c->cur);          // warm-up
+            if (hipEventRecord(e0, c->stream) != hipSuccess) st = PPMB_ERR_HIP;
+            for (int r = 0; r < reps && st == PPMB_OK; ++r) st = enqueue_pass(c, axis, 0, 0, c->nb, c->cur);
+            if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) st = PPMB_ERR_HIP;
+            float ms = 0.f;
+            if (st == PPMB_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = PPMB_ERR_HIP;
+            if (axis == 0) tx = ms; else tm += ms;
+        }
+        if (st == PPMB_OK && tm < best_m) { best_m = tm; bm = cand[a]; }
+        if (st == PPMB_OK && tx < best_x) { best_x = tx; bx = cand[a]; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->profiling = prof;
+    if (st != PPMB_OK) return st;
+    HIPCHK(c, hipMemcpy(c->cnt, saved, sizeof saved, hipMemcpyHostToDevice));
+    TRY(ppmb_set_pass_shape(c, bm, bx));
+    out_shape[0] = bm;
+    out_shape[1] = bx;
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s| %d %d\n", key.c_str(), bm, bx);
+            fclose(f);
+        }
+    }
+    return PPMB_OK;
+}
+
+ppmb_status ppmb_profile_enable(ppmb_ctx *c, int enable)
+{
+    if (!c) return PPMB_ERR_INVALID;
+    c->profiling = enable != 0;
+    return PPMB_OK;
+}
+
+ppmb_status ppmb_profile_read(ppmb_ctx *c, double ms[3], long count[3])
+{
+    if (!c || !ms || !count) return PPMB_ERR_INVALID;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int d = 0; d < 3; ++d) { ms[d] = 0.0; count[d] = 0; }
+    ppmb_status st = PPMB_OK;
+    for (auto &t : c->timed) {
+        float v = 0.f;
+        if (st == PPMB_OK && hipEventElapsedTime(&v, t.a, t.b) == hipSuccess) {
+            ms[t.axis] += v;
+            count[t.axis] += 1;
+        } else {
+            st = fail(c, PPMB_ERR_HIP, "profile_read: event timing failed");
+        }
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    c->timed.clear();
+    return st;
 }
 
 ppmb_status ppmb_synchronize(ppmb_ctx *c)

@@ -223,20 +223,30 @@ hipError_t launch_narrow(const double *src, T *dst, long count, hipStream_t st)
 // all in FP64.  The maximum is order independent, so it is exact.
 // ---------------------------------------------------------------------
 
-__global__ void cfl_reset_kernel(unsigned long long *work)
+int cfl_blocks(long ncell) { return (int)((ncell + kCflBlockCells - 1) / kCflBlockCells); }
+
+__global__ void cfl_reset_kernel(unsigned long long *work, int b0, int nb)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) work[0] = 0ull;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) work[2 * (b0 + b)] = 0ull;
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void cfl_kernel(Geom g, const T *S, const double *rho0,
-                                                  const double *p0, unsigned long long *work)
+__global__ __launch_bounds__(256) void cfl_kernel(const Brick *bricks, const BlockMap *map,
+                                                  const T *arena, const double *base64,
+                                                  unsigned long long *work)
 {
-    const long nc = (long)g.n[0] * g.n[1] * g.n[2];
+    const BlockMap m = map[blockIdx.x];
+    const Brick &B = bricks[m.brick];
+    const Geom g = B.g;
+    const long nc = B.ncell;
+    const T *S = arena + B.off;
+    const double *rho0 = base64 + B.boff, *p0 = base64 + B.boff + nc;
     const double gm1 = g.gamma - 1.0;
+    const long c0 = (long)m.local * kCflBlockCells;
+    const long c1 = c0 + kCflBlockCells < nc ? c0 + kCflBlockCells : nc;
     double smax = 0.0;
     bool bad = false;
-    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
+    for (long c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
         if (g.sphere) {
             int i = (int)(c % g.n[0]);
             int j = (int)((c / g.n[0]) % g.n[1]);
@@ -249,34 +259,37 @@ __global__ __launch_bounds__(256) void cfl_kernel(Geom g, const T *S, const doub
         double pp = gm1 * ((double)S[EN * nc + c] - 0.5 * (mx * u + my * v + mz * w));
         double p = p0[c] + pp;
         double cs = sqrt(g.gamma * p / rho);
-        double s = fmax(fabs(u), fmax(fabs(v), fabs(w))) + cs;
-        if (!(rho > 0.0) || !(p > 0.0) || !(s == s) || s > 1e300) bad = true;
-        else if (s > smax) smax = s;
+        double sp = fmax(fabs(u), fmax(fabs(v), fabs(w))) + cs;
+        if (!(rho > 0.0) || !(p > 0.0) || !(sp == sp) || sp > 1e300) bad = true;
+        else if (sp > smax) smax = sp;
     }
     // wave64 max, then one atomic per wave (positive doubles order like their bits)
     for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_down(smax, off));
-    unsigned long long b = __ballot(bad);
+    unsigned long long bb = __ballot(bad);
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(&work[0], (unsigned long long)__double_as_longlong(smax));
-        if (b) atomicOr(&work[1], 1ull);
+        atomicMax(&work[2 * m.brick], (unsigned long long)__double_as_longlong(smax));
+        if (bb) atomicOr(&work[2 * m.brick + 1], 1ull);
     }
 }
 
-__global__ void cfl_finish_kernel(const unsigned long long *work, double cfl, double dx, double *dtp)
+__global__ void cfl_finish_kernel(const Brick *bricks, int b0, int nb, const unsigned long long *work,
+                                  double cfl, double *dt)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double smax = __longlong_as_double((long long)work[0]);
-        dtp[0] = cfl * dx / smax;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const Brick &B = bricks[b0 + b];
+        double smax = __longlong_as_double((long long)work[2 * (b0 + b)]);
+        dt[B.dti] = cfl * B.g.dx / smax;
     }
 }
 
 template <typename T>
-hipError_t launch_cfl(const Geom &g, const T *state, const double *rho0, const double *p0,
-                      unsigned long long *work, double cfl, double *dtp, hipStream_t st)
+hipError_t launch_cfl(const Brick *bricks, int b0, int nb, const BlockMap *map, int nblocks,
+                      const T *state, const double *base64, unsigned long long *work, double cfl,
+                      double *dt, hipStream_t st)
 {
-    hipLaunchKernelGGL(cfl_reset_kernel, dim3(1), dim3(64), 0, st, work);
-    hipLaunchKernelGGL((cfl_kernel<T>), dim3(2048), dim3(256), 0, st, g, state, rho0, p0, work);
-    hipLaunchKernelGGL(cfl_finish_kernel, dim3(1), dim3(64), 0, st, work, cfl, g.dx, dtp);
+    hipLaunchKernelGGL(cfl_reset_kernel, dim3(1), dim3(256), 0, st, work, b0, nb);
+    hipLaunchKernelGGL((cfl_kernel<T>), dim3(nblocks), dim3(256), 0, st, bricks, map, state, base64, work);
+    hipLaunchKernelGGL(cfl_finish_kernel, dim3(1), dim3(256), 0, st, bricks, b0, nb, work, cfl, dt);
     return hipGetLastError();
 }
 
@@ -384,8 +397,9 @@ hipError_t launch_zero_u64(unsigned long long *dst, int count, hipStream_t st)
                                                hipStream_t);                                      \
     template hipError_t launch_widen<T>(const T *, double *, long, hipStream_t);                   \
     template hipError_t launch_narrow<T>(const double *, T *, long, hipStream_t);                  \
-    template hipError_t launch_cfl<T>(const Geom &, const T *, const double *, const double *,     \
-                                      unsigned long long *, double, double *, hipStream_t);       \
+    template hipError_t launch_cfl<T>(const Brick *, int, int, const BlockMap *, int, const T *,   \
+                                      const double *, unsigned long long *, double, double *,     \
+                                      hipStream_t);                                               \
     template hipError_t launch_totals<T>(const Geom &, const T *, const double *, const double *,  \
                                          double *, double *, hipStream_t);
 PPMB_INST(float)

@@ -29,9 +29,13 @@ struct Geom {
     int    smooth_detect;
 };
 
-template <typename T> __device__ __forceinline__ T tabs(T a) { return a < T(0) ? -a : a; }
-template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return b < a ? b : a; }
-template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a < b ? b : a; }
+// hardware abs / min / max (operand modifiers and single instructions)
+__device__ __forceinline__ float tabs(float a) { return fabsf(a); }
+__device__ __forceinline__ double tabs(double a) { return fabs(a); }
+__device__ __forceinline__ float tmin(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ double tmin(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float tmax(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double tmax(double a, double b) { return fmax(a, b); }
 
 // ---------------------------------------------------------------------
 // Geometry: ghost mapping, gravity, heating, confining sphere
@@ -82,35 +86,71 @@ __device__ __forceinline__ double grav_taper(const Geom &g, double r)
     return (g.grav[3] - r) / (g.grav[3] - g.grav[2]);
 }
 
-// Component `axis` of the gravitational acceleration at a cell centre.
+// Component `axis` of the gravitational acceleration at a point, in the
+// working precision; rt2 is the squared distance to the centre.
 template <typename T>
-__device__ __forceinline__ T gravity(const Geom &g, int axis, double x, double y, double z)
+__device__ __forceinline__ T gravity(const Geom &g, int axis, T xd, T rt2)
 {
     if (g.grav_kind == 1) return T(g.grav[axis]);
     if (g.grav_kind == 2) {
-        double r = sqrt(r2_exact(x, y, z));
-        double rc = g.grav[1];
-        double h = (r < rc) ? 1.0 / rc : (rc * rc) / (r * r * r);
-        double xd = axis == 0 ? x : (axis == 1 ? y : z);
-        return T(-g.grav[0] * xd * h * grav_taper(g, r));
+        T r = sqrt(rt2);
+        T rc = T(g.grav[1]);
+        T h = (r < rc) ? T(1) / rc : (rc * rc) / (rt2 * r);
+        T r1 = T(g.grav[2]), r2 = T(g.grav[3]);
+        T t = r <= r1 ? T(1) : (r >= r2 ? T(0) : (r2 - r) / (r2 - r1));
+        return -T(g.grav[0]) * xd * h * t;
     }
     return T(0);
 }
 
 // Heating profile: full below half the extent, smoothstep to zero at it.
-__device__ __forceinline__ double heat_shape(double xi)
+template <typename T>
+__device__ __forceinline__ T heat_shape(T xi)
 {
-    if (xi <= 0.5) return 1.0;
-    if (xi >= 1.0) return 0.0;
-    double t = 2.0 * xi - 1.0;
-    return 1.0 - t * t * (3.0 - 2.0 * t);
+    if (xi <= T(0.5)) return T(1);
+    if (xi >= T(1)) return T(0);
+    T t = T(2) * xi - T(1);
+    return T(1) - t * t * (T(3) - T(2) * t);
 }
 
-__device__ __forceinline__ double heating(const Geom &g, double x, double y, double z)
+template <typename T>
+__device__ __forceinline__ T heating(const Geom &g, T z, T rt2)
 {
-    if (g.heat_kind == 1) return g.heat[0] * heat_shape((z - g.heat[2]) / g.heat[1]);
-    if (g.heat_kind == 2) return g.heat[0] * heat_shape(sqrt(r2_exact(x, y, z)) / g.heat[1]);
-    return 0.0;
+    if (g.heat_kind == 1) return T(g.heat[0]) * heat_shape((z - T(g.heat[2])) / T(g.heat[1]));
+    if (g.heat_kind == 2) return T(g.heat[0]) * heat_shape(sqrt(rt2) / T(g.heat[1]));
+    return T(0);
+}
+
+// Fluid cells of a pencil along `axis` through the cell centres with
+// transverse coordinates fixed: the exact solid test is monotone in the
+// distance from the pencil's closest point to the centre, so the fluid
+// cells form one interval [lo, hi] (empty: lo > hi), found by bisection
+// with the same FP64 test as everywhere else.
+__device__ __forceinline__ void fluid_interval(const Geom &g, int axis, const double xt[3], int &lo, int &hi)
+{
+    const int n = g.n[axis];
+    lo = 0;
+    hi = n - 1;
+    if (!g.sphere) return;
+    auto solid = [&](int i) {
+        double x[3] = { xt[0], xt[1], xt[2] };
+        x[axis] = centre(g, axis, i);
+        return solid_at(g, x[0], x[1], x[2]);
+    };
+    // index nearest to coordinate 0 along the pencil, and its neighbours
+    double fm = -g.origin[axis] / g.dx - 0.5;
+    int m = (int)floor(fm + 0.5);
+    m = m < 0 ? 0 : (m > n - 1 ? n - 1 : m);
+    int best = -1;
+    for (int c = m - 1; c <= m + 1; ++c)
+        if (c >= 0 && c < n && !solid(c)) { best = c; break; }
+    if (best < 0) { lo = 1; hi = 0; return; }
+    int a = 0, b = best;                 // first fluid index in [0, best]
+    while (a < b) { int mid = (a + b) / 2; if (solid(mid)) a = mid + 1; else b = mid; }
+    lo = a;
+    a = best; b = n - 1;                 // last fluid index in [best, n-1]
+    while (a < b) { int mid = (a + b + 1) / 2; if (solid(mid)) b = mid - 1; else a = mid; }
+    hi = a;
 }
 
 // ---------------------------------------------------------------------
@@ -137,6 +177,20 @@ __device__ __forceinline__ T smooth_weight(T q0, T q1, T q2, T q3, T q4)
     T d0 = (q0 + q2) - T(2) * q1;
     T d1 = (q1 + q3) - T(2) * q2;
     T d2 = (q2 + q4) - T(2) * q3;
+    if (d0 == T(0) && d1 == T(0) && d2 == T(0)) return T(1);
+    bool same = (d0 > T(0) && d1 > T(0) && d2 > T(0)) || (d0 < T(0) && d1 < T(0) && d2 < T(0));
+    if (!same) return T(0);
+    T a0 = tabs(d0), a1 = tabs(d1), a2 = tabs(d2);
+    T mx = tmax(a0, tmax(a1, a2)), mn = tmin(a0, tmin(a1, a2));
+    if (mx <= T(2) * mn) return T(1);
+    if (mx >= T(3) * mn) return T(0);
+    return (T(3) * mn - mx) / mn;
+}
+
+// The same judgment from the three second differences themselves.
+template <typename T>
+__device__ __forceinline__ T smooth_weight_d(T d0, T d1, T d2)
+{
     if (d0 == T(0) && d1 == T(0) && d2 == T(0)) return T(1);
     bool same = (d0 > T(0) && d1 > T(0) && d2 > T(0)) || (d0 < T(0) && d1 < T(0) && d2 < T(0));
     if (!same) return T(0);
@@ -384,6 +438,142 @@ __device__ __forceinline__ void ppb_update(const T *q, T ds, T dl, const T *GL, 
     }
 #pragma unroll
     for (int c = 7; c < 10; ++c) o[c] = L * q[c] - (GR[c] - GL[c]);
+}
+
+// ---------------------------------------------------------------------
+// Per-cell and per-face stages of the pass, shared by both kernel shapes
+// ---------------------------------------------------------------------
+
+// Edge values of one variable's parabola in cell q: the unconstrained
+// 4th-order face values (qfL, qfR) unless the 5-cell judgment (second
+// differences d0..d2) says otherwise, then the CW84-constrained values from
+// the limited-slope faces (flL, flR), blended over the graded band.
+// Returns true when constraints entered.
+template <typename T>
+__device__ __forceinline__ bool parabola(int detect, T q, T qfL, T qfR, T flL, T flR, T d0, T d1, T d2,
+                                         T &l, T &r)
+{
+    T ws = detect == 1 ? smooth_weight_d(d0, d1, d2) : T(detect == 2 ? 1 : 0);
+    l = qfL;
+    r = qfR;
+    if (!(ws < T(1))) return false;
+    T lc = flL, rc = flR;
+    constrain(q, lc, rc);
+    if (ws > T(0)) { lc = lc + ws * (l - lc); rc = rc + ws * (r - rc); }
+    l = lc;
+    r = rc;
+    return true;
+}
+
+// Characteristic tracing of one cell (CW84 Sec. 3): the states at its right
+// face (TL, seen from the left of that face) and at its left face (TR), from
+// the parabolas of rho', u, v, w, p' (edge values qL, qR, dq, q6), the
+// cell's rho, c, u, rho', gravity, and the base face values, plus the
+// half-step sources (gravity on rho', advection of the base).
+template <typename T>
+__device__ __forceinline__ void trace_cell(const T *qL, const T *qR, const T *dq, const T *q6,
+                                           T rj, T cj, T uj, T rpj, T gj, T r0fL, T r0fR,
+                                           T p0fL, T p0fR, T nu, T hdt, T rdx, St<T> &TL, St<T> &TR)
+{
+    const T c2 = cj * cj;
+    const T lm = uj - cj, l0 = uj, lp = uj + cj;
+    const T irj = T(1) / rj, icj = T(1) / cj;
+    const T rc2 = T(0.5) * rj * icj, cr_ = cj * irj, ic2 = icj * icj, i2c2 = T(0.5) * ic2;
+    {   // right face: waves moving right
+        T y = tmax(lp, T(0)) * nu;
+        T ref[5];
+#pragma unroll
+        for (int vv = 0; vv < 5; ++vv) ref[vv] = avg_right(qR[vv], dq[vv], q6[vv], y);
+        T bz = T(0), bm = T(0);
+        if (l0 > T(0)) {
+            T y0 = l0 * nu;
+            bz = (ref[0] - avg_right(qR[0], dq[0], q6[0], y0)) - (ref[4] - avg_right(qR[4], dq[4], q6[4], y0)) * ic2;
+        }
+        if (lm > T(0)) {
+            T ym = lm * nu;
+            T du = ref[1] - avg_right(qR[1], dq[1], q6[1], ym);
+            T dp = ref[4] - avg_right(qR[4], dq[4], q6[4], ym);
+            bm = dp * i2c2 - rc2 * du;
+        }
+        T yv = tmax(l0, T(0)) * nu;
+        TL.r = ref[0] - bz - bm;
+        TL.u = ref[1] + bm * cr_;
+        TL.v = avg_right(qR[2], dq[2], q6[2], yv);
+        TL.w = avg_right(qR[3], dq[3], q6[3], yv);
+        TL.p = ref[4] - bm * c2;
+    }
+    {   // left face: waves moving left
+        T y = tmax(-lm, T(0)) * nu;
+        T ref[5];
+#pragma unroll
+        for (int vv = 0; vv < 5; ++vv) ref[vv] = avg_left(qL[vv], dq[vv], q6[vv], y);
+        T bz = T(0), bp = T(0);
+        if (l0 < T(0)) {
+            T y0 = -l0 * nu;
+            bz = (ref[0] - avg_left(qL[0], dq[0], q6[0], y0)) - (ref[4] - avg_left(qL[4], dq[4], q6[4], y0)) * ic2;
+        }
+        if (lp < T(0)) {
+            T yp = -lp * nu;
+            T du = ref[1] - avg_left(qL[1], dq[1], q6[1], yp);
+            T dp = ref[4] - avg_left(qL[4], dq[4], q6[4], yp);
+            bp = dp * i2c2 + rc2 * du;
+        }
+        T yv = tmax(-l0, T(0)) * nu;
+        TR.r = ref[0] - bz - bp;
+        TR.u = ref[1] - bp * cr_;
+        TR.v = avg_left(qL[2], dq[2], q6[2], yv);
+        TR.w = avg_left(qL[3], dq[3], q6[3], yv);
+        TR.p = ref[4] - bp * c2;
+    }
+    T su = hdt * (rpj * gj * irj);
+    T sr = hdt * (uj * (r0fR - r0fL) * rdx);
+    T sp = hdt * (uj * (p0fR - p0fL) * rdx);
+    TL.u += su; TR.u += su;
+    TL.r -= sr; TR.r -= sr;
+    TL.p -= sp; TR.p -= sp;
+}
+
+// Riemann problem and fluxes at one face (states Ls | Rs; sa, sb: the two
+// cells are solid).  A face between a fluid and a solid cell is a
+// reflecting wall (Sec. 3): the solid side takes the mirrored fluid state.
+// F = mass, normal, two transverse momenta, energy; sg = u* dt/dx.
+// Returns true when the Riemann problem was counted (FP64 re-solve).
+template <typename T>
+__device__ __forceinline__ bool face_flux(St<T> Ls, St<T> Rs, bool sa, bool sb, T r0f, T p0f, T gam,
+                                          T gfac, T nu, T *F, T &sg)
+{
+    if (sa && sb) {
+#pragma unroll
+        for (int vv = 0; vv < 5; ++vv) F[vv] = T(0);
+        sg = T(0);
+        return false;
+    }
+    if (sb) { Rs = Ls; Rs.u = -Ls.u; }
+    if (sa) { Ls = Rs; Ls.u = -Rs.u; }
+    bool cnt;
+    St<T> f = Solver<T>::solve(Ls, Rs, r0f, p0f, gam, cnt);
+    T rf = r0f + f.r;
+    T Fr = rf * f.u;
+    F[0] = Fr;
+    F[1] = Fr * f.u + f.p;
+    F[2] = Fr * f.v;
+    F[3] = Fr * f.w;
+    F[4] = f.u * (gfac * (p0f + f.p) + T(0.5) * rf * ((f.u * f.u + f.v * f.v) + f.w * f.w));
+    sg = f.u * nu;
+    return cnt;
+}
+
+// Conservative update of one fluid cell: flux differences, gravity on the
+// perturbation density (time centred) and on the mass flux in the energy.
+template <typename T>
+__device__ __forceinline__ void hydro_update(const T *cu, const T *Fl, const T *Fr, T nu, T dt, T gj, T *o)
+{
+    T rn = cu[0] - nu * (Fr[0] - Fl[0]);
+    o[0] = rn;
+    o[1] = cu[1] - nu * (Fr[1] - Fl[1]) + dt * gj * (T(0.5) * (cu[0] + rn));
+    o[2] = cu[2] - nu * (Fr[2] - Fl[2]);
+    o[3] = cu[3] - nu * (Fr[3] - Fl[3]);
+    o[4] = cu[4] - nu * (Fr[4] - Fl[4]) + dt * gj * (T(0.5) * (Fl[0] + Fr[0]));
 }
 
 }  // namespace ppmb

@@ -7,10 +7,42 @@
 
 namespace ppmb {
 
-// fused 1-D pass over every pencil of the grid along `axis`
+// One brick of a batch (a single grid is a batch of one): its grid and where
+// its fields live.  State arena: field q of the brick at off + q * ncell.
+// Base arena (working precision and FP64 alike): rho0 at boff, p0 at
+// boff + ncell.  Its time step is dt[dti].
+struct Brick {
+    Geom g;
+    long off;
+    long boff;
+    long ncell;
+    int dti;
+    int pad;
+};
+
+// One entry per block of a launch: the brick it works on and its index
+// among that brick's blocks.
+struct BlockMap {
+    int brick;
+    int local;
+};
+
+// Launch shape of the pass kernels: waves per block for the marching
+// kernel (y and z passes) and the lanes-along-x kernel (x pass).
+struct PassShape {
+    int march_waves;
+    int x_waves;
+};
+
+// Number of blocks the pass along `axis` needs for one brick.
+int pass_blocks(const Geom &g, int axis, const PassShape &sh);
+
+// Fused 1-D pass along `axis` for the bricks whose blocks are
+// map[0 .. nblocks): one launch, every brick's pencils.
 template <typename T>
-hipError_t launch_sweep(const Geom &g, int axis, const T *in, T *out, const T *rho0, const T *p0,
-                        const double *dtp, unsigned long long *counters, int heat, hipStream_t st);
+hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, const BlockMap *map,
+                        int nblocks, const T *in, T *out, const T *base, const double *dt,
+                        unsigned long long *counters, int heat, hipStream_t st);
 
 // hydrostatic base state: FP64 RK4 node table (one thread), then cell values
 hipError_t launch_base_state(const Geom &g, int kind, const double *params, double *table,
@@ -29,11 +61,16 @@ hipError_t launch_widen(const T *src, double *dst, long count, hipStream_t st);
 template <typename T>
 hipError_t launch_narrow(const double *src, T *dst, long count, hipStream_t st);
 
-// CFL reduction: smax (uint64 image of the FP64 maximum) and a flag word,
-// then dt = cfl * dx / smax into *dtp
+// CFL reduction for bricks [b0, b0 + nb): per brick the uint64 image of the
+// FP64 maximum of |u_d| + c in work[2 brick], a sticky non-physical flag in
+// work[2 brick + 1], then dt[dti] = cfl dx / smax.  `map` covers nblocks
+// blocks of kCflBlockCells cells each.
+constexpr int kCflBlockCells = 65536;
+int cfl_blocks(long ncell);
 template <typename T>
-hipError_t launch_cfl(const Geom &g, const T *state, const double *rho0, const double *p0,
-                      unsigned long long *work, double cfl, double *dtp, hipStream_t st);
+hipError_t launch_cfl(const Brick *bricks, int b0, int nb, const BlockMap *map, int nblocks,
+                      const T *state, const double *base64, unsigned long long *work, double cfl,
+                      double *dt, hipStream_t st);
 
 // conserved totals with a fixed reduction tree; out[8] on the device
 template <typename T>

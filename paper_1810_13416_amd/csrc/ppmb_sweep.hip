@@ -10,19 +10,43 @@
 // load and store of a field is one coalesced 256-byte row.
 #include "ppmb_internal.h"
 
+#include <cstdlib>
+
 namespace ppmb {
 
+// Per-brick view handed to the pencil code: the brick's state, output and
+// base fields, its dt and cell count.
 template <typename T>
 struct SweepArgs {
     const T *in;          // 15 fields, stride ncell
     T *out;
     const T *rho0;        // base state, working precision
     const T *p0;
-    const double *dtp;    // device dt
-    unsigned long long *counters;   // limiter, unsmooth, riemann, (steps)
+    const double *dtp;    // this brick's dt
+    unsigned long long *counters;   // limiter, unsmooth, riemann
     long ncell;
     int heat;             // 1: add the heating source after the update
 };
+
+// Arguments of one pass launch over a batch of bricks.
+template <typename T>
+struct BatchArgs {
+    const Brick *bricks;
+    const BlockMap *map;
+    const T *in;
+    T *out;
+    const T *base;
+    const double *dt;
+    unsigned long long *counters;
+    int heat;
+};
+
+template <typename T>
+__device__ __forceinline__ SweepArgs<T> brick_args(const BatchArgs<T> &b, const Brick &B)
+{
+    return SweepArgs<T>{b.in + B.off, b.out + B.off, b.base + B.boff, b.base + B.boff + B.ncell,
+                        b.dt + B.dti, b.counters, B.ncell, b.heat};
+}
 
 // pass-local order of the 10 fv coefficients and which flip at a wall
 __host__ __device__ constexpr int mixed_of(int a, int b) { return FXY + (4 - a - b) % 3; }
@@ -64,6 +88,12 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
     const long base = ijk0[0] * stride[0] + ijk0[1] * stride[1] + ijk0[2] * stride[2];
     const long sAX = stride[AX];
     const double xt[3] = { centre(g, 0, ijk0[0]), centre(g, 1, ijk0[1]), centre(g, 2, ijk0[2]) };
+    // transverse part of |x|^2 and the fluid interval of this pencil
+    const T xt1 = T(xt[AI::t1]), xt2 = T(xt[AI::t2]);
+    const T rtt = xt1 * xt1 + xt2 * xt2;
+    int flo, fhi;
+    fluid_interval(g, AX, xt, flo, fhi);
+    const T ox = T(g.origin[AX]), dxT = T(g.dx);
 
     const double dt64 = *a.dtp;
     const T dt = T(dt64), nu = T(dt64 / g.dx), hdt = T(0.5 * dt64), rdx = T(1.0 / g.dx);
@@ -81,6 +111,8 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
     bool sol[5];          // solid flags of cells k-4..k
     T qf[2][5], r0f[2], p0f[2];   // faces (k-3)+1/2 and (k-2)+1/2
     T sm[3][5];           // limited slopes of cells k-3..k-1
+    T d2[3][5];           // second differences of cells k-3..k-1
+    T flm[2][5];          // limited-slope face values at (k-3)+1/2, (k-2)+1/2
     St<T> TLp;            // right-face state of cell k-3
     T Fp[5];              // fluxes at face (k-4)+1/2
     T sg1 = T(0), sg2 = T(0);     // sigma at faces (k-4)+1/2, (k-5)+1/2
@@ -97,8 +129,9 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
     for (int k = -NG; k < n + NG; ++k) {
         // ---- (1) load cell k and form its primitives (base added back, Sec. 1)
         {
-            int fl;
-            int s = bc_source(k, n, bc, fl);
+            int fl = 1;
+            int s = k;
+            if (k < 0 || k >= n) s = bc_source(k, n, bc, fl);
             long ci = base + s * sAX;
             T rp = in[RHO * nc + ci];
             T mn = T(fl) * in[(MX + AX) * nc + ci];
@@ -106,14 +139,14 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
             T m2 = in[(MX + AI::t2) * nc + ci];
             T ep = in[EN * nc + ci];
             T r0 = a.rho0[ci], pb = a.p0[ci];
-            double xs[3] = { xt[0], xt[1], xt[2] };
-            xs[AX] = centre(g, AX, s);
-            T gv = T(fl) * gravity<T>(g, AX, xs[0], xs[1], xs[2]);
-            bool so = solid_at(g, xs[0], xs[1], xs[2]);
+            T xd = ox + (T(s) + T(0.5)) * dxT;
+            T gv = T(fl) * gravity<T>(g, AX, xd, rtt + xd * xd);
+            bool so = s < flo || s > fhi;
             T rho = r0 + rp;
-            T u = mn / rho, v = m1 / rho, w = m2 / rho;
+            T ir = T(1) / rho;
+            T u = mn * ir, v = m1 * ir, w = m2 * ir;
             T pp = gm1 * (ep - T(0.5) * (mn * u + m1 * v + m2 * w));
-            T c = sqrt(gam * (pb + pp) / rho);
+            T c = sqrt(gam * (pb + pp) * ir);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -134,8 +167,9 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
         }
         // fv coefficients of cell k-3 (donors -1..n)
         if (k - 3 >= -1) {
-            int fl;
-            int s = bc_source(k - 3, n, bc, fl);
+            int fl = 1;
+            int s = k - 3;
+            if (s < 0 || s >= n) s = bc_source(k - 3, n, bc, fl);
             long ci = base + s * sAX;
 #pragma unroll
             for (int v = 0; v < 10; ++v) {
@@ -150,10 +184,18 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
             r0f[0] = r0f[1]; r0f[1] = face4(b0[0], b0[1], b0[2], b0[3]);
             p0f[0] = p0f[1]; p0f[1] = face4(b1[0], b1[1], b1[2], b1[3]);
         }
-        // ---- (3) limited slope of cell k-1
+        // ---- (3) limited slope and second difference of cell k-1; the
+        //          limited-slope face value at (k-2)+1/2
         if (k >= -2) {
 #pragma unroll
-            for (int vv = 0; vv < 5; ++vv) { sm[0][vv] = sm[1][vv]; sm[1][vv] = sm[2][vv]; sm[2][vv] = limited_slope(q[2][vv], q[3][vv], q[4][vv]); }
+            for (int vv = 0; vv < 5; ++vv) {
+                sm[0][vv] = sm[1][vv]; sm[1][vv] = sm[2][vv];
+                sm[2][vv] = limited_slope(q[2][vv], q[3][vv], q[4][vv]);
+                d2[0][vv] = d2[1][vv]; d2[1][vv] = d2[2][vv];
+                d2[2][vv] = (q[2][vv] + q[4][vv]) - T(2) * q[3][vv];
+                flm[0][vv] = flm[1][vv];
+                flm[1][vv] = face_limited(q[2][vv], q[3][vv], sm[1][vv], sm[2][vv]);
+            }
         }
         if (k < 0) continue;
         // ---- (4) parabolas of cell k-2, constrained only where the 5-cell
@@ -165,101 +207,23 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
             T qL[5], qR[5], dq[5], q6[5];
 #pragma unroll
             for (int vv = 0; vv < 5; ++vv) {
-                T ws = g.smooth_detect == 1 ? smooth_weight(q[0][vv], q[1][vv], q[2][vv], q[3][vv], q[4][vv])
-                                            : T(g.smooth_detect == 2 ? 1 : 0);
-                T l = qf[0][vv], r = qf[1][vv];
-                if (ws < T(1)) {
-                    T lc = face_limited(q[1][vv], q[2][vv], sm[0][vv], sm[1][vv]);
-                    T rc = face_limited(q[2][vv], q[3][vv], sm[1][vv], sm[2][vv]);
-                    constrain(q[2][vv], lc, rc);
-                    if (ws > T(0)) { lc = lc + ws * (l - lc); rc = rc + ws * (r - rc); }
-                    l = lc; r = rc;
-                    if (interior) ++c_uns;
-                }
+                T l, r;
+                bool con = parabola(g.smooth_detect, q[2][vv], qf[0][vv], qf[1][vv], flm[0][vv], flm[1][vv],
+                                    d2[0][vv], d2[1][vv], d2[2][vv], l, r);
+                if (con && interior) ++c_uns;
                 qL[vv] = l; qR[vv] = r;
                 dq[vv] = r - l;
                 q6[vv] = T(6) * (q[2][vv] - T(0.5) * (l + r));
             }
-            const T rj = rr[0], cj = cr[0], uj = q[2][1], c2 = cj * cj;
-            const T lm = uj - cj, l0 = uj, lp = uj + cj;
-            const T rc2 = rj / (T(2) * cj), cr_ = cj / rj, i2c2 = T(1) / (T(2) * c2), ic2 = T(1) / c2;
-            {   // right face: waves moving right
-                T y = tmax(lp, T(0)) * nu;
-                T ref[5];
-#pragma unroll
-                for (int vv = 0; vv < 5; ++vv) ref[vv] = avg_right(qR[vv], dq[vv], q6[vv], y);
-                T bz = T(0), bm = T(0);
-                if (l0 > T(0)) {
-                    T y0 = l0 * nu;
-                    bz = (ref[0] - avg_right(qR[0], dq[0], q6[0], y0)) - (ref[4] - avg_right(qR[4], dq[4], q6[4], y0)) * ic2;
-                }
-                if (lm > T(0)) {
-                    T ym = lm * nu;
-                    T du = ref[1] - avg_right(qR[1], dq[1], q6[1], ym);
-                    T dp = ref[4] - avg_right(qR[4], dq[4], q6[4], ym);
-                    bm = dp * i2c2 - rc2 * du;
-                }
-                T yv = tmax(l0, T(0)) * nu;
-                TL.r = ref[0] - bz - bm;
-                TL.u = ref[1] + bm * cr_;
-                TL.v = avg_right(qR[2], dq[2], q6[2], yv);
-                TL.w = avg_right(qR[3], dq[3], q6[3], yv);
-                TL.p = ref[4] - bm * c2;
-            }
-            {   // left face: waves moving left
-                T y = tmax(-lm, T(0)) * nu;
-                T ref[5];
-#pragma unroll
-                for (int vv = 0; vv < 5; ++vv) ref[vv] = avg_left(qL[vv], dq[vv], q6[vv], y);
-                T bz = T(0), bp = T(0);
-                if (l0 < T(0)) {
-                    T y0 = -l0 * nu;
-                    bz = (ref[0] - avg_left(qL[0], dq[0], q6[0], y0)) - (ref[4] - avg_left(qL[4], dq[4], q6[4], y0)) * ic2;
-                }
-                if (lp < T(0)) {
-                    T yp = -lp * nu;
-                    T du = ref[1] - avg_left(qL[1], dq[1], q6[1], yp);
-                    T dp = ref[4] - avg_left(qL[4], dq[4], q6[4], yp);
-                    bp = dp * i2c2 + rc2 * du;
-                }
-                T yv = tmax(-l0, T(0)) * nu;
-                TR.r = ref[0] - bz - bp;
-                TR.u = ref[1] - bp * cr_;
-                TR.v = avg_left(qL[2], dq[2], q6[2], yv);
-                TR.w = avg_left(qL[3], dq[3], q6[3], yv);
-                TR.p = ref[4] - bp * c2;
-            }
-            // half-step sources: gravity on rho' (momentum), base advection
-            T su = hdt * (q[2][0] * gr[1] / rj);
-            T sr = hdt * (uj * (r0f[1] - r0f[0]) * rdx);
-            T sp = hdt * (uj * (p0f[1] - p0f[0]) * rdx);
-            TL.u += su; TR.u += su;
-            TL.r -= sr; TR.r -= sr;
-            TL.p -= sp; TR.p -= sp;
+            trace_cell(qL, qR, dq, q6, rr[0], cr[0], q[2][1], q[2][0], gr[1], r0f[0], r0f[1], p0f[0],
+                       p0f[1], nu, hdt, rdx, TL, TR);
         }
         // ---- (5) Riemann problem and fluxes at face (k-3)+1/2
         T F[5] = { T(0), T(0), T(0), T(0), T(0) };
         T sg = T(0);
         if (k >= 1) {
-            St<T> Ls = TLp, Rs = TR;
-            const bool sa = sol[1], sb = sol[2];
-            if (sa && sb) {
-                for (int vv = 0; vv < 5; ++vv) F[vv] = T(0);
-            } else {
-                if (sb) { Rs = Ls; Rs.u = -Ls.u; }          // wall: mirror the fluid side (Sec. 3)
-                if (sa) { Ls = Rs; Ls.u = -Rs.u; }
-                bool cnt;
-                St<T> f = Solver<T>::solve(Ls, Rs, r0f[0], p0f[0], gam, cnt);
-                if (cnt && k - 3 >= -1 && k - 3 < n) ++c_rie;
-                T rf = r0f[0] + f.r;
-                T Fr = rf * f.u;
-                F[0] = Fr;
-                F[1] = Fr * f.u + f.p;
-                F[2] = Fr * f.v;
-                F[3] = Fr * f.w;
-                F[4] = f.u * (gfac * (p0f[0] + f.p) + T(0.5) * rf * ((f.u * f.u + f.v * f.v) + f.w * f.w));
-                sg = f.u * nu;
-            }
+            bool cnt = face_flux(TLp, TR, sol[1], sol[2], r0f[0], p0f[0], gam, gfac, nu, F, sg);
+            if (cnt && k - 3 >= -1 && k - 3 < n) ++c_rie;
         }
         TLp = TL;
         // ---- (6) conservative update of cell k-3 (written one step later)
@@ -269,12 +233,7 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
             if (sol[1]) {
                 for (int vv = 0; vv < 5; ++vv) hn[vv] = cu[0][vv];
             } else {
-                T rn = cu[0][0] - nu * (F[0] - Fp[0]);
-                hn[0] = rn;
-                hn[1] = cu[0][1] - nu * (F[1] - Fp[1]) + dt * gr[0] * (T(0.5) * (cu[0][0] + rn));
-                hn[2] = cu[0][2] - nu * (F[2] - Fp[2]);
-                hn[3] = cu[0][3] - nu * (F[3] - Fp[3]);
-                hn[4] = cu[0][4] - nu * (F[4] - Fp[4]) + dt * gr[0] * (T(0.5) * (Fp[0] + F[0]));
+                hydro_update(cu[0], Fp, F, nu, dt, gr[0], hn);
             }
         }
         // ---- (7) PPB: donor k-3, slab at face (k-4)+1/2, update cell k-4
@@ -304,8 +263,6 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
                 if (cw >= 0 && cw < n) {
                     long ci = base + cw * sAX;
                     T o[10];
-                    double xs[3] = { xt[0], xt[1], xt[2] };
-                    xs[AX] = centre(g, AX, cw);
                     const bool solid_w = sol[0];
                     if (solid_w) {
 #pragma unroll
@@ -314,7 +271,11 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
                         ppb_update(pqp, sg1 - sg2, T(0.5) * (sg2 + sg1), Gp, G, o);
                     }
                     T e = hyd[4];
-                    if (a.heat && !solid_w) e = T((double)e + heating(g, xs[0], xs[1], xs[2]) * dt64);
+                    if (a.heat && !solid_w) {
+                        T xd = ox + (T(cw) + T(0.5)) * dxT;
+                        T zc = AX == 2 ? xd : T(xt[2]);
+                        e = e + heating<T>(g, zc, rtt + xd * xd) * dt;
+                    }
                     a.out[RHO * nc + ci] = hyd[0];
                     a.out[(MX + AX) * nc + ci] = hyd[1];
                     a.out[(MX + AI::t1) * nc + ci] = hyd[2];
@@ -336,16 +297,23 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
     }
 }
 
+// Marching kernel: each wave covers 64 pencils (lanes across x for the y
+// and z passes, across y for the x pass); a block holds blockDim/64 waves
+// on consecutive rows of the other transverse axis.
 template <typename T, int AX>
-__global__ __launch_bounds__(64)
-void sweep_kernel(Geom g, SweepArgs<T> a)
+__global__ __launch_bounds__(256)
+void sweep_kernel(BatchArgs<T> b)
 {
-    // lanes run across x for the y and z passes, across y for the x pass
+    const BlockMap m = b.map[blockIdx.x];
+    const Brick &B = b.bricks[m.brick];
+    const Geom g = B.g;
+    const SweepArgs<T> a = brick_args(b, B);
     const int ca = (AX == 0) ? 1 : 0;
     const int cb = 3 - AX - ca;
+    const int waves = blockDim.x >> 6;
     const int nblk_a = (g.n[ca] + 63) / 64;
-    const int la = (blockIdx.x % nblk_a) * 64 + threadIdx.x;
-    const int lb = blockIdx.x / nblk_a;
+    const int la = (m.local % nblk_a) * 64 + (threadIdx.x & 63);
+    const int lb = (m.local / nblk_a) * waves + (threadIdx.x >> 6);
     unsigned long long c_lim = 0, c_uns = 0, c_rie = 0;
     if (la < g.n[ca] && lb < g.n[cb]) march<T, AX>(g, a, la, lb, c_lim, c_uns, c_rie);
     // event counters: one atomic per wave and counter
@@ -362,29 +330,257 @@ void sweep_kernel(Geom g, SweepArgs<T> a)
     }
 }
 
+// ---------------------------------------------------------------------
+// x pass with lanes along x.  Marching along x with lanes across y would
+// make every load touch 64 separate cache lines; instead one wave holds 64
+// consecutive cells of one x-pencil (cells x0-4 .. x0+59), every load and
+// store of a field is one coalesced 256-byte row, neighbours come from wave
+// shuffles, and the wave finishes the middle 56 cells, whose 4-cell
+// dependency cone (Sec. 4) lies inside the wave.
+// ---------------------------------------------------------------------
+
+constexpr int kXOut = 56;
+
 template <typename T>
-hipError_t launch_sweep(const Geom &g, int axis, const T *in, T *out, const T *rho0, const T *p0,
-                        const double *dtp, unsigned long long *counters, int heat, hipStream_t st)
+__device__ __forceinline__ T lane_sh(T v, int lane, int d)
 {
-    SweepArgs<T> a{in, out, rho0, p0, dtp, counters, (long)g.n[0] * g.n[1] * g.n[2], heat};
+    return __shfl(v, (lane + d) & 63, 64);
+}
+
+template <typename T>
+__device__ __forceinline__ St<T> lane_sh(const St<T> &v, int lane, int d)
+{
+    return St<T>{lane_sh(v.r, lane, d), lane_sh(v.u, lane, d), lane_sh(v.v, lane, d),
+                 lane_sh(v.w, lane, d), lane_sh(v.p, lane, d)};
+}
+
+template <typename T>
+__global__ __launch_bounds__(256)
+void sweep_x_kernel(BatchArgs<T> b)
+{
+    using AI = AxisInfo<0>;
+    const BlockMap m = b.map[blockIdx.x];
+    const Brick &B = b.bricks[m.brick];
+    const Geom g = B.g;
+    const SweepArgs<T> a = brick_args(b, B);
+    const int lane = threadIdx.x & 63;
+    const long wave = (long)m.local * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int nseg = (nx + kXOut - 1) / kXOut;
+    if (wave >= (long)nseg * ny * nz) return;          // whole waves only
+    const int seg = (int)(wave % nseg);
+    const long pen = wave / nseg;
+    const int y = (int)(pen % ny), z = (int)(pen / ny);
+    const int i = seg * kXOut - NG + lane;             // this lane's cell along x
+    const long nc = a.ncell;
+    const long base = ((long)z * ny + y) * nx;
+    const double xt[3] = { 0.0, centre(g, 1, y), centre(g, 2, z) };
+    const T xt1 = T(xt[1]), xt2 = T(xt[2]);
+    const T rtt = xt1 * xt1 + xt2 * xt2;
+    int flo, fhi;
+    fluid_interval(g, 0, xt, flo, fhi);
+    const double dt64 = *a.dtp;
+    const T dt = T(dt64), nu = T(dt64 / g.dx), hdt = T(0.5 * dt64), rdx = T(1.0 / g.dx);
+    const T gam = T(g.gamma), gm1 = T(g.gamma - 1.0), gfac = T(g.gamma / (g.gamma - 1.0));
+    const T *in = a.in;
+
+    // (1) load this lane's cell, BC-mapped
+    int fl = 1;
+    int s = i;
+    if (i < 0 || i >= nx) s = bc_source(i, nx, g.bc[0], fl);
+    const long ci = base + s;
+    T cu[5];
+    cu[0] = in[RHO * nc + ci];
+    cu[1] = T(fl) * in[MX * nc + ci];
+    cu[2] = in[MY * nc + ci];
+    cu[3] = in[MZ * nc + ci];
+    cu[4] = in[EN * nc + ci];
+    const T r0 = a.rho0[ci], pb = a.p0[ci];
+    T pq[10];
+#pragma unroll
+    for (int v = 0; v < 10; ++v) {
+        T val = in[AI::ppb(v) * nc + ci];
+        pq[v] = AI::odd(v) ? T(fl) * val : val;
+    }
+    const T xd = T(g.origin[0]) + (T(s) + T(0.5)) * T(g.dx);
+    const T gv = T(fl) * gravity<T>(g, 0, xd, rtt + xd * xd);
+    const bool so = s < flo || s > fhi;
+    const T rho = r0 + cu[0];
+    const T ir = T(1) / rho;
+    T q[5];
+    q[0] = cu[0];
+    q[1] = cu[1] * ir;
+    q[2] = cu[2] * ir;
+    q[3] = cu[3] * ir;
+    q[4] = gm1 * (cu[4] - T(0.5) * (cu[1] * q[1] + cu[2] * q[2] + cu[3] * q[3]));
+    const T c = sqrt(gam * (pb + q[4]) * ir);
+
+    // (2) face values at i+1/2, second differences, limited slopes
+    T qf[5], d2[5], sm[5], flm[5];
+    T qm1[5], qp1[5];
+#pragma unroll
+    for (int vv = 0; vv < 5; ++vv) {
+        qm1[vv] = lane_sh(q[vv], lane, -1);
+        qp1[vv] = lane_sh(q[vv], lane, 1);
+        T qp2 = lane_sh(q[vv], lane, 2);
+        qf[vv] = face4(qm1[vv], q[vv], qp1[vv], qp2);
+        d2[vv] = (qm1[vv] + qp1[vv]) - T(2) * q[vv];
+        sm[vv] = limited_slope(qm1[vv], q[vv], qp1[vv]);
+    }
+    T r0f, p0f;
+    {
+        T rm = lane_sh(r0, lane, -1), rp = lane_sh(r0, lane, 1), rp2 = lane_sh(r0, lane, 2);
+        T pm = lane_sh(pb, lane, -1), pp = lane_sh(pb, lane, 1), pp2 = lane_sh(pb, lane, 2);
+        r0f = face4(rm, r0, rp, rp2);
+        p0f = face4(pm, pb, pp, pp2);
+    }
+#pragma unroll
+    for (int vv = 0; vv < 5; ++vv) flm[vv] = face_limited(q[vv], qp1[vv], sm[vv], lane_sh(sm[vv], lane, 1));
+
+    // (3) parabolas of cell i and tracing
+    const bool own = lane >= NG && lane < NG + kXOut && i < nx;
+    unsigned long long c_lim = 0, c_uns = 0, c_rie = 0;
+    T qL[5], qR[5], dqv[5], q6[5];
+#pragma unroll
+    for (int vv = 0; vv < 5; ++vv) {
+        T l, r;
+        bool con = parabola(g.smooth_detect, q[vv], lane_sh(qf[vv], lane, -1), qf[vv],
+                            lane_sh(flm[vv], lane, -1), flm[vv], lane_sh(d2[vv], lane, -1), d2[vv],
+                            lane_sh(d2[vv], lane, 1), l, r);
+        if (con && own) ++c_uns;
+        qL[vv] = l; qR[vv] = r;
+        dqv[vv] = r - l;
+        q6[vv] = T(6) * (q[vv] - T(0.5) * (l + r));
+    }
+    St<T> TL, TR;
+    const T r0fL = lane_sh(r0f, lane, -1), p0fL = lane_sh(p0f, lane, -1);
+    trace_cell(qL, qR, dqv, q6, rho, c, q[1], q[0], gv, r0fL, r0f, p0fL, p0f, nu, hdt, rdx, TL, TR);
+
+    // (4) Riemann problem and fluxes at face i+1/2
+    T F[5], sg;
+    {
+        St<T> Rs = lane_sh(TR, lane, 1);
+        bool sb = lane_sh((int)so, lane, 1) != 0;
+        bool cnt = face_flux(TL, Rs, so, sb, r0f, p0f, gam, gfac, nu, F, sg);
+        bool own_face = (own && i >= 0) || (seg == 0 && lane == NG - 1);
+        if (cnt && own_face) ++c_rie;
+    }
+    T Fl[5];
+#pragma unroll
+    for (int vv = 0; vv < 5; ++vv) Fl[vv] = lane_sh(F[vv], lane, -1);
+    const T sgl = lane_sh(sg, lane, -1);
+
+    // (5) PPB: limit this cell's profile, slab at face i+1/2, update
+    T L = T(1) + (sg - sgl);
+    T pql[10];
+#pragma unroll
+    for (int v = 0; v < 10; ++v) pql[v] = pq[v];
+    {
+        bool hit = fv_limit(pq[0], pql[1], pql[2]);
+        if (hit && own && !so) ++c_lim;
+    }
+    T G[10];
+    {
+        T dn[10];
+#pragma unroll
+        for (int v = 0; v < 10; ++v) dn[v] = lane_sh(pql[v], lane, 1);
+        const T Ln = lane_sh(L, lane, 1);
+        if (sg > T(0)) {
+            slab(pql, sg, L, G);
+        } else if (sg < T(0)) {
+#pragma unroll
+            for (int v = 0; v < 10; ++v) dn[v] = (v == 1 || v == 4 || v == 6) ? -dn[v] : dn[v];
+            slab(dn, sg, Ln, G);
+        } else {
+#pragma unroll
+            for (int v = 0; v < 10; ++v) G[v] = T(0);
+        }
+    }
+    T Gl[10];
+#pragma unroll
+    for (int v = 0; v < 10; ++v) Gl[v] = lane_sh(G[v], lane, -1);
+
+    if (own) {
+        T hn[5], o[10];
+        if (so) {
+#pragma unroll
+            for (int vv = 0; vv < 5; ++vv) hn[vv] = cu[vv];
+#pragma unroll
+            for (int v = 0; v < 10; ++v) o[v] = pq[v];
+        } else {
+            hydro_update(cu, Fl, F, nu, dt, gv, hn);
+            ppb_update(pql, sg - sgl, T(0.5) * (sgl + sg), Gl, G, o);
+            if (a.heat) {
+                T zc = T(xt[2]);
+                hn[4] = hn[4] + heating<T>(g, zc, rtt + xd * xd) * dt;
+            }
+        }
+        const long co = base + i;
+        a.out[RHO * nc + co] = hn[0];
+        a.out[MX * nc + co] = hn[1];
+        a.out[MY * nc + co] = hn[2];
+        a.out[MZ * nc + co] = hn[3];
+        a.out[EN * nc + co] = hn[4];
+#pragma unroll
+        for (int v = 0; v < 10; ++v) a.out[AI::ppb(v) * nc + co] = o[v];
+    }
+    unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
+    for (int off = 32; off > 0; off >>= 1) {
+        s0 += __shfl_down(s0, off);
+        s1 += __shfl_down(s1, off);
+        s2 += __shfl_down(s2, off);
+    }
+    if (lane == 0) {
+        if (s0) atomicAdd(&a.counters[0], s0);
+        if (s1) atomicAdd(&a.counters[1], s1);
+        if (s2) atomicAdd(&a.counters[2], s2);
+    }
+}
+
+// The x pass uses the lanes-along-x kernel unless PPMB_X_MARCH=1 selects
+// the marching kernel (kept for comparison; both compute the same pass).
+static bool x_lanes_enabled()
+{
+    const char *e = getenv("PPMB_X_MARCH");
+    return !(e && e[0] == '1');
+}
+
+int pass_blocks(const Geom &g, int axis, const PassShape &sh)
+{
+    if (axis == 0 && x_lanes_enabled()) {
+        const long nw = (long)((g.n[0] + kXOut - 1) / kXOut) * g.n[1] * g.n[2];
+        return (int)((nw + sh.x_waves - 1) / sh.x_waves);
+    }
     const int ca = (axis == 0) ? 1 : 0;
     const int cb = 3 - axis - ca;
-    const long nblk = (long)((g.n[ca] + 63) / 64) * g.n[cb];
-    if (nblk <= 0 || nblk > 0x7fffffffL) return hipErrorInvalidValue;
-    dim3 grid((unsigned)nblk), block(64);
+    return ((g.n[ca] + 63) / 64) * ((g.n[cb] + sh.march_waves - 1) / sh.march_waves);
+}
+
+template <typename T>
+hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, const BlockMap *map,
+                        int nblocks, const T *in, T *out, const T *base, const double *dt,
+                        unsigned long long *counters, int heat, hipStream_t st)
+{
+    if (nblocks <= 0) return hipErrorInvalidValue;
+    BatchArgs<T> a{bricks, map, in, out, base, dt, counters, heat};
+    if (axis == 0 && x_lanes_enabled()) {
+        hipLaunchKernelGGL((sweep_x_kernel<T>), dim3(nblocks), dim3(64 * sh.x_waves), 0, st, a);
+        return hipGetLastError();
+    }
+    dim3 grid(nblocks), block(64 * sh.march_waves);
     switch (axis) {
-    case 0: hipLaunchKernelGGL((sweep_kernel<T, 0>), grid, block, 0, st, g, a); break;
-    case 1: hipLaunchKernelGGL((sweep_kernel<T, 1>), grid, block, 0, st, g, a); break;
-    default: hipLaunchKernelGGL((sweep_kernel<T, 2>), grid, block, 0, st, g, a); break;
+    case 0: hipLaunchKernelGGL((sweep_kernel<T, 0>), grid, block, 0, st, a); break;
+    case 1: hipLaunchKernelGGL((sweep_kernel<T, 1>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((sweep_kernel<T, 2>), grid, block, 0, st, a); break;
     }
     return hipGetLastError();
 }
 
-template hipError_t launch_sweep<float>(const Geom &, int, const float *, float *, const float *,
-                                        const float *, const double *, unsigned long long *, int,
-                                        hipStream_t);
-template hipError_t launch_sweep<double>(const Geom &, int, const double *, double *,
-                                         const double *, const double *, const double *,
+template hipError_t launch_sweep<float>(int, const PassShape &, const Brick *, const BlockMap *, int,
+                                        const float *, float *, const float *, const double *,
+                                        unsigned long long *, int, hipStream_t);
+template hipError_t launch_sweep<double>(int, const PassShape &, const Brick *, const BlockMap *, int,
+                                         const double *, double *, const double *, const double *,
                                          unsigned long long *, int, hipStream_t);
 
 }  // namespace ppmb

@@ -24,8 +24,12 @@ EXPORTS = ("ppmb_create", "ppmb_destroy", "ppmb_state_bytes", "ppmb_bind_state",
            "ppmb_set_state_device", "ppmb_get_state", "ppmb_get_conserved",
            "ppmb_set_conserved", "ppmb_compute_dt", "ppmb_step", "ppmb_step_auto",
            "ppmb_last_dt", "ppmb_pass", "ppmb_get_nstep", "ppmb_set_nstep",
-           "ppmb_reduce_totals", "ppmb_counters", "ppmb_synchronize", "ppmb_status_string",
-           "ppmb_last_error")
+           "ppmb_reduce_totals", "ppmb_counters", "ppmb_profile_enable", "ppmb_profile_read",
+           "ppmb_synchronize", "ppmb_status_string", "ppmb_last_error", "ppmb_batch_create",
+           "ppmb_brick_count", "ppmb_brick_set_base_state", "ppmb_brick_get_base",
+           "ppmb_brick_set_state", "ppmb_brick_get_state", "ppmb_brick_get_conserved",
+           "ppmb_brick_totals", "ppmb_brick_last_dt", "ppmb_batch_step", "ppmb_set_pass_shape",
+           "ppmb_get_pass_shape", "ppmb_autotune")
 
 
 class PPMBError(RuntimeError):
@@ -77,7 +81,22 @@ def load():
         "ppmb_set_nstep": [p, ctypes.c_long],
         "ppmb_reduce_totals": [p, _D],
         "ppmb_counters": [p, ctypes.POINTER(ctypes.c_ulonglong)],
+        "ppmb_profile_enable": [p, i],
+        "ppmb_profile_read": [p, _D, ctypes.POINTER(ctypes.c_long)],
         "ppmb_synchronize": [p],
+        "ppmb_batch_create": [i, ctypes.POINTER(Grid), i, p, ctypes.POINTER(p)],
+        "ppmb_brick_count": [p, ctypes.POINTER(i)],
+        "ppmb_brick_set_base_state": [p, i, i, _D],
+        "ppmb_brick_get_base": [p, i, _D, _D],
+        "ppmb_brick_set_state": [p, i, _DD],
+        "ppmb_brick_get_state": [p, i, _DD],
+        "ppmb_brick_get_conserved": [p, i, _DD],
+        "ppmb_brick_totals": [p, i, _D],
+        "ppmb_brick_last_dt": [p, i, _D],
+        "ppmb_batch_step": [p, d, i, i],
+        "ppmb_set_pass_shape": [p, i, i],
+        "ppmb_get_pass_shape": [p, ctypes.POINTER(i), ctypes.POINTER(i)],
+        "ppmb_autotune": [p, d, i, ctypes.c_char_p, ctypes.POINTER(i)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -246,6 +265,16 @@ class Sim:
         self._check(self.L.ppmb_counters(self.h, out))
         return [int(v) for v in out]
 
+    def profile(self, enable=True):
+        self._check(self.L.ppmb_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """Per axis: (number of timed pass kernels, summed milliseconds)."""
+        ms = (ctypes.c_double * 3)()
+        cnt = (ctypes.c_long * 3)()
+        self._check(self.L.ppmb_profile_read(self.h, ms, cnt))
+        return [int(v) for v in cnt], [float(v) for v in ms]
+
     def synchronize(self):
         self._check(self.L.ppmb_synchronize(self.h))
 
@@ -256,3 +285,89 @@ class Sim:
             if b.data_ptr() == p.value:
                 return b
         raise PPMBError("current state is not one of the bound buffers")
+
+
+class Batch:
+    """Many independent bricks advanced together (each with its own grid,
+    boundaries, base state and CFL dt).  The library owns both state arenas;
+    `stream` must be a non-default torch stream for graph replay (mode 1)."""
+
+    def __init__(self, params_list, precision=FP32, device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise PPMBError("no GPU: the PPM+PPB path runs only in the HIP library")
+        self.L = load()
+        self.params = list(params_list)
+        self.precision = precision
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        grids = (Grid * len(self.params))(*[grid_of(p) for p in self.params])
+        h = ctypes.c_void_p()
+        st = self.L.ppmb_batch_create(len(self.params), grids, precision,
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise PPMBError(f"ppmb_batch_create failed: {st}")
+        self.h = h
+        for b, p in enumerate(self.params):
+            arr = np.ascontiguousarray(getattr(p, "base", (0.0,) * 6), dtype=np.float64)
+            self._check(self.L.ppmb_brick_set_base_state(self.h, b, int(getattr(p, "base_kind", 0)),
+                                                         arr.ctypes.data_as(_D)))
+
+    _check = Sim._check
+    close = Sim.close
+    __del__ = Sim.__del__
+
+    def _shape(self, b):
+        n = self.params[b].n
+        return (n[2], n[1], n[0])
+
+    def set_state(self, b, state):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in state]
+        self._check(self.L.ppmb_brick_set_state(self.h, int(b), _ptrs(arrs)))
+
+    def get_state(self, b):
+        out = [np.empty(self._shape(b)) for _ in range(NFIELDS)]
+        self._check(self.L.ppmb_brick_get_state(self.h, int(b), _ptrs(out)))
+        return out
+
+    def get_conserved(self, b):
+        out = [np.empty(self._shape(b)) for _ in range(NFIELDS)]
+        self._check(self.L.ppmb_brick_get_conserved(self.h, int(b), _ptrs(out)))
+        return out
+
+    def totals(self, b):
+        out = np.zeros(8)
+        self._check(self.L.ppmb_brick_totals(self.h, int(b), out.ctypes.data_as(_D)))
+        return out
+
+    def last_dt(self, b):
+        v = ctypes.c_double()
+        self._check(self.L.ppmb_brick_last_dt(self.h, int(b), ctypes.byref(v)))
+        return v.value
+
+    def step(self, cfl, nsteps, mode=0):
+        """mode 0: one launch per stage for all bricks; 1: replayed hipGraph;
+        2: one launch per stage and brick."""
+        self._check(self.L.ppmb_batch_step(self.h, float(cfl), int(nsteps), int(mode)))
+
+    def set_shape(self, march_waves, x_waves):
+        self._check(self.L.ppmb_set_pass_shape(self.h, int(march_waves), int(x_waves)))
+
+    def shape(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        self._check(self.L.ppmb_get_pass_shape(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def autotune(self, cfl, reps=3, cache_path=None):
+        out = (ctypes.c_int * 2)()
+        cp = cache_path.encode() if cache_path else None
+        self._check(self.L.ppmb_autotune(self.h, float(cfl), int(reps), cp, out))
+        return out[0], out[1]
+
+    def counters(self):
+        out = (ctypes.c_ulonglong * 4)()
+        self._check(self.L.ppmb_counters(self.h, out))
+        return [int(v) for v in out]
+
+    def synchronize(self):
+        self._check(self.L.ppmb_synchronize(self.h))

@@ -77,9 +77,14 @@ def test_library_loads_on_gpu():
     ppmb.load()
 
 
+@pytest.mark.parametrize("xshape", ["lanes", "march"])
 @pytest.mark.parametrize("axis", [0, 1, 2])
-@pytest.mark.parametrize("shape", [(20, 24, 28), (67, 5, 9)])
-def test_single_pass_matches_oracle(axis, shape):
+@pytest.mark.parametrize("shape", [(20, 24, 28), (67, 5, 9), (130, 3, 4)])
+def test_single_pass_matches_oracle(axis, shape, xshape, monkeypatch):
+    if xshape == "march" and axis != 0:
+        pytest.skip("the kernel shape choice only exists for the x pass")
+    if xshape == "march":
+        monkeypatch.setenv("PPMB_X_MARCH", "1")
     # one pass on a ragged grid (not a multiple of the 64-lane tile)
     P = pr.config1(n=8).params
     P = dataclasses.replace(P, n=shape, dx=1.0 / max(shape))
