@@ -508,22 +508,37 @@ struct Staging {
     ~Staging() { if (p) hipFree(p); }
 };
 
+// Host transfers go through an FP64 staging buffer of at most kChunk cells
+// per field, so that the largest grids need no full-size staging copy.
+static const long kChunk = 1L << 24;
+
 ppmb_status ppmb_brick_set_state(ppmb_ctx *c, int brick, const double *const host_prim[15])
 {
     if (!c || !host_prim) return PPMB_ERR_INVALID;
     TRY(check_brick(c, brick));
-    const long n = c->hb[brick].ncell;
-    Staging st;
-    if (hipMalloc(&st.p, sizeof(double) * NF * n) != hipSuccess)
-        return fail(c, PPMB_ERR_NOMEM, "set_state: staging");
-    const double *dev[NF];
-    for (int q = 0; q < NF; ++q) {
+    for (int q = 0; q < NF; ++q)
         if (!host_prim[q]) return fail(c, PPMB_ERR_INVALID, "set_state: null field");
-        HIPCHK(c, hipMemcpyAsync(st.p + q * n, host_prim[q], sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
-        dev[q] = st.p + q * n;
+    const Brick &B = c->hb[brick];
+    const long n = B.ncell, ch = n < kChunk ? n : kChunk;
+    Staging st;
+    if (hipMalloc(&st.p, sizeof(double) * NF * ch) != hipSuccess)
+        return fail(c, PPMB_ERR_NOMEM, "set_state: staging");
+    for (long c0 = 0; c0 < n; c0 += ch) {
+        const long m = (n - c0) < ch ? (n - c0) : ch;
+        const double *dev[NF];
+        for (int q = 0; q < NF; ++q) {
+            HIPCHK(c, hipMemcpyAsync(st.p + q * ch, host_prim[q] + c0, sizeof(double) * m,
+                                     hipMemcpyHostToDevice, c->stream));
+            dev[q] = st.p + q * ch;
+        }
+        if (c->prec == PPMB_FP64)
+            HIPCHK(c, launch_prim_to_cons_range<double>(B.g, dev, c->base64 + B.boff + c0,
+                                                        arena<double>(c, c->cur) + B.off + c0, m, n, c->stream));
+        else
+            HIPCHK(c, launch_prim_to_cons_range<float>(B.g, dev, c->base64 + B.boff + c0,
+                                                       arena<float>(c, c->cur) + B.off + c0, m, n, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
     }
-    TRY(set_state_dev(c, brick, dev));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
     return PPMB_OK;
 }
 
@@ -536,20 +551,26 @@ ppmb_status ppmb_brick_get_state(ppmb_ctx *c, int brick, double *const host_prim
 {
     if (!c || !host_prim) return PPMB_ERR_INVALID;
     TRY(check_brick(c, brick));
-    const Brick &B = c->hb[brick];
-    const long n = B.ncell;
-    Staging st;
-    if (hipMalloc(&st.p, sizeof(double) * NF * n) != hipSuccess)
-        return fail(c, PPMB_ERR_NOMEM, "get_state: staging");
-    if (c->prec == PPMB_FP64)
-        HIPCHK(c, launch_cons_to_prim<double>(B.g, arena<double>(c, c->cur) + B.off, c->base64 + B.boff, st.p, c->stream));
-    else
-        HIPCHK(c, launch_cons_to_prim<float>(B.g, arena<float>(c, c->cur) + B.off, c->base64 + B.boff, st.p, c->stream));
-    for (int q = 0; q < NF; ++q) {
+    for (int q = 0; q < NF; ++q)
         if (!host_prim[q]) return fail(c, PPMB_ERR_INVALID, "get_state: null field");
-        HIPCHK(c, hipMemcpyAsync(host_prim[q], st.p + q * n, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    const Brick &B = c->hb[brick];
+    const long n = B.ncell, ch = n < kChunk ? n : kChunk;
+    Staging st;
+    if (hipMalloc(&st.p, sizeof(double) * NF * ch) != hipSuccess)
+        return fail(c, PPMB_ERR_NOMEM, "get_state: staging");
+    for (long c0 = 0; c0 < n; c0 += ch) {
+        const long m = (n - c0) < ch ? (n - c0) : ch;
+        if (c->prec == PPMB_FP64)
+            HIPCHK(c, launch_cons_to_prim_range<double>(B.g, arena<double>(c, c->cur) + B.off + c0,
+                                                        c->base64 + B.boff + c0, st.p, m, n, ch, c->stream));
+        else
+            HIPCHK(c, launch_cons_to_prim_range<float>(B.g, arena<float>(c, c->cur) + B.off + c0,
+                                                       c->base64 + B.boff + c0, st.p, m, n, ch, c->stream));
+        for (int q = 0; q < NF; ++q)
+            HIPCHK(c, hipMemcpyAsync(host_prim[q] + c0, st.p + q * ch, sizeof(double) * m,
+                                     hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
     }
-    HIPCHK(c, hipStreamSynchronize(c->stream));
     return PPMB_OK;
 }
 

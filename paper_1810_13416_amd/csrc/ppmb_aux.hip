@@ -177,6 +177,60 @@ __global__ void cons_to_prim_kernel(long nc, double gm1, const T *S, const doubl
     }
 }
 
+template <typename T>
+__global__ void prim_to_cons_range_kernel(long m, long stride, double gm1, PrimPtrs P,
+                                          const double *rho0, T *S)
+{
+    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < m; c += (long)gridDim.x * blockDim.x) {
+        double rho = rho0[c] + P.p[0][c];
+        double u = P.p[1][c], v = P.p[2][c], w = P.p[3][c];
+        S[RHO * stride + c] = T(P.p[0][c]);
+        S[MX * stride + c] = T(rho * u);
+        S[MY * stride + c] = T(rho * v);
+        S[MZ * stride + c] = T(rho * w);
+        S[EN * stride + c] = T(P.p[4][c] / gm1 + 0.5 * rho * ((u * u + v * v) + w * w));
+        for (int q = 5; q < NF; ++q) S[q * stride + c] = T(P.p[q][c]);
+    }
+}
+
+template <typename T>
+__global__ void cons_to_prim_range_kernel(long m, long stride, long ostride, double gm1, const T *S,
+                                          const double *rho0, double *out)
+{
+    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < m; c += (long)gridDim.x * blockDim.x) {
+        double rp = S[RHO * stride + c], mx = S[MX * stride + c], my = S[MY * stride + c];
+        double mz = S[MZ * stride + c], e = S[EN * stride + c];
+        double rho = rho0[c] + rp;
+        double u = mx / rho, v = my / rho, w = mz / rho;
+        out[0 * ostride + c] = rp;
+        out[1 * ostride + c] = u;
+        out[2 * ostride + c] = v;
+        out[3 * ostride + c] = w;
+        out[4 * ostride + c] = gm1 * (e - 0.5 * (mx * u + my * v + mz * w));
+        for (int q = 5; q < NF; ++q) out[q * ostride + c] = S[q * stride + c];
+    }
+}
+
+template <typename T>
+hipError_t launch_prim_to_cons_range(const Geom &g, const double *const *prim, const double *rho0,
+                                     T *state, long m, long stride, hipStream_t st)
+{
+    PrimPtrs P;
+    for (int q = 0; q < NF; ++q) P.p[q] = prim[q];
+    hipLaunchKernelGGL((prim_to_cons_range_kernel<T>), dim3(4096), dim3(256), 0, st, m, stride,
+                       g.gamma - 1.0, P, rho0, state);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cons_to_prim_range(const Geom &g, const T *state, const double *rho0, double *out,
+                                     long m, long stride, long ostride, hipStream_t st)
+{
+    hipLaunchKernelGGL((cons_to_prim_range_kernel<T>), dim3(4096), dim3(256), 0, st, m, stride, ostride,
+                       g.gamma - 1.0, state, rho0, out);
+    return hipGetLastError();
+}
+
 template <typename A, typename B>
 __global__ void convert_kernel(const A *src, B *dst, long count)
 {
@@ -391,6 +445,10 @@ hipError_t launch_zero_u64(unsigned long long *dst, int count, hipStream_t st)
 }
 
 #define PPMB_INST(T)                                                                              \
+    template hipError_t launch_prim_to_cons_range<T>(const Geom &, const double *const *,           \
+                                                     const double *, T *, long, long, hipStream_t); \
+    template hipError_t launch_cons_to_prim_range<T>(const Geom &, const T *, const double *,        \
+                                                     double *, long, long, long, hipStream_t);     \
     template hipError_t launch_prim_to_cons<T>(const Geom &, const double *const *, const double *, \
                                                T *, hipStream_t);                                 \
     template hipError_t launch_cons_to_prim<T>(const Geom &, const T *, const double *, double *,  \

@@ -56,6 +56,15 @@ hipError_t launch_prim_to_cons(const Geom &g, const double *const *prim, const d
 template <typename T>
 hipError_t launch_cons_to_prim(const Geom &g, const T *state, const double *rho0, double *prim,
                                hipStream_t st);
+// The same on a range of m cells of a brick whose field stride is `stride`:
+// prim[q] / state fields start at the range's first cell; the FP64 staging
+// of cons_to_prim holds field q at out + q * ostride.
+template <typename T>
+hipError_t launch_prim_to_cons_range(const Geom &g, const double *const *prim, const double *rho0,
+                                     T *state, long m, long stride, hipStream_t st);
+template <typename T>
+hipError_t launch_cons_to_prim_range(const Geom &g, const T *state, const double *rho0, double *out,
+                                     long m, long stride, long ostride, hipStream_t st);
 template <typename T>
 hipError_t launch_widen(const T *src, double *dst, long count, hipStream_t st);
 template <typename T>
