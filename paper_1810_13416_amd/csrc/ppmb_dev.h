@@ -29,6 +29,18 @@ struct Geom {
     int    smooth_detect;
 };
 
+// Reciprocal, reciprocal square root and square root.  FP32: the hardware
+// instructions (1 ulp), without the denormal rescaling the compiler wraps
+// around them: no quantity of the pass comes near the FP32 denormal range
+// (densities, pressures and sound speeds are O(1e-3 .. 1e3)).  FP64:
+// correctly rounded.
+__device__ __forceinline__ float trcp(float a) { return __builtin_amdgcn_rcpf(a); }
+__device__ __forceinline__ double trcp(double a) { return 1.0 / a; }
+__device__ __forceinline__ float trsq(float a) { return __builtin_amdgcn_rsqf(a); }
+__device__ __forceinline__ double trsq(double a) { return 1.0 / sqrt(a); }
+__device__ __forceinline__ float tsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+__device__ __forceinline__ double tsqrt(double a) { return sqrt(a); }
+
 // hardware abs / min / max (operand modifiers and single instructions)
 __device__ __forceinline__ float tabs(float a) { return fabsf(a); }
 __device__ __forceinline__ double tabs(double a) { return fabs(a); }
@@ -93,11 +105,11 @@ __device__ __forceinline__ T gravity(const Geom &g, int axis, T xd, T rt2)
 {
     if (g.grav_kind == 1) return T(g.grav[axis]);
     if (g.grav_kind == 2) {
-        T r = sqrt(rt2);
+        T r = tsqrt(rt2);
         T rc = T(g.grav[1]);
-        T h = (r < rc) ? T(1) / rc : (rc * rc) / (rt2 * r);
+        T h = (r < rc) ? T(1.0 / g.grav[1]) : (rc * rc) * trcp(rt2 * r);
         T r1 = T(g.grav[2]), r2 = T(g.grav[3]);
-        T t = r <= r1 ? T(1) : (r >= r2 ? T(0) : (r2 - r) / (r2 - r1));
+        T t = r <= r1 ? T(1) : (r >= r2 ? T(0) : (r2 - r) * T(1.0 / (g.grav[3] - g.grav[2])));
         return -T(g.grav[0]) * xd * h * t;
     }
     return T(0);
@@ -116,8 +128,8 @@ __device__ __forceinline__ T heat_shape(T xi)
 template <typename T>
 __device__ __forceinline__ T heating(const Geom &g, T z, T rt2)
 {
-    if (g.heat_kind == 1) return T(g.heat[0]) * heat_shape((z - T(g.heat[2])) / T(g.heat[1]));
-    if (g.heat_kind == 2) return T(g.heat[0]) * heat_shape(sqrt(rt2) / T(g.heat[1]));
+    if (g.heat_kind == 1) return T(g.heat[0]) * heat_shape((z - T(g.heat[2])) * T(1.0 / g.heat[1]));
+    if (g.heat_kind == 2) return T(g.heat[0]) * heat_shape(tsqrt(rt2) * T(1.0 / g.heat[1]));
     return T(0);
 }
 
@@ -184,7 +196,7 @@ __device__ __forceinline__ T smooth_weight(T q0, T q1, T q2, T q3, T q4)
     T mx = tmax(a0, tmax(a1, a2)), mn = tmin(a0, tmin(a1, a2));
     if (mx <= T(2) * mn) return T(1);
     if (mx >= T(3) * mn) return T(0);
-    return (T(3) * mn - mx) / mn;
+    return (T(3) * mn - mx) * trcp(mn);
 }
 
 // The same judgment from the three second differences themselves.
@@ -198,7 +210,7 @@ __device__ __forceinline__ T smooth_weight_d(T d0, T d1, T d2)
     T mx = tmax(a0, tmax(a1, a2)), mn = tmin(a0, tmin(a1, a2));
     if (mx <= T(2) * mn) return T(1);
     if (mx >= T(3) * mn) return T(0);
-    return (T(3) * mn - mx) / mn;
+    return (T(3) * mn - mx) * trcp(mn);
 }
 
 // van Leer limited slope (CW84 eq. 1.8).
@@ -251,28 +263,62 @@ template <typename T> struct St { T r, u, v, w, p; };
 
 // Newton iterations of the two-shock approximation.  p0f cancels from every
 // pressure difference; the full pressures only set the wave impedances.
-// Stops once the pre-update velocity residual |u*_R - u*_L| is at most
-// tol (cL + cR); returns whether that happened within `maxit` iterations.
+// Written with reciprocals: 1/W from one rsqrt per side, the linearised
+// impedances as 1/Z = (1 + C^2 / W^2) / (2 W), so that an iteration costs
+// two rsqrt and one reciprocal.  Stops once the pre-update velocity residual
+// |u*_R - u*_L| is at most tol (cL + cR); returns whether that happened
+// within `maxit` iterations.  Outputs p'*, u*, 1/W_L, 1/W_R.
 template <typename T>
-__device__ __forceinline__ bool two_shock(const St<T> &L, const St<T> &R, T rL, T rR, T pL, T pR,
-                                          T p0f, T CL, T CR, T gamma, int maxit, T tol,
-                                          T &ps, T &us, T &WL, T &WR)
+struct Face {
+    T rL, rR, irL, irR;   // full densities and their reciprocals
+    T pL, pR, ipL, ipR;   // full pressures and their reciprocals
+    T CL, CR, iCL, iCR;   // Lagrangian sound speeds sqrt(gamma p rho) and reciprocals
+};
+
+template <typename T>
+__device__ __forceinline__ Face<T> face_setup(const St<T> &L, const St<T> &R, T r0f, T p0f, T gamma)
 {
-    const T A = (gamma + T(1)) / (T(2) * gamma);
-    T cs = CL / rL + CR / rR;
-    T pfl = T(1e-10) * tmin(pL, pR) - p0f;
-    ps = (CR * L.p + CL * R.p + CL * CR * (L.u - R.u)) / (CL + CR);
+    Face<T> F;
+    F.rL = r0f + L.r;
+    F.rR = r0f + R.r;
+    F.pL = p0f + L.p;
+    F.pR = p0f + R.p;
+    F.irL = trcp(F.rL);
+    F.irR = trcp(F.rR);
+    F.ipL = trcp(F.pL);
+    F.ipR = trcp(F.pR);
+    T gL = gamma * F.pL * F.rL, gR = gamma * F.pR * F.rR;
+    F.iCL = trsq(gL);
+    F.iCR = trsq(gR);
+    F.CL = gL * F.iCL;
+    F.CR = gR * F.iCR;
+    return F;
+}
+
+template <typename T>
+__device__ __forceinline__ bool two_shock(const St<T> &L, const St<T> &R, const Face<T> &F, T p0f,
+                                          T gamma, int maxit, T tol, T &ps, T &us, T &iWL, T &iWR)
+{
+    const T A = (gamma + T(1)) * trcp(T(2) * gamma);
+    const T cs = F.CL * F.irL + F.CR * F.irR;
+    const T pfl = T(1e-10) * tmin(F.pL, F.pR) - p0f;
+    ps = (F.CR * L.p + F.CL * R.p + F.CL * F.CR * (L.u - R.u)) * trcp(F.CL + F.CR);
     if (ps < pfl) ps = pfl;
+    iWL = F.iCL;
+    iWR = F.iCR;
+    us = T(0.5) * (L.u + R.u);
+    const T CL2 = F.CL * F.CL, CR2 = F.CR * F.CR;
     for (int it = 0; it < maxit; ++it) {
-        WL = CL * sqrt(T(1) + A * (ps - L.p) / pL);
-        WR = CR * sqrt(T(1) + A * (ps - R.p) / pR);
-        T uLs = L.u - (ps - L.p) / WL;
-        T uRs = R.u + (ps - R.p) / WR;
-        T ZL = T(2) * WL * WL * WL / (WL * WL + CL * CL);
-        T ZR = T(2) * WR * WR * WR / (WR * WR + CR * CR);
+        iWL = F.iCL * trsq(T(1) + A * (ps - L.p) * F.ipL);
+        iWR = F.iCR * trsq(T(1) + A * (ps - R.p) * F.ipR);
+        T uLs = L.u - (ps - L.p) * iWL;
+        T uRs = R.u + (ps - R.p) * iWR;
+        T iZL = T(0.5) * iWL * (T(1) + CL2 * iWL * iWL);
+        T iZR = T(0.5) * iWR * (T(1) + CR2 * iWR * iWR);
+        T rden = trcp(iZL + iZR);
         T du = uRs - uLs;
-        us = (ZL * uLs + ZR * uRs) / (ZL + ZR);
-        ps = ps - ZL * ZR * du / (ZL + ZR);
+        us = (uLs * iZR + uRs * iZL) * rden;
+        ps = ps - du * rden;
         if (ps < pfl) ps = pfl;
         if (tabs(du) <= tol * cs) return true;
     }
@@ -280,21 +326,22 @@ __device__ __forceinline__ bool two_shock(const St<T> &L, const St<T> &R, T rL, 
 }
 
 // Sample the face state by the sign of u* and the speed of the wave on
-// that side (CW84 Sec. 2).
+// that side (CW84 Sec. 2); the side is unshocked when that wave has
+// already passed the face: u_s -+ W_s / rho_s of the sign of u*.
 template <typename T>
-__device__ __forceinline__ St<T> sample(const St<T> &L, const St<T> &R, T rL, T rR, T ps, T us,
-                                        T WL, T WR)
+__device__ __forceinline__ St<T> sample(const St<T> &L, const St<T> &R, const Face<T> &F, T ps, T us,
+                                        T iWL, T iWR)
 {
     St<T> f;
     if (us >= T(0)) {
-        if (L.u - WL / rL >= T(0)) return L;
-        T X = rL * (ps - L.p) / (WL * WL);
-        f.r = L.r + rL * X / (T(1) - X);
+        if (L.u * F.rL * iWL >= T(1)) return L;
+        T X = F.rL * (ps - L.p) * (iWL * iWL);
+        f.r = L.r + F.rL * X * trcp(T(1) - X);
         f.u = us; f.v = L.v; f.w = L.w; f.p = ps;
     } else {
-        if (R.u + WR / rR <= T(0)) return R;
-        T X = rR * (ps - R.p) / (WR * WR);
-        f.r = R.r + rR * X / (T(1) - X);
+        if (-R.u * F.rR * iWR >= T(1)) return R;
+        T X = F.rR * (ps - R.p) * (iWR * iWR);
+        f.r = R.r + F.rR * X * trcp(T(1) - X);
         f.u = us; f.v = R.v; f.w = R.w; f.p = ps;
     }
     return f;
@@ -306,11 +353,10 @@ __device__ __forceinline__ St<T> sample(const St<T> &L, const St<T> &R, T rL, T 
 __device__ __forceinline__ St<double> riemann64(const St<double> &L, const St<double> &R,
                                                 double r0f, double p0f, double gamma, bool &bad)
 {
-    double rL = r0f + L.r, rR = r0f + R.r, pL = p0f + L.p, pR = p0f + R.p;
-    double CL = sqrt(gamma * pL * rL), CR = sqrt(gamma * pR * rR);
-    double ps, us, WL = CL, WR = CR;
-    bad = !two_shock<double>(L, R, rL, rR, pL, pR, p0f, CL, CR, gamma, 20, 1e-13, ps, us, WL, WR);
-    return sample<double>(L, R, rL, rR, ps, us, WL, WR);
+    Face<double> F = face_setup<double>(L, R, r0f, p0f, gamma);
+    double ps, us, iWL, iWR;
+    bad = !two_shock<double>(L, R, F, p0f, gamma, 20, 1e-13, ps, us, iWL, iWR);
+    return sample<double>(L, R, F, ps, us, iWL, iWR);
 }
 
 template <typename T> struct Solver;
@@ -327,10 +373,9 @@ template <> struct Solver<float> {
     __device__ static St<float> solve(const St<float> &L, const St<float> &R, float r0f,
                                       float p0f, float gamma, bool &counted)
     {
-        float rL = r0f + L.r, rR = r0f + R.r, pL = p0f + L.p, pR = p0f + R.p;
-        float CL = sqrtf(gamma * pL * rL), CR = sqrtf(gamma * pR * rR);
-        float ps, us, WL = CL, WR = CR;
-        bool ok = two_shock<float>(L, R, rL, rR, pL, pR, p0f, CL, CR, gamma, 2, 1e-5f, ps, us, WL, WR);
+        Face<float> F = face_setup<float>(L, R, r0f, p0f, gamma);
+        float ps, us, iWL, iWR;
+        bool ok = two_shock<float>(L, R, F, p0f, gamma, 2, 1e-5f, ps, us, iWL, iWR);
         counted = false;
         if (!ok) {
             counted = true;
@@ -339,7 +384,7 @@ template <> struct Solver<float> {
             St<double> f = riemann64(Ld, Rd, (double)r0f, (double)p0f, (double)gamma, bad);
             return St<float>{(float)f.r, (float)f.u, (float)f.v, (float)f.w, (float)f.p};
         }
-        return sample<float>(L, R, rL, rR, ps, us, WL, WR);
+        return sample<float>(L, R, F, ps, us, iWL, iWR);
     }
 };
 
@@ -356,14 +401,12 @@ __device__ __forceinline__ bool fv_limit(T a0, T &a1, T &a2)
     T gm = a0 - T(0.5) * a1 + a2 * T(1.0 / 6.0);
     T gp = a0 + T(0.5) * a1 + a2 * T(1.0 / 6.0);
     T lo = tmin(gm, gp), hi = tmax(gm, gp);
-    if (a2 != T(0)) {
-        T sv = -a1 / (T(2) * a2);
-        if (sv > T(-0.5) && sv < T(0.5)) {
-            T gv = a0 + a1 * sv + a2 * (sv * sv - T(1.0 / 12.0));
-            lo = tmin(lo, gv);
-            hi = tmax(hi, gv);
-        }
+    if (tabs(a1) < tabs(a2)) {                 // vertex -a1 / (2 a2) inside the cell
+        T gv = a0 - a2 * T(1.0 / 12.0) - (a1 * a1) * trcp(T(4) * a2);
+        lo = tmin(lo, gv);
+        hi = tmax(hi, gv);
     }
+    if (!(hi > T(1) || lo < T(0))) return false;
     T th = T(1);
     if (hi > T(1)) th = tmin(th, (T(1) - a0) / (hi - a0));
     if (lo < T(0)) th = tmin(th, a0 / (a0 - lo));
@@ -386,7 +429,7 @@ struct PPBIdx { int f[10]; };
 template <typename T>
 __device__ __forceinline__ void slab(const T *q, T sig, T L, T *G)
 {
-    T t = tabs(sig) / L;
+    T t = tabs(sig) * trcp(L);
     T h = T(0.5) - t;
     T al0 = q[0] + q[1] * h + q[2] * (h * h - T(1.0 / 12.0));
     T al1 = t * (q[1] + T(2) * q[2] * h);
@@ -477,7 +520,7 @@ __device__ __forceinline__ void trace_cell(const T *qL, const T *qR, const T *dq
 {
     const T c2 = cj * cj;
     const T lm = uj - cj, l0 = uj, lp = uj + cj;
-    const T irj = T(1) / rj, icj = T(1) / cj;
+    const T irj = trcp(rj), icj = trcp(cj);
     const T rc2 = T(0.5) * rj * icj, cr_ = cj * irj, ic2 = icj * icj, i2c2 = T(0.5) * ic2;
     {   // right face: waves moving right
         T y = tmax(lp, T(0)) * nu;

@@ -143,10 +143,10 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
             T gv = T(fl) * gravity<T>(g, AX, xd, rtt + xd * xd);
             bool so = s < flo || s > fhi;
             T rho = r0 + rp;
-            T ir = T(1) / rho;
+            T ir = trcp(rho);
             T u = mn * ir, v = m1 * ir, w = m2 * ir;
             T pp = gm1 * (ep - T(0.5) * (mn * u + m1 * v + m2 * w));
-            T c = sqrt(gam * (pb + pp) * ir);
+            T c = tsqrt(gam * (pb + pp) * ir);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -377,8 +377,6 @@ void sweep_x_kernel(BatchArgs<T> b)
     const double xt[3] = { 0.0, centre(g, 1, y), centre(g, 2, z) };
     const T xt1 = T(xt[1]), xt2 = T(xt[2]);
     const T rtt = xt1 * xt1 + xt2 * xt2;
-    int flo, fhi;
-    fluid_interval(g, 0, xt, flo, fhi);
     const double dt64 = *a.dtp;
     const T dt = T(dt64), nu = T(dt64 / g.dx), hdt = T(0.5 * dt64), rdx = T(1.0 / g.dx);
     const T gam = T(g.gamma), gm1 = T(g.gamma - 1.0), gfac = T(g.gamma / (g.gamma - 1.0));
@@ -404,16 +402,16 @@ void sweep_x_kernel(BatchArgs<T> b)
     }
     const T xd = T(g.origin[0]) + (T(s) + T(0.5)) * T(g.dx);
     const T gv = T(fl) * gravity<T>(g, 0, xd, rtt + xd * xd);
-    const bool so = s < flo || s > fhi;
+    const bool so = solid_at(g, centre(g, 0, s), xt[1], xt[2]);    // exact FP64 test, own cell
     const T rho = r0 + cu[0];
-    const T ir = T(1) / rho;
+    const T ir = trcp(rho);
     T q[5];
     q[0] = cu[0];
     q[1] = cu[1] * ir;
     q[2] = cu[2] * ir;
     q[3] = cu[3] * ir;
     q[4] = gm1 * (cu[4] - T(0.5) * (cu[1] * q[1] + cu[2] * q[2] + cu[3] * q[3]));
-    const T c = sqrt(gam * (pb + q[4]) * ir);
+    const T c = tsqrt(gam * (pb + q[4]) * ir);
 
     // (2) face values at i+1/2, second differences, limited slopes
     T qf[5], d2[5], sm[5], flm[5];
