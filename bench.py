@@ -1,6 +1,7 @@
 """Throughput of the PPM + PPB 3-D step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu]
+                    [--calib-copy-mib M]
 
 Workload: the spherical convection shell on a 512^3 grid (FP32 perturbation
 form on an FP64 radial hydrostatic base, radial gravity, heating, confining
@@ -9,10 +10,13 @@ FP64 CFL reduction and heating, with dt computed on the device.  Inputs are
 resident in HBM before timing starts.  Prints ONE JSON line.
 
 The JSON carries
-  roofline      the dominant kernel (the fused pass) against the HBM peak:
-                algorithmic bytes per launch (15 fields read + 15 written per
-                cell) over its average duration, timed with HIP events on
-                the library's stream inside the timed region;
+  roofline      the dominant kernel (the pass kernel with the largest time
+                per step) against the HBM peak: algorithmic bytes per launch
+                (15 fields read + 15 written per cell) over its average
+                duration, timed with HIP events on the library's stream
+                inside the timed region; `traffic` is the measured HBM bytes
+                per launch from the committed hardware-counter summary, or
+                null when the pass sources differ from the ones counted;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same recipe;
   fp64          the same grid and steps in FP64 on the same GPU.
 """
@@ -28,6 +32,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_traffic_shell512_fp32.txt")
+# the kernels behind each pass of the FP32 step
+PASS_KERNELS = {"x": "sweep_x_kernel<float>", "y": "sweep_kernel<float, 1>", "z": "sweep_kernel<float, 2>"}
 N_FIELDS = 15
 METRIC = "cell-updates/s per PPM+PPB 3-D step, FP32-perturb vs FP64, % HBM roofline"
 
@@ -67,12 +74,39 @@ def run_gpu(prob, precision, steps, warmup, dev_prims):
     return info
 
 
-def cpu_baseline(n=256, steps=3):
+def measured_traffic():
+    """Measured HBM bytes per launch of each pass kernel, from the committed
+    counter summary, if it was taken from the pass sources as they are now."""
+    from paper_1810_13416_amd import profsum
+    try:
+        info = profsum.read_traffic_summary(TRAFFIC_SUMMARY)
+    except OSError:
+        return None
+    if info.get("sweep_sources_sha256") != profsum.sweep_sources_hash():
+        return None
+    return info
+
+
+def calib_copy(mib):
+    """One plain elementwise copy kernel (read M MiB, write M MiB): the
+    reference dispatch against which hardware byte counters are scaled."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    log(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written")
+    del a, b
+    torch.cuda.empty_cache()
+
+
+def cpu_baseline(n=256, steps=8):
     import numpy as np  # noqa: F401
     import oracle
     from paper_1810_13416_amd import problems
     prob = problems.config3(n=n)
-    threads = os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
     O = oracle.Oracle(prob.params, threads=threads)
     O.set_state(prob.state)
     del prob.state
@@ -95,6 +129,7 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -105,6 +140,8 @@ def main():
     import torch
     from paper_1810_13416_amd import ppmb, problems
 
+    if args.calib_copy_mib:
+        calib_copy(args.calib_copy_mib)
     log(f"generating the {args.n}^3 shell inputs")
     t0 = time.perf_counter()
     prob = problems.config3(n=args.n)
@@ -126,10 +163,19 @@ def main():
     torch.cuda.empty_cache()
 
     value = cells / (r32["ms_per_step"] * 1e-3)
-    pass_ms = [v for v in r32["pass_ms"].values() if v]
-    avg_pass_ms = sum(pass_ms) / len(pass_ms)
     bytes_per_launch = 2 * N_FIELDS * 4 * cells
-    achieved = bytes_per_launch / (avg_pass_ms * 1e-3) / 1e9
+    kernels = {}
+    for ax, ms in r32["pass_ms"].items():
+        if ms:
+            kernels[PASS_KERNELS[ax]] = {"avg_launch_ms": ms,
+                                         "achieved_GBs": bytes_per_launch / (ms * 1e-3) / 1e9}
+    dom_ax = max((ax for ax in r32["pass_ms"] if r32["pass_ms"][ax]), key=lambda a: r32["pass_ms"][a])
+    dom = PASS_KERNELS[dom_ax]
+    achieved = kernels[dom]["achieved_GBs"]
+    tr = measured_traffic()
+    traffic = None
+    if tr and dom in tr.get("bytes_per_launch", {}):
+        traffic = tr["bytes_per_launch"][dom]
     out = {
         "metric": METRIC,
         "value": value,
@@ -148,10 +194,10 @@ def main():
                                "velocity noise 1e-4 c0; step = 3 passes + FP64 CFL dt on device",
                    "cells": cells, "grid": [args.n] * 3, "precision": "fp32-perturbation"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sweep_kernel<float> (fused 1-D PPM+PPB pass)",
-                     "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_pass_ms,
-                     "pass_ms": r32["pass_ms"]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": dom, "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_ms": kernels[dom]["avg_launch_ms"], "kernels": kernels,
+                     "traffic_source": os.path.relpath(TRAFFIC_SUMMARY, ROOT) if traffic else None},
         "hbm_roofline_cell_updates_per_s": HBM_PEAK_GBS * 1e9 / (3 * 2 * N_FIELDS * 4),
         "fraction_of_hbm_roofline": value / (HBM_PEAK_GBS * 1e9 / (3 * 2 * N_FIELDS * 4)),
         "counters": r32["counters"],

@@ -332,17 +332,20 @@ template <typename T>
 __device__ __forceinline__ St<T> sample(const St<T> &L, const St<T> &R, const Face<T> &F, T ps, T us,
                                         T iWL, T iWR)
 {
+    // field-wise selects (no selection between whole structs, which would
+    // put the states in scratch memory)
+    const bool lft = us >= T(0);
+    const T r = lft ? L.r : R.r, u = lft ? L.u : R.u, v = lft ? L.v : R.v;
+    const T w = lft ? L.w : R.w, p = lft ? L.p : R.p;
+    const T rr = lft ? F.rL : F.rR, iW = lft ? iWL : iWR;
+    const T su = lft ? u : -u;
     St<T> f;
-    if (us >= T(0)) {
-        if (L.u * F.rL * iWL >= T(1)) return L;
-        T X = F.rL * (ps - L.p) * (iWL * iWL);
-        f.r = L.r + F.rL * X * trcp(T(1) - X);
-        f.u = us; f.v = L.v; f.w = L.w; f.p = ps;
+    if (su * rr * iW >= T(1)) {                  // the wave has passed the face
+        f.r = r; f.u = u; f.v = v; f.w = w; f.p = p;
     } else {
-        if (-R.u * F.rR * iWR >= T(1)) return R;
-        T X = F.rR * (ps - R.p) * (iWR * iWR);
-        f.r = R.r + F.rR * X * trcp(T(1) - X);
-        f.u = us; f.v = R.v; f.w = R.w; f.p = ps;
+        T X = rr * (ps - p) * (iW * iW);
+        f.r = r + rr * X * trcp(T(1) - X);
+        f.u = us; f.v = v; f.w = w; f.p = ps;
     }
     return f;
 }
@@ -591,8 +594,12 @@ __device__ __forceinline__ bool face_flux(St<T> Ls, St<T> Rs, bool sa, bool sb, 
         sg = T(0);
         return false;
     }
-    if (sb) { Rs = Ls; Rs.u = -Ls.u; }
-    if (sa) { Ls = Rs; Ls.u = -Rs.u; }
+    // a wall mirrors the fluid side (sa and sb exclusive here); field-wise
+    // selects keep the states in registers
+    Rs.r = sb ? Ls.r : Rs.r; Rs.u = sb ? -Ls.u : Rs.u; Rs.v = sb ? Ls.v : Rs.v;
+    Rs.w = sb ? Ls.w : Rs.w; Rs.p = sb ? Ls.p : Rs.p;
+    Ls.r = sa ? Rs.r : Ls.r; Ls.u = sa ? -Rs.u : Ls.u; Ls.v = sa ? Rs.v : Ls.v;
+    Ls.w = sa ? Rs.w : Ls.w; Ls.p = sa ? Rs.p : Ls.p;
     bool cnt;
     St<T> f = Solver<T>::solve(Ls, Rs, r0f, p0f, gam, cnt);
     T rf = r0f + f.r;

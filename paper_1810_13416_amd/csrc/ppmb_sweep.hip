@@ -341,17 +341,41 @@ void sweep_kernel(BatchArgs<T> b)
 
 constexpr int kXOut = 56;
 
-template <typename T>
-__device__ __forceinline__ T lane_sh(T v, int lane, int d)
+// Neighbour values inside the wave by DPP whole-wave shifts (wave_shr:1,
+// wave_shl:1): a VALU move, no LDS round trip.  The lane at the wave's edge
+// keeps its own value, so every lane holds a physical state.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
 {
-    return __shfl(v, (lane + d) & 63, 64);
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
 }
+template <int CTRL>
+__device__ __forceinline__ float dpp_v(float v)
+{
+    return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_v(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)b);
+    const unsigned hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+constexpr int kWaveShr1 = 0x138;   // lane l reads lane l - 1
+constexpr int kWaveShl1 = 0x130;   // lane l reads lane l + 1
+
+// value of the cell on the left (lane - 1) and on the right (lane + 1)
+template <typename T>
+__device__ __forceinline__ T from_left(T v) { return dpp_v<kWaveShr1>(v); }
+template <typename T>
+__device__ __forceinline__ T from_right(T v) { return dpp_v<kWaveShl1>(v); }
+__device__ __forceinline__ int from_right_i(int v) { return dpp_i<kWaveShl1>(v); }
 
 template <typename T>
-__device__ __forceinline__ St<T> lane_sh(const St<T> &v, int lane, int d)
+__device__ __forceinline__ St<T> from_right(const St<T> &v)
 {
-    return St<T>{lane_sh(v.r, lane, d), lane_sh(v.u, lane, d), lane_sh(v.v, lane, d),
-                 lane_sh(v.w, lane, d), lane_sh(v.p, lane, d)};
+    return St<T>{from_right(v.r), from_right(v.u), from_right(v.v), from_right(v.w), from_right(v.p)};
 }
 
 template <typename T>
@@ -418,22 +442,22 @@ void sweep_x_kernel(BatchArgs<T> b)
     T qm1[5], qp1[5];
 #pragma unroll
     for (int vv = 0; vv < 5; ++vv) {
-        qm1[vv] = lane_sh(q[vv], lane, -1);
-        qp1[vv] = lane_sh(q[vv], lane, 1);
-        T qp2 = lane_sh(q[vv], lane, 2);
+        qm1[vv] = from_left(q[vv]);
+        qp1[vv] = from_right(q[vv]);
+        T qp2 = from_right(qp1[vv]);
         qf[vv] = face4(qm1[vv], q[vv], qp1[vv], qp2);
         d2[vv] = (qm1[vv] + qp1[vv]) - T(2) * q[vv];
         sm[vv] = limited_slope(qm1[vv], q[vv], qp1[vv]);
     }
     T r0f, p0f;
     {
-        T rm = lane_sh(r0, lane, -1), rp = lane_sh(r0, lane, 1), rp2 = lane_sh(r0, lane, 2);
-        T pm = lane_sh(pb, lane, -1), pp = lane_sh(pb, lane, 1), pp2 = lane_sh(pb, lane, 2);
+        T rm = from_left(r0), rp = from_right(r0), rp2 = from_right(rp);
+        T pm = from_left(pb), pp = from_right(pb), pp2 = from_right(pp);
         r0f = face4(rm, r0, rp, rp2);
         p0f = face4(pm, pb, pp, pp2);
     }
 #pragma unroll
-    for (int vv = 0; vv < 5; ++vv) flm[vv] = face_limited(q[vv], qp1[vv], sm[vv], lane_sh(sm[vv], lane, 1));
+    for (int vv = 0; vv < 5; ++vv) flm[vv] = face_limited(q[vv], qp1[vv], sm[vv], from_right(sm[vv]));
 
     // (3) parabolas of cell i and tracing
     const bool own = lane >= NG && lane < NG + kXOut && i < nx;
@@ -442,31 +466,31 @@ void sweep_x_kernel(BatchArgs<T> b)
 #pragma unroll
     for (int vv = 0; vv < 5; ++vv) {
         T l, r;
-        bool con = parabola(g.smooth_detect, q[vv], lane_sh(qf[vv], lane, -1), qf[vv],
-                            lane_sh(flm[vv], lane, -1), flm[vv], lane_sh(d2[vv], lane, -1), d2[vv],
-                            lane_sh(d2[vv], lane, 1), l, r);
+        bool con = parabola(g.smooth_detect, q[vv], from_left(qf[vv]), qf[vv],
+                            from_left(flm[vv]), flm[vv], from_left(d2[vv]), d2[vv],
+                            from_right(d2[vv]), l, r);
         if (con && own) ++c_uns;
         qL[vv] = l; qR[vv] = r;
         dqv[vv] = r - l;
         q6[vv] = T(6) * (q[vv] - T(0.5) * (l + r));
     }
     St<T> TL, TR;
-    const T r0fL = lane_sh(r0f, lane, -1), p0fL = lane_sh(p0f, lane, -1);
+    const T r0fL = from_left(r0f), p0fL = from_left(p0f);
     trace_cell(qL, qR, dqv, q6, rho, c, q[1], q[0], gv, r0fL, r0f, p0fL, p0f, nu, hdt, rdx, TL, TR);
 
     // (4) Riemann problem and fluxes at face i+1/2
     T F[5], sg;
     {
-        St<T> Rs = lane_sh(TR, lane, 1);
-        bool sb = lane_sh((int)so, lane, 1) != 0;
+        St<T> Rs = from_right(TR);
+        bool sb = from_right_i((int)so) != 0;
         bool cnt = face_flux(TL, Rs, so, sb, r0f, p0f, gam, gfac, nu, F, sg);
         bool own_face = (own && i >= 0) || (seg == 0 && lane == NG - 1);
         if (cnt && own_face) ++c_rie;
     }
     T Fl[5];
 #pragma unroll
-    for (int vv = 0; vv < 5; ++vv) Fl[vv] = lane_sh(F[vv], lane, -1);
-    const T sgl = lane_sh(sg, lane, -1);
+    for (int vv = 0; vv < 5; ++vv) Fl[vv] = from_left(F[vv]);
+    const T sgl = from_left(sg);
 
     // (5) PPB: limit this cell's profile, slab at face i+1/2, update
     T L = T(1) + (sg - sgl);
@@ -481,8 +505,8 @@ void sweep_x_kernel(BatchArgs<T> b)
     {
         T dn[10];
 #pragma unroll
-        for (int v = 0; v < 10; ++v) dn[v] = lane_sh(pql[v], lane, 1);
-        const T Ln = lane_sh(L, lane, 1);
+        for (int v = 0; v < 10; ++v) dn[v] = from_right(pql[v]);
+        const T Ln = from_right(L);
         if (sg > T(0)) {
             slab(pql, sg, L, G);
         } else if (sg < T(0)) {
@@ -496,7 +520,7 @@ void sweep_x_kernel(BatchArgs<T> b)
     }
     T Gl[10];
 #pragma unroll
-    for (int v = 0; v < 10; ++v) Gl[v] = lane_sh(G[v], lane, -1);
+    for (int v = 0; v < 10; ++v) Gl[v] = from_left(G[v]);
 
     if (own) {
         T hn[5], o[10];

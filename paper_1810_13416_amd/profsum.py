@@ -1,0 +1,198 @@
+"""Summaries of rocprofv3 output for the pass kernels (text, a few KB).
+
+    python -m paper_1810_13416_amd.profsum stats  <kernel_stats.csv> <out.md> <command...>
+    python -m paper_1810_13416_amd.profsum traffic <fetch counter_collection.csv>
+           <write counter_collection.csv> <calib MiB> <cells> <out.txt> <command...>
+
+`stats` turns a `--kernel-trace --stats` run into a table of kernels by
+total time.  `traffic` turns two `--pmc` runs (FETCH_SIZE, then WRITE_SIZE,
+both in KiB per dispatch) into HBM bytes per launch of each pass kernel,
+scaled by what the same counters read for one plain elementwise copy of
+known size (`bench.py --calib-copy-mib M`, which reads M MiB and writes M
+MiB), and records a hash of the pass sources so that a reader can tell
+whether the figures still describe the kernels as built.
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SWEEP_SOURCES = ["csrc/ppmb_sweep.hip", "csrc/ppmb_dev.h", "csrc/ppmb_internal.h", "build.py"]
+
+
+def sweep_sources_hash() -> str:
+    h = hashlib.sha256()
+    for rel in SWEEP_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def short_name(name: str) -> str:
+    """'void ppmb::sweep_kernel<float, 1>(ppmb::BatchArgs<float>)' ->
+    'sweep_kernel<float, 1>'; other kernels keep their name up to '('."""
+    n = name.strip()
+    if n.startswith("void "):
+        n = n[5:]
+    depth = 0
+    for i, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            n = n[:i]
+            break
+    n = n.replace("ppmb::", "")
+    return re.sub(r"\s+", " ", n)
+
+
+def _col(header, *keys):
+    low = [h.lower() for h in header]
+    for k in keys:
+        for i, h in enumerate(low):
+            if h == k:
+                return i
+    for k in keys:
+        for i, h in enumerate(low):
+            if k in h:
+                return i
+    raise KeyError(f"none of {keys} in {header}")
+
+
+def read_kernel_stats(path):
+    with open(path, newline="") as f:
+        rows = list(csv.reader(f))
+    hdr, body = rows[0], rows[1:]
+    iname = _col(hdr, "name", "kernel_name")
+    icalls = _col(hdr, "calls")
+    itot = _col(hdr, "totaldurationns")
+    iavg = _col(hdr, "averagens")
+    imin = _col(hdr, "minns")
+    imax = _col(hdr, "maxns")
+    out = []
+    for r in body:
+        if not r:
+            continue
+        out.append({"name": short_name(r[iname]), "calls": int(r[icalls]),
+                    "total_ms": float(r[itot]) * 1e-6, "avg_ms": float(r[iavg]) * 1e-6,
+                    "min_ms": float(r[imin]) * 1e-6, "max_ms": float(r[imax]) * 1e-6})
+    out.sort(key=lambda d: -d["total_ms"])
+    return out
+
+
+def write_stats(csv_path, out_path, command):
+    rows = read_kernel_stats(csv_path)
+    tot = sum(r["total_ms"] for r in rows) or 1.0
+    lines = ["# Kernel time, rocprofv3 --kernel-trace --stats", "",
+             "Command:", "", "    " + command, "",
+             "| kernel | calls | total ms | avg ms | min ms | max ms | % |",
+             "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| `{r['name']}` | {r['calls']} | {r['total_ms']:.3f} | {r['avg_ms']:.4f} | "
+                     f"{r['min_ms']:.4f} | {r['max_ms']:.4f} | {100 * r['total_ms'] / tot:.1f} |")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def read_counters(path, counter):
+    """Per kernel: list of counter values (one per dispatch)."""
+    with open(path, newline="") as f:
+        rows = list(csv.reader(f))
+    hdr, body = rows[0], rows[1:]
+    iname = _col(hdr, "kernel_name")
+    icn = _col(hdr, "counter_name")
+    icv = _col(hdr, "counter_value")
+    idisp = _col(hdr, "dispatch_id", "correlation_id")
+    per = {}
+    seen = {}
+    for r in body:
+        if not r or r[icn] != counter:
+            continue
+        key = (r[idisp], r[iname])
+        seen[key] = seen.get(key, 0.0) + float(r[icv])     # sum over instances if split
+    for (disp, name), v in seen.items():
+        per.setdefault(short_name(name), []).append(v)
+    return per
+
+
+def _calib_value(per, mib):
+    """Counter reading of the calibration copy: the dispatch of an
+    elementwise 'neg' kernel whose reading is closest to M MiB."""
+    cands = [(k, v) for k, vs in per.items() for v in vs if "neg" in k.lower()]
+    if not cands:
+        cands = [(k, v) for k, vs in per.items() for v in vs if "elementwise" in k.lower()]
+    if not cands:
+        raise RuntimeError("calibration copy dispatch not found")
+    want = mib * 1024.0
+    k, v = min(cands, key=lambda kv: abs(kv[1] - want))
+    return k, v
+
+
+def write_traffic(fetch_csv, write_csv, mib, cells, out_path, command):
+    fe = read_counters(fetch_csv, "FETCH_SIZE")
+    wr = read_counters(write_csv, "WRITE_SIZE")
+    ck, cf = _calib_value(fe, mib)
+    _, cw = _calib_value(wr, mib)
+    true_kib = mib * 1024.0
+    sf, sw = true_kib / cf, true_kib / cw
+    alg = 2 * 15 * 4 * cells
+    lines = ["# HBM traffic of the FP32 pass kernels, spherical shell 512^3", "",
+             "Counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two separate",
+             "rocprofv3 --pmc runs of the same command, scaled by what they read for",
+             f"one plain elementwise copy of {mib} MiB in and {mib} MiB out.", "",
+             "Command (run once with --pmc FETCH_SIZE, once with --pmc WRITE_SIZE):", "",
+             "    " + command, "",
+             f"sweep_sources_sha256: {sweep_sources_hash()}",
+             f"calibration_kernel: {ck}",
+             f"calibration: FETCH_SIZE {cf:.1f} KiB, WRITE_SIZE {cw:.1f} KiB for {true_kib:.0f} KiB each; "
+             f"scale fetch {sf:.4f}, write {sw:.4f}",
+             f"algorithmic_bytes_per_launch: {alg}", "",
+             "| kernel | dispatches | FETCH KiB | WRITE KiB | HBM bytes/launch (scaled) | / algorithmic |",
+             "|---|---|---|---|---|---|"]
+    result = {}
+    for k in sorted(set(fe) & set(wr)):
+        f_kib = sum(fe[k]) / len(fe[k])
+        w_kib = sum(wr[k]) / len(wr[k])
+        b = (f_kib * sf + w_kib * sw) * 1024.0
+        lines.append(f"| `{k}` | {len(fe[k])} | {f_kib:.0f} | {w_kib:.0f} | {b:.4g} | "
+                     f"{b / alg:.3f} |")
+        if k.startswith("sweep"):
+            result[k] = b
+    lines.append("")
+    for k, b in result.items():
+        lines.append(f"bytes_per_launch {k}: {b:.6g}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def read_traffic_summary(path):
+    info = {"bytes_per_launch": {}}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("sweep_sources_sha256:"):
+                info["sweep_sources_sha256"] = line.split(":", 1)[1].strip()
+            elif line.startswith("bytes_per_launch "):
+                k, v = line[len("bytes_per_launch "):].rsplit(":", 1)
+                info["bytes_per_launch"][k.strip()] = float(v)
+    return info
+
+
+def main(argv):
+    if len(argv) >= 3 and argv[0] == "stats":
+        write_stats(argv[1], argv[2], " ".join(argv[3:]))
+    elif len(argv) >= 6 and argv[0] == "traffic":
+        write_traffic(argv[1], argv[2], int(argv[3]), int(argv[4]), argv[5], " ".join(argv[6:]))
+    else:
+        sys.stderr.write(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))
