@@ -149,6 +149,24 @@ static ppmb_status check_grid(const ppmb_grid *grid)
     return PPMB_OK;
 }
 
+// Least t with sqrt(t) >= R (IEEE sqrt, correctly rounded and monotone):
+// sqrt(r2) >= R exactly when r2 >= t.  R <= 0: every r2 >= 0 passes;
+// NaN R: none does.
+static double solid_threshold(double R)
+{
+    if (R != R) return R;
+    if (!(R > 0.0)) return -INFINITY;
+    if (std::isinf(R)) return R;
+    double t = R * R;
+    while (std::sqrt(t) < R) t = std::nextafter(t, INFINITY);
+    for (;;) {
+        double d = std::nextafter(t, 0.0);
+        if (std::sqrt(d) < R) break;
+        t = d;
+    }
+    return t;
+}
+
 static Geom geom_of(const ppmb_grid *grid)
 {
     Geom g{};
@@ -157,6 +175,7 @@ static Geom geom_of(const ppmb_grid *grid)
     g.gamma = grid->gamma;
     g.sphere = grid->sphere;
     g.sphere_r = grid->sphere_r;
+    g.sphere_t = solid_threshold(grid->sphere_r);
     g.grav_kind = grid->grav_kind;
     for (int q = 0; q < 4; ++q) g.grav[q] = grid->grav[q];
     g.heat_kind = grid->heat_kind;

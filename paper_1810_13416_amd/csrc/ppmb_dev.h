@@ -22,6 +22,7 @@ struct Geom {
     double gamma;
     int    sphere;
     double sphere_r;
+    double sphere_t;      // least r^2 whose correctly rounded sqrt is >= sphere_r
     int    grav_kind;
     double grav[4];
     int    heat_kind;
@@ -83,11 +84,13 @@ __device__ __forceinline__ double r2_exact(double x, double y, double z)
     return __dadd_rn(__dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y)), __dmul_rn(z, z));
 }
 
-// Sec. 3: cells outside the inscribed sphere are solid.
+// Sec. 3: cells outside the inscribed sphere are solid: sqrt(|x|^2) >= R.
+// The square root is correctly rounded and monotone, so the test is the
+// same as |x|^2 >= sphere_t, the threshold the host finds once.
 __device__ __forceinline__ bool solid_at(const Geom &g, double x, double y, double z)
 {
     if (!g.sphere) return false;
-    return sqrt(r2_exact(x, y, z)) >= g.sphere_r;
+    return r2_exact(x, y, z) >= g.sphere_t;
 }
 
 // Sec. 3: gravity falls to zero a few cells before the sphere; linear taper.
@@ -401,6 +404,16 @@ template <> struct Solver<float> {
 template <typename T>
 __device__ __forceinline__ bool fv_limit(T a0, T &a1, T &a2)
 {
+    // Quick acceptance: on the cell |a1 s| <= |a1|/2 and |a2 (s^2 - 1/12)|
+    // <= |a2|/6, so a profile whose bound a0 -+ e lies inside [0, 1] by more
+    // than the rounding of the exact test below is left as it is, exactly
+    // as the exact test would leave it.
+    {
+        const T eps = sizeof(T) == 4 ? T(1.0 / 16777216.0) : T(1.0 / 9007199254740992.0);
+        const T e = T(0.5) * tabs(a1) + tabs(a2) * T(1.0 / 6.0);
+        const T m = T(16) * eps * (tabs(a0) + tabs(a1) + tabs(a2));
+        if (a0 - e >= m && a0 + e <= T(1) - m) return false;
+    }
     T gm = a0 - T(0.5) * a1 + a2 * T(1.0 / 6.0);
     T gp = a0 + T(0.5) * a1 + a2 * T(1.0 / 6.0);
     T lo = tmin(gm, gp), hi = tmax(gm, gp);

@@ -248,17 +248,17 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
             pql[1] = l1; pql[2] = l2;
             T G[10];
             if (k >= 3) {
-                if (sg1 > T(0)) {
-                    slab(pqp, sg1, Lp, G);
-                } else if (sg1 < T(0)) {
-                    T fq[10];
+                // donor: cell k-4 when the face velocity is positive, else
+                // cell k-3 seen mirrored (odd-in-s coefficients flipped); a
+                // zero velocity gives a zero slab
+                const bool pos = sg1 > T(0);
+                T dn[10];
 #pragma unroll
-                    for (int v = 0; v < 10; ++v) fq[v] = (v == 1 || v == 4 || v == 6) ? -pql[v] : pql[v];
-                    slab(fq, sg1, Ld, G);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < 10; ++v) G[v] = T(0);
+                for (int v = 0; v < 10; ++v) {
+                    const T f = (v == 1 || v == 4 || v == 6) ? -pql[v] : pql[v];
+                    dn[v] = pos ? pqp[v] : f;
                 }
+                slab(dn, sg1, pos ? Lp : Ld, G);
                 const int cw = k - 4;
                 if (cw >= 0 && cw < n) {
                     long ci = base + cw * sAX;
@@ -300,8 +300,9 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
 // Marching kernel: each wave covers 64 pencils (lanes across x for the y
 // and z passes, across y for the x pass); a block holds blockDim/64 waves
 // on consecutive rows of the other transverse axis.
+// FP32: at most 256 VGPRs, two waves per SIMD; FP64 needs the full file.
 template <typename T, int AX>
-__global__ __launch_bounds__(256)
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1)
 void sweep_kernel(BatchArgs<T> b)
 {
     const BlockMap m = b.map[blockIdx.x];
@@ -334,9 +335,10 @@ void sweep_kernel(BatchArgs<T> b)
 // x pass with lanes along x.  Marching along x with lanes across y would
 // make every load touch 64 separate cache lines; instead one wave holds 64
 // consecutive cells of one x-pencil (cells x0-4 .. x0+59), every load and
-// store of a field is one coalesced 256-byte row, neighbours come from wave
-// shuffles, and the wave finishes the middle 56 cells, whose 4-cell
-// dependency cone (Sec. 4) lies inside the wave.
+// store of a field is one coalesced 256-byte row, neighbours come from
+// whole-wave shifts, and the wave finishes the middle 56 cells, whose
+// 4-cell dependency cone (Sec. 4) lies inside the wave; then it moves 56
+// cells on along the same row.
 // ---------------------------------------------------------------------
 
 constexpr int kXOut = 56;
@@ -378,6 +380,41 @@ __device__ __forceinline__ St<T> from_right(const St<T> &v)
     return St<T>{from_right(v.r), from_right(v.u), from_right(v.v), from_right(v.w), from_right(v.p)};
 }
 
+// Inputs of one lane for one segment: its cell's conserved fields, fv
+// coefficients (pass order, odd ones flipped through a wall) and base.
+template <typename T>
+struct XIn {
+    T cu[5];
+    T pq[10];
+    T r0, pb;
+    int s, fl;
+};
+
+template <typename T>
+__device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, long nc, long row,
+                                       int nx, int bc, int i, XIn<T> &o)
+{
+    using AI = AxisInfo<0>;
+    int fl = 1;
+    int s = i;
+    if (i < 0 || i >= nx) s = bc_source(i, nx, bc, fl);
+    const long ci = row + s;
+    o.s = s;
+    o.fl = fl;
+    o.cu[0] = in[RHO * nc + ci];
+    o.cu[1] = in[MX * nc + ci];
+    o.cu[2] = in[MY * nc + ci];
+    o.cu[3] = in[MZ * nc + ci];
+    o.cu[4] = in[EN * nc + ci];
+#pragma unroll
+    for (int v = 0; v < 10; ++v) o.pq[v] = in[AI::ppb(v) * nc + ci];
+    o.r0 = rho0[ci];
+    o.pb = p0[ci];
+}
+
+// One wave owns one x-row and walks it in segments of 56 outputs; the
+// loads of the next segment are issued before the current one is computed,
+// so their latency hides behind the arithmetic.
 template <typename T>
 __global__ __launch_bounds__(256)
 void sweep_x_kernel(BatchArgs<T> b)
@@ -388,163 +425,159 @@ void sweep_x_kernel(BatchArgs<T> b)
     const Geom g = B.g;
     const SweepArgs<T> a = brick_args(b, B);
     const int lane = threadIdx.x & 63;
-    const long wave = (long)m.local * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int rowi = m.local * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+    if (rowi >= ny * nz) return;                       // whole waves only
+    const int y = rowi % ny, z = rowi / ny;
     const int nseg = (nx + kXOut - 1) / kXOut;
-    if (wave >= (long)nseg * ny * nz) return;          // whole waves only
-    const int seg = (int)(wave % nseg);
-    const long pen = wave / nseg;
-    const int y = (int)(pen % ny), z = (int)(pen / ny);
-    const int i = seg * kXOut - NG + lane;             // this lane's cell along x
     const long nc = a.ncell;
-    const long base = ((long)z * ny + y) * nx;
-    const double xt[3] = { 0.0, centre(g, 1, y), centre(g, 2, z) };
-    const T xt1 = T(xt[1]), xt2 = T(xt[2]);
+    const long row = (long)rowi * nx;
+    const double yc = centre(g, 1, y), zc = centre(g, 2, z);
+    const T xt1 = T(yc), xt2 = T(zc);
     const T rtt = xt1 * xt1 + xt2 * xt2;
     const double dt64 = *a.dtp;
     const T dt = T(dt64), nu = T(dt64 / g.dx), hdt = T(0.5 * dt64), rdx = T(1.0 / g.dx);
     const T gam = T(g.gamma), gm1 = T(g.gamma - 1.0), gfac = T(g.gamma / (g.gamma - 1.0));
-    const T *in = a.in;
-
-    // (1) load this lane's cell, BC-mapped
-    int fl = 1;
-    int s = i;
-    if (i < 0 || i >= nx) s = bc_source(i, nx, g.bc[0], fl);
-    const long ci = base + s;
-    T cu[5];
-    cu[0] = in[RHO * nc + ci];
-    cu[1] = T(fl) * in[MX * nc + ci];
-    cu[2] = in[MY * nc + ci];
-    cu[3] = in[MZ * nc + ci];
-    cu[4] = in[EN * nc + ci];
-    const T r0 = a.rho0[ci], pb = a.p0[ci];
-    T pq[10];
-#pragma unroll
-    for (int v = 0; v < 10; ++v) {
-        T val = in[AI::ppb(v) * nc + ci];
-        pq[v] = AI::odd(v) ? T(fl) * val : val;
-    }
-    const T xd = T(g.origin[0]) + (T(s) + T(0.5)) * T(g.dx);
-    const T gv = T(fl) * gravity<T>(g, 0, xd, rtt + xd * xd);
-    const bool so = solid_at(g, centre(g, 0, s), xt[1], xt[2]);    // exact FP64 test, own cell
-    const T rho = r0 + cu[0];
-    const T ir = trcp(rho);
-    T q[5];
-    q[0] = cu[0];
-    q[1] = cu[1] * ir;
-    q[2] = cu[2] * ir;
-    q[3] = cu[3] * ir;
-    q[4] = gm1 * (cu[4] - T(0.5) * (cu[1] * q[1] + cu[2] * q[2] + cu[3] * q[3]));
-    const T c = tsqrt(gam * (pb + q[4]) * ir);
-
-    // (2) face values at i+1/2, second differences, limited slopes
-    T qf[5], d2[5], sm[5], flm[5];
-    T qm1[5], qp1[5];
-#pragma unroll
-    for (int vv = 0; vv < 5; ++vv) {
-        qm1[vv] = from_left(q[vv]);
-        qp1[vv] = from_right(q[vv]);
-        T qp2 = from_right(qp1[vv]);
-        qf[vv] = face4(qm1[vv], q[vv], qp1[vv], qp2);
-        d2[vv] = (qm1[vv] + qp1[vv]) - T(2) * q[vv];
-        sm[vv] = limited_slope(qm1[vv], q[vv], qp1[vv]);
-    }
-    T r0f, p0f;
-    {
-        T rm = from_left(r0), rp = from_right(r0), rp2 = from_right(rp);
-        T pm = from_left(pb), pp = from_right(pb), pp2 = from_right(pp);
-        r0f = face4(rm, r0, rp, rp2);
-        p0f = face4(pm, pb, pp, pp2);
-    }
-#pragma unroll
-    for (int vv = 0; vv < 5; ++vv) flm[vv] = face_limited(q[vv], qp1[vv], sm[vv], from_right(sm[vv]));
-
-    // (3) parabolas of cell i and tracing
-    const bool own = lane >= NG && lane < NG + kXOut && i < nx;
+    const T ox = T(g.origin[0]), dxT = T(g.dx);
+    const int bc = g.bc[0];
     unsigned long long c_lim = 0, c_uns = 0, c_rie = 0;
-    T qL[5], qR[5], dqv[5], q6[5];
-#pragma unroll
-    for (int vv = 0; vv < 5; ++vv) {
-        T l, r;
-        bool con = parabola(g.smooth_detect, q[vv], from_left(qf[vv]), qf[vv],
-                            from_left(flm[vv]), flm[vv], from_left(d2[vv]), d2[vv],
-                            from_right(d2[vv]), l, r);
-        if (con && own) ++c_uns;
-        qL[vv] = l; qR[vv] = r;
-        dqv[vv] = r - l;
-        q6[vv] = T(6) * (q[vv] - T(0.5) * (l + r));
-    }
-    St<T> TL, TR;
-    const T r0fL = from_left(r0f), p0fL = from_left(p0f);
-    trace_cell(qL, qR, dqv, q6, rho, c, q[1], q[0], gv, r0fL, r0f, p0fL, p0f, nu, hdt, rdx, TL, TR);
 
-    // (4) Riemann problem and fluxes at face i+1/2
-    T F[5], sg;
-    {
-        St<T> Rs = from_right(TR);
-        bool sb = from_right_i((int)so) != 0;
-        bool cnt = face_flux(TL, Rs, so, sb, r0f, p0f, gam, gfac, nu, F, sg);
-        bool own_face = (own && i >= 0) || (seg == 0 && lane == NG - 1);
-        if (cnt && own_face) ++c_rie;
-    }
-    T Fl[5];
-#pragma unroll
-    for (int vv = 0; vv < 5; ++vv) Fl[vv] = from_left(F[vv]);
-    const T sgl = from_left(sg);
+    XIn<T> cur, nxt;
+    x_load(a.in, a.rho0, a.p0, nc, row, nx, bc, -NG + lane, cur);
+    for (int seg = 0; seg < nseg; ++seg) {
+        const int i = seg * kXOut - NG + lane;         // this lane's cell along x
+        if (seg + 1 < nseg) x_load(a.in, a.rho0, a.p0, nc, row, nx, bc, i + kXOut, nxt);
 
-    // (5) PPB: limit this cell's profile, slab at face i+1/2, update
-    T L = T(1) + (sg - sgl);
-    T pql[10];
+        // (1) this lane's cell: primitives, gravity, solid flag
+        const int s = cur.s;
+        const T fl = T(cur.fl);
+        T cu[5], pq[10];
+        cu[0] = cur.cu[0];
+        cu[1] = fl * cur.cu[1];
+        cu[2] = cur.cu[2];
+        cu[3] = cur.cu[3];
+        cu[4] = cur.cu[4];
 #pragma unroll
-    for (int v = 0; v < 10; ++v) pql[v] = pq[v];
-    {
-        bool hit = fv_limit(pq[0], pql[1], pql[2]);
-        if (hit && own && !so) ++c_lim;
-    }
-    T G[10];
-    {
-        T dn[10];
+        for (int v = 0; v < 10; ++v) pq[v] = AI::odd(v) ? fl * cur.pq[v] : cur.pq[v];
+        const T r0 = cur.r0, pb = cur.pb;
+        const T xd = ox + (T(s) + T(0.5)) * dxT;
+        const T gv = fl * gravity<T>(g, 0, xd, rtt + xd * xd);
+        const bool so = solid_at(g, centre(g, 0, s), yc, zc);
+        const T rho = r0 + cu[0];
+        const T ir = trcp(rho);
+        T q[5];
+        q[0] = cu[0];
+        q[1] = cu[1] * ir;
+        q[2] = cu[2] * ir;
+        q[3] = cu[3] * ir;
+        q[4] = gm1 * (cu[4] - T(0.5) * (cu[1] * q[1] + cu[2] * q[2] + cu[3] * q[3]));
+        const T c = tsqrt(gam * (pb + q[4]) * ir);
+
+        // (2) face values at i+1/2, second differences, limited slopes
+        T qf[5], d2[5], sm[5], flm[5];
+        T qp1[5];
 #pragma unroll
-        for (int v = 0; v < 10; ++v) dn[v] = from_right(pql[v]);
-        const T Ln = from_right(L);
-        if (sg > T(0)) {
-            slab(pql, sg, L, G);
-        } else if (sg < T(0)) {
-#pragma unroll
-            for (int v = 0; v < 10; ++v) dn[v] = (v == 1 || v == 4 || v == 6) ? -dn[v] : dn[v];
-            slab(dn, sg, Ln, G);
-        } else {
-#pragma unroll
-            for (int v = 0; v < 10; ++v) G[v] = T(0);
+        for (int vv = 0; vv < 5; ++vv) {
+            const T qm1 = from_left(q[vv]);
+            qp1[vv] = from_right(q[vv]);
+            const T qp2 = from_right(qp1[vv]);
+            qf[vv] = face4(qm1, q[vv], qp1[vv], qp2);
+            d2[vv] = (qm1 + qp1[vv]) - T(2) * q[vv];
+            sm[vv] = limited_slope(qm1, q[vv], qp1[vv]);
         }
-    }
-    T Gl[10];
+        T r0f, p0f;
+        {
+            T rm = from_left(r0), rp = from_right(r0), rp2 = from_right(rp);
+            T pm = from_left(pb), pp = from_right(pb), pp2 = from_right(pp);
+            r0f = face4(rm, r0, rp, rp2);
+            p0f = face4(pm, pb, pp, pp2);
+        }
 #pragma unroll
-    for (int v = 0; v < 10; ++v) Gl[v] = from_left(G[v]);
+        for (int vv = 0; vv < 5; ++vv) flm[vv] = face_limited(q[vv], qp1[vv], sm[vv], from_right(sm[vv]));
 
-    if (own) {
-        T hn[5], o[10];
-        if (so) {
+        // (3) parabolas of cell i and tracing
+        const bool own = lane >= NG && lane < NG + kXOut && i < nx;
+        T qL[5], qR[5], dqv[5], q6[5];
 #pragma unroll
-            for (int vv = 0; vv < 5; ++vv) hn[vv] = cu[vv];
+        for (int vv = 0; vv < 5; ++vv) {
+            T l, r;
+            bool con = parabola(g.smooth_detect, q[vv], from_left(qf[vv]), qf[vv],
+                                from_left(flm[vv]), flm[vv], from_left(d2[vv]), d2[vv],
+                                from_right(d2[vv]), l, r);
+            if (con && own) ++c_uns;
+            qL[vv] = l; qR[vv] = r;
+            dqv[vv] = r - l;
+            q6[vv] = T(6) * (q[vv] - T(0.5) * (l + r));
+        }
+        St<T> TL, TR;
+        const T r0fL = from_left(r0f), p0fL = from_left(p0f);
+        trace_cell(qL, qR, dqv, q6, rho, c, q[1], q[0], gv, r0fL, r0f, p0fL, p0f, nu, hdt, rdx, TL, TR);
+
+        // (4) Riemann problem and fluxes at face i+1/2
+        T F[5], sg;
+        {
+            St<T> Rs = from_right(TR);
+            bool sb = from_right_i((int)so) != 0;
+            bool cnt = face_flux(TL, Rs, so, sb, r0f, p0f, gam, gfac, nu, F, sg);
+            bool own_face = (own && i >= 0) || (seg == 0 && lane == NG - 1);
+            if (cnt && own_face) ++c_rie;
+        }
+        T Fl[5];
 #pragma unroll
-            for (int v = 0; v < 10; ++v) o[v] = pq[v];
-        } else {
-            hydro_update(cu, Fl, F, nu, dt, gv, hn);
-            ppb_update(pql, sg - sgl, T(0.5) * (sgl + sg), Gl, G, o);
-            if (a.heat) {
-                T zc = T(xt[2]);
-                hn[4] = hn[4] + heating<T>(g, zc, rtt + xd * xd) * dt;
+        for (int vv = 0; vv < 5; ++vv) Fl[vv] = from_left(F[vv]);
+        const T sgl = from_left(sg);
+
+        // (5) PPB: limit this cell's profile, slab at face i+1/2, update
+        T L = T(1) + (sg - sgl);
+        T pql[10];
+#pragma unroll
+        for (int v = 0; v < 10; ++v) pql[v] = pq[v];
+        {
+            bool hit = fv_limit(pq[0], pql[1], pql[2]);
+            if (hit && own && !so) ++c_lim;
+        }
+        T G[10];
+        {
+            T dn[10];
+#pragma unroll
+            for (int v = 0; v < 10; ++v) dn[v] = from_right(pql[v]);
+            const T Ln = from_right(L);
+            // donor: this cell for a positive face velocity, else the right
+            // neighbour mirrored; a zero velocity gives a zero slab
+            const bool pos = sg > T(0);
+#pragma unroll
+            for (int v = 0; v < 10; ++v) {
+                const T f = (v == 1 || v == 4 || v == 6) ? -dn[v] : dn[v];
+                dn[v] = pos ? pql[v] : f;
             }
+            slab(dn, sg, pos ? L : Ln, G);
         }
-        const long co = base + i;
-        a.out[RHO * nc + co] = hn[0];
-        a.out[MX * nc + co] = hn[1];
-        a.out[MY * nc + co] = hn[2];
-        a.out[MZ * nc + co] = hn[3];
-        a.out[EN * nc + co] = hn[4];
+        T Gl[10];
 #pragma unroll
-        for (int v = 0; v < 10; ++v) a.out[AI::ppb(v) * nc + co] = o[v];
+        for (int v = 0; v < 10; ++v) Gl[v] = from_left(G[v]);
+
+        if (own) {
+            T hn[5], o[10];
+            if (so) {
+#pragma unroll
+                for (int vv = 0; vv < 5; ++vv) hn[vv] = cu[vv];
+#pragma unroll
+                for (int v = 0; v < 10; ++v) o[v] = pq[v];
+            } else {
+                hydro_update(cu, Fl, F, nu, dt, gv, hn);
+                ppb_update(pql, sg - sgl, T(0.5) * (sgl + sg), Gl, G, o);
+                if (a.heat) hn[4] = hn[4] + heating<T>(g, xt2, rtt + xd * xd) * dt;
+            }
+            const long co = row + i;
+            a.out[RHO * nc + co] = hn[0];
+            a.out[MX * nc + co] = hn[1];
+            a.out[MY * nc + co] = hn[2];
+            a.out[MZ * nc + co] = hn[3];
+            a.out[EN * nc + co] = hn[4];
+#pragma unroll
+            for (int v = 0; v < 10; ++v) a.out[AI::ppb(v) * nc + co] = o[v];
+        }
+        if (seg + 1 < nseg) cur = nxt;
     }
     unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
     for (int off = 32; off > 0; off >>= 1) {
@@ -570,7 +603,7 @@ static bool x_lanes_enabled()
 int pass_blocks(const Geom &g, int axis, const PassShape &sh)
 {
     if (axis == 0 && x_lanes_enabled()) {
-        const long nw = (long)((g.n[0] + kXOut - 1) / kXOut) * g.n[1] * g.n[2];
+        const long nw = (long)g.n[1] * g.n[2];            // one wave per x-row
         return (int)((nw + sh.x_waves - 1) / sh.x_waves);
     }
     const int ca = (axis == 0) ? 1 : 0;

@@ -3,9 +3,11 @@
     python -m paper_1810_13416_amd.profsum stats  <kernel_stats.csv> <out.md> <command...>
     python -m paper_1810_13416_amd.profsum traffic <fetch counter_collection.csv>
            <write counter_collection.csv> <calib MiB> <cells> <out.txt> <command...>
+    python -m paper_1810_13416_amd.profsum counters <out.md> <title> <csv> [<csv> ...] -- <command...>
 
 `stats` turns a `--kernel-trace --stats` run into a table of kernels by
-total time.  `traffic` turns two `--pmc` runs (FETCH_SIZE, then WRITE_SIZE,
+total time; `counters` tabulates any `--pmc` counters per kernel (mean per
+dispatch) from one or more runs.  `traffic` turns two `--pmc` runs (FETCH_SIZE, then WRITE_SIZE,
 both in KiB per dispatch) into HBM bytes per launch of each pass kernel,
 scaled by what the same counters read for one plain elementwise copy of
 known size (`bench.py --calib-copy-mib M`, which reads M MiB and writes M
@@ -170,6 +172,48 @@ def write_traffic(fetch_csv, write_csv, mib, cells, out_path, command):
         f.write("\n".join(lines) + "\n")
 
 
+def read_all_counters(path):
+    """{kernel: {counter: [value per dispatch]}} for every counter in a run."""
+    with open(path, newline="") as f:
+        rows = list(csv.reader(f))
+    hdr, body = rows[0], rows[1:]
+    iname = _col(hdr, "kernel_name")
+    icn = _col(hdr, "counter_name")
+    icv = _col(hdr, "counter_value")
+    idisp = _col(hdr, "dispatch_id", "correlation_id")
+    acc = {}
+    for r in body:
+        if not r:
+            continue
+        key = (r[idisp], short_name(r[iname]), r[icn])
+        acc[key] = acc.get(key, 0.0) + float(r[icv])
+    out = {}
+    for (disp, k, c), v in acc.items():
+        out.setdefault(k, {}).setdefault(c, []).append(v)
+    return out
+
+
+def write_counters(out_path, title, csvs, command, only_prefix=("sweep", "cfl_kernel")):
+    per = {}
+    for p in csvs:
+        for k, cs in read_all_counters(p).items():
+            per.setdefault(k, {}).update(cs)
+    names = sorted({c for cs in per.values() for c in cs})
+    lines = [f"# {title}", "", "Command (one run per counter group):", "", "    " + command, "",
+             "Mean per dispatch.", "",
+             "| kernel | " + " | ".join(names) + " |", "|---|" + "---|" * len(names)]
+    for k in sorted(per):
+        if only_prefix and not k.startswith(only_prefix):
+            continue
+        vals = []
+        for c in names:
+            v = per[k].get(c)
+            vals.append(f"{sum(v) / len(v):.4g}" if v else "")
+        lines.append(f"| `{k}` | " + " | ".join(vals) + " |")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def read_traffic_summary(path):
     info = {"bytes_per_launch": {}}
     with open(path) as f:
@@ -186,6 +230,9 @@ def read_traffic_summary(path):
 def main(argv):
     if len(argv) >= 3 and argv[0] == "stats":
         write_stats(argv[1], argv[2], " ".join(argv[3:]))
+    elif len(argv) >= 5 and argv[0] == "counters" and "--" in argv:
+        j = argv.index("--")
+        write_counters(argv[1], argv[2], argv[3:j], " ".join(argv[j + 1:]))
     elif len(argv) >= 6 and argv[0] == "traffic":
         write_traffic(argv[1], argv[2], int(argv[3]), int(argv[4]), argv[5], " ".join(argv[6:]))
     else:
