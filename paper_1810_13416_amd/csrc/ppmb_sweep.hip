@@ -48,6 +48,76 @@ __device__ __forceinline__ SweepArgs<T> brick_args(const BatchArgs<T> &b, const 
                         b.dt + B.dti, b.counters, B.ncell, b.heat};
 }
 
+template <bool B>
+struct Phase {
+    static constexpr bool value = B;
+};
+
+// Range-checked raw buffer access (gfx9 buffer resource, no stride): an
+// element index at or past the resource's count reads zero and writes
+// nothing, so stores are switched off per lane by their index, with no
+// branch, and every address is a 32-bit lane offset from a wave-uniform base.
+constexpr int kBufWord3 = 0x00020000;    // gfx9 raw buffer: 32-bit data format
+constexpr unsigned kNoIdx = 1u << 28;    // past every resource made here
+// A wave-uniform value passed through an empty asm: whatever is computed
+// from it is recomputed at each use (a few scalar instructions) instead of
+// being kept live in scalar registers across the loop, which would spill.
+__device__ __forceinline__ long opaque_s(long v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const T *p, int count)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(p), 0, count * (int)sizeof(T), kBufWord3);
+}
+__device__ __forceinline__ float bld(__amdgpu_buffer_rsrc_t r, unsigned idx, float)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4u, 0, 0));
+}
+__device__ __forceinline__ double bld(__amdgpu_buffer_rsrc_t r, unsigned idx, double)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8u, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t r, unsigned idx)
+{
+    return bld(r, idx, T(0));
+}
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned idx, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, idx * 4u, 0, 0);
+}
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned idx, double v)
+{
+    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, idx * 8u, 0, 0);
+}
+
+// A copy of v as a new value (an identity DPP move).  Loop-carried inputs
+// loaded one step ahead are taken through it where they are consumed: the
+// loaded registers then die there and the next step's loads can reuse them,
+// instead of the compiler copying them at the loop latch, which would wait
+// for the loads (and every store issued after them) at the end of each step.
+template <typename T>
+__device__ __forceinline__ T fresh(T v);
+template <>
+__device__ __forceinline__ float fresh(float v)
+{
+    const int b = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, 0xE4, 0xf, 0xf, false));
+}
+template <>
+__device__ __forceinline__ double fresh(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)b, (int)(unsigned)b, 0xE4, 0xf, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(b >> 32), (int)(unsigned)(b >> 32), 0xE4, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // pass-local order of the 10 fv coefficients and which flip at a wall
 __host__ __device__ constexpr int mixed_of(int a, int b) { return FXY + (4 - a - b) % 3; }
 
@@ -74,7 +144,7 @@ struct AxisInfo {
 
 // March one pencil; la / lb index it across the lane and block axes.
 template <typename T, int AX>
-__device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
+__device__ void march(const Geom &g, const SweepArgs<T> &a, int la0, int lane, int lb,
                       unsigned long long &c_lim, unsigned long long &c_uns, unsigned long long &c_rie)
 {
     using AI = AxisInfo<AX>;
@@ -82,11 +152,23 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
     const int n = g.n[AX];
     const int ca = (AX == 0) ? 1 : 0;
     const int cb = 3 - AX - ca;
+    // lanes past the edge of the brick march a copy of its last pencil and
+    // store nothing
+    const int cnt = min(64, g.n[ca] - la0);
+    const bool valid = lane < cnt;
+    const int lld = valid ? lane : cnt - 1;
+    const int la = la0 + lld;
     int ijk0[3];
     ijk0[ca] = la; ijk0[cb] = lb; ijk0[AX] = 0;
     const long stride[3] = { 1, (long)nx, (long)nx * ny };
-    const long base = ijk0[0] * stride[0] + ijk0[1] * stride[1] + ijk0[2] * stride[2];
     const long sAX = stride[AX];
+    // element index of this lane in the row of 64 pencils (stride 1 for the
+    // y and z passes, nx for the x pass), and the row's element count
+    const unsigned lix = (unsigned)(lld * stride[ca]);
+    const unsigned lst = valid ? lix : kNoIdx;
+    const int rcnt = (int)((cnt - 1) * stride[ca] + 1);
+    // wave-uniform offset of the 64-lane row at pencil index 0
+    const long ubase = (long)la0 * stride[ca] + (long)lb * stride[cb];
     const double xt[3] = { centre(g, 0, ijk0[0]), centre(g, 1, ijk0[1]), centre(g, 2, ijk0[2]) };
     // transverse part of |x|^2 and the fluid interval of this pencil
     const T xt1 = T(xt[AI::t1]), xt2 = T(xt[AI::t2]);
@@ -101,13 +183,17 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
     const int bc = g.bc[AX];
     const T *in = a.in;
     const long nc = a.ncell;
+    // field q of the 64-lane row at pencil index s (in / out / base)
+    const T *inb = in + ubase;
+    T *outb = a.out + ubase;
+    auto rin = [&](int q, int s) { return rsrc(inb + (opaque_s(nc) * q + s * sAX), rcnt); };
+    auto rout = [&](int q, int s) { return rsrc(outb + (opaque_s(nc) * q + s * sAX), rcnt); };
 
     // --- register window ---------------------------------------------
     T q[5][5];            // primitives rho', u, v, w, p' of cells k-4..k
     T rr[3], cr[3];       // rho, c of cells k-2..k
     T b0[4], b1[4];       // base rho0, p0 of cells k-3..k
     T gr[4];              // gravity along the pass, cells k-3..k
-    T cu[4][5];           // conserved rho', mn, mt1, mt2, E' of cells k-3..k
     bool sol[5];          // solid flags of cells k-4..k
     T qf[2][5], r0f[2], p0f[2];   // faces (k-3)+1/2 and (k-2)+1/2
     T sm[3][5];           // limited slopes of cells k-3..k-1
@@ -116,31 +202,70 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
     St<T> TLp;            // right-face state of cell k-3
     T Fp[5];              // fluxes at face (k-4)+1/2
     T sg1 = T(0), sg2 = T(0);     // sigma at faces (k-4)+1/2, (k-5)+1/2
-    T hyd[5];             // updated hydro of cell k-4
     T pq[10], pqp[10];    // fv coefficients of cells k-3 (this step) and k-4 (limited)
+    T pqr1 = T(0), pqr2 = T(0);   // cell k-4's slope and curvature before limiting
     T Lp = T(1);          // Lagrangian length of cell k-4
     T Gp[10];             // slab at face (k-5)+1/2
-    for (int v = 0; v < 5; ++v) { Fp[v] = T(0); hyd[v] = T(0); }
+    for (int v = 0; v < 5; ++v) Fp[v] = T(0);
     for (int v = 0; v < 10; ++v) { pq[v] = T(0); pqp[v] = T(0); Gp[v] = T(0); }
     TLp = St<T>{T(0), T(0), T(0), T(0), T(0)};
     for (int c = 0; c < 4; ++c) { gr[c] = T(0); b0[c] = T(0); b1[c] = T(0); }
     for (int c = 0; c < 5; ++c) sol[c] = false;
 
-    for (int k = -NG; k < n + NG; ++k) {
-        // ---- (1) load cell k and form its primitives (base added back, Sec. 1)
+    // Inputs of the next cell, loaded one step ahead so that their latency
+    // hides behind the current step's arithmetic.
+    T nx_rp, nx_mn, nx_m1, nx_m2, nx_ep, nx_r0, nx_pb;
+    int nx_s, nx_fl;
+    auto load_next = [&](int k) {
+        int fl = 1;
+        int s = k;
+        if (k < 0 || k >= n) s = bc_source(k, n, bc, fl);
+        nx_rp = bld<T>(rin(RHO, s), lix);
+        nx_mn = bld<T>(rin(MX + AX, s), lix);
+        nx_m1 = bld<T>(rin(MX + AI::t1, s), lix);
+        nx_m2 = bld<T>(rin(MX + AI::t2, s), lix);
+        nx_ep = bld<T>(rin(EN, s), lix);
+        nx_r0 = bld<T>(rsrc(a.rho0 + ubase + s * sAX, rcnt), lix);
+        nx_pb = bld<T>(rsrc(a.p0 + ubase + s * sAX, rcnt), lix);
+        nx_s = s;
+        nx_fl = fl;
+    };
+    load_next(-NG);
+    // settle the first loads here, so that the loop's own wait for the next
+    // cell's inputs only counts memory operations issued after them
+    __builtin_amdgcn_s_waitcnt(0);
+
+    // One step of the march.  The steady steps (every stage active, every
+    // cell of the step inside the pencil) are a loop of their own with the
+    // range tests compiled out, so that every memory operation is issued on
+    // every step and the compiler's waits count exactly the operations
+    // issued after the one waited for; the few steps at either end of the
+    // pencil run the general form.
+    auto step = [&](const int k, auto phase) {
+        constexpr bool S = decltype(phase)::value;
+        // ---- (1) cell k from the prefetched inputs (base added back, Sec. 1);
+        //          loads of cell k+1 and of the conserved fields of cell k-3
+        //          (cache hits, for its update) are issued first
+        const int s = nx_s;
+        const T flT = T(nx_fl);
+        const T rp = fresh(nx_rp), mn = flT * nx_mn, m1 = fresh(nx_m1), m2 = fresh(nx_m2), ep = fresh(nx_ep);
+        const T r0 = fresh(nx_r0), pb = fresh(nx_pb);
+        const int cu_ = k - 3;
+        const bool upd = S || (cu_ >= 0 && cu_ < n);
+        // cell k-3 for its update; outside the pencil the loads and the
+        // stores below are switched off by index (one clamped row address)
+        const int c3 = upd ? cu_ : 0;
+        const unsigned ld3 = upd ? lix : kNoIdx;
+        const unsigned st3 = upd ? lst : kNoIdx;
+        T cu3[5];
+        cu3[0] = bld<T>(rin(RHO, c3), ld3);
+        cu3[1] = bld<T>(rin(MX + AX, c3), ld3);
+        cu3[2] = bld<T>(rin(MX + AI::t1, c3), ld3);
+        cu3[3] = bld<T>(rin(MX + AI::t2, c3), ld3);
+        cu3[4] = bld<T>(rin(EN, c3), ld3);
         {
-            int fl = 1;
-            int s = k;
-            if (k < 0 || k >= n) s = bc_source(k, n, bc, fl);
-            long ci = base + s * sAX;
-            T rp = in[RHO * nc + ci];
-            T mn = T(fl) * in[(MX + AX) * nc + ci];
-            T m1 = in[(MX + AI::t1) * nc + ci];
-            T m2 = in[(MX + AI::t2) * nc + ci];
-            T ep = in[EN * nc + ci];
-            T r0 = a.rho0[ci], pb = a.p0[ci];
             T xd = ox + (T(s) + T(0.5)) * dxT;
-            T gv = T(fl) * gravity<T>(g, AX, xd, rtt + xd * xd);
+            T gv = flT * gravity<T>(g, AX, xd, rtt + xd * xd);
             bool so = s < flo || s > fhi;
             T rho = r0 + rp;
             T ir = trcp(rho);
@@ -155,30 +280,30 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
             rr[0] = rr[1]; rr[1] = rr[2]; rr[2] = rho;
             cr[0] = cr[1]; cr[1] = cr[2]; cr[2] = c;
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                b0[r] = b0[r + 1]; b1[r] = b1[r + 1]; gr[r] = gr[r + 1];
-#pragma unroll
-                for (int vv = 0; vv < 5; ++vv) cu[r][vv] = cu[r + 1][vv];
-            }
+            for (int r = 0; r < 3; ++r) { b0[r] = b0[r + 1]; b1[r] = b1[r + 1]; gr[r] = gr[r + 1]; }
 #pragma unroll
             for (int r = 0; r < 4; ++r) sol[r] = sol[r + 1];
             b0[3] = r0; b1[3] = pb; gr[3] = gv; sol[4] = so;
-            cu[3][0] = rp; cu[3][1] = mn; cu[3][2] = m1; cu[3][3] = m2; cu[3][4] = ep;
         }
-        // fv coefficients of cell k-3 (donors -1..n)
-        if (k - 3 >= -1) {
-            int fl = 1;
-            int s = k - 3;
-            if (s < 0 || s >= n) s = bc_source(k - 3, n, bc, fl);
-            long ci = base + s * sAX;
+        // the inputs of cell k are consumed: their registers take the loads
+        // of cell k+1 (past the end this reads a valid ghost source, unused).
+        // The barrier keeps the scheduler from hoisting these loads above
+        // the last use of the old values, which would force a register copy
+        // (and a wait on the loads) at the end of every step.
+        __builtin_amdgcn_sched_barrier(0);
+        load_next(k + 1);
+        // fv coefficients of cell k-3 (donors -1..n), loaded raw; the wall
+        // flip of the odd ones is applied where they are used, so that no
+        // arithmetic waits on these loads before then
+        int pq_fl = 1;
+        {
+            int s3 = k - 3;
+            if (!S && (s3 < 0 || s3 >= n)) s3 = bc_source(k - 3, n, bc, pq_fl);
 #pragma unroll
-            for (int v = 0; v < 10; ++v) {
-                T val = in[AI::ppb(v) * nc + ci];
-                pq[v] = AI::odd(v) ? T(fl) * val : val;
-            }
+            for (int v = 0; v < 10; ++v) pq[v] = bld<T>(rin(AI::ppb(v), s3), lix);
         }
         // ---- (2) interface values at face (k-2)+1/2 (cells k-3..k)
-        if (k >= -1) {
+        if (S || k >= -1) {
 #pragma unroll
             for (int vv = 0; vv < 5; ++vv) { qf[0][vv] = qf[1][vv]; qf[1][vv] = face4(q[1][vv], q[2][vv], q[3][vv], q[4][vv]); }
             r0f[0] = r0f[1]; r0f[1] = face4(b0[0], b0[1], b0[2], b0[3]);
@@ -186,7 +311,7 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
         }
         // ---- (3) limited slope and second difference of cell k-1; the
         //          limited-slope face value at (k-2)+1/2
-        if (k >= -2) {
+        if (S || k >= -2) {
 #pragma unroll
             for (int vv = 0; vv < 5; ++vv) {
                 sm[0][vv] = sm[1][vv]; sm[1][vv] = sm[2][vv];
@@ -197,20 +322,20 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
                 flm[1][vv] = face_limited(q[2][vv], q[3][vv], sm[1][vv], sm[2][vv]);
             }
         }
-        if (k < 0) continue;
+        if (!S && k < 0) return;
         // ---- (4) parabolas of cell k-2, constrained only where the 5-cell
         //          window is not smooth (Sec. 1), blended over the graded
         //          band; tracing (CW84 Sec. 3)
         St<T> TL, TR;
         {
-            const bool interior = (k - 2 >= 0) && (k - 2 < n);
+            const bool interior = S || ((k - 2 >= 0) && (k - 2 < n));
             T qL[5], qR[5], dq[5], q6[5];
 #pragma unroll
             for (int vv = 0; vv < 5; ++vv) {
                 T l, r;
                 bool con = parabola(g.smooth_detect, q[2][vv], qf[0][vv], qf[1][vv], flm[0][vv], flm[1][vv],
                                     d2[0][vv], d2[1][vv], d2[2][vv], l, r);
-                if (con && interior) ++c_uns;
+                if (con && interior && valid) ++c_uns;
                 qL[vv] = l; qR[vv] = r;
                 dq[vv] = r - l;
                 q6[vv] = T(6) * (q[2][vv] - T(0.5) * (l + r));
@@ -221,33 +346,44 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
         // ---- (5) Riemann problem and fluxes at face (k-3)+1/2
         T F[5] = { T(0), T(0), T(0), T(0), T(0) };
         T sg = T(0);
-        if (k >= 1) {
-            bool cnt = face_flux(TLp, TR, sol[1], sol[2], r0f[0], p0f[0], gam, gfac, nu, F, sg);
-            if (cnt && k - 3 >= -1 && k - 3 < n) ++c_rie;
+        if (S || k >= 1) {
+            bool rie = face_flux(TLp, TR, sol[1], sol[2], r0f[0], p0f[0], gam, gfac, nu, F, sg);
+            if (rie && (S || (k - 3 >= -1 && k - 3 < n)) && valid) ++c_rie;
         }
         TLp = TL;
-        // ---- (6) conservative update of cell k-3 (written one step later)
-        T hn[5] = { T(0), T(0), T(0), T(0), T(0) };
-        const int cu_ = k - 3;
-        if (cu_ >= 0 && cu_ < n) {
-            if (sol[1]) {
-                for (int vv = 0; vv < 5; ++vv) hn[vv] = cu[0][vv];
-            } else {
-                hydro_update(cu[0], Fp, F, nu, dt, gr[0], hn);
+        // ---- (6) conservative update of cell k-3 and heating; written now
+        {
+            T hn[5];
+            hydro_update(cu3, Fp, F, nu, dt, gr[0], hn);
+            if (a.heat) {
+                T xd = ox + (T(cu_) + T(0.5)) * dxT;
+                T zc = AX == 2 ? xd : T(xt[2]);
+                hn[4] = hn[4] + heating<T>(g, zc, rtt + xd * xd) * dt;
             }
+#pragma unroll
+            for (int vv = 0; vv < 5; ++vv) hn[vv] = sol[1] ? cu3[vv] : hn[vv];
+            bst(rout(RHO, c3), st3, hn[0]);
+            bst(rout(MX + AX, c3), st3, hn[1]);
+            bst(rout(MX + AI::t1, c3), st3, hn[2]);
+            bst(rout(MX + AI::t2, c3), st3, hn[3]);
+            bst(rout(EN, c3), st3, hn[4]);
         }
         // ---- (7) PPB: donor k-3, slab at face (k-4)+1/2, update cell k-4
-        if (k >= 2) {
+        if (S || k >= 2) {
+            if (!S && pq_fl < 0) {
+#pragma unroll
+                for (int v = 0; v < 10; ++v) pq[v] = AI::odd(v) ? -pq[v] : pq[v];
+            }
             T Ld = T(1) + (sg - sg1);
             T l1 = pq[1], l2 = pq[2];
             bool hit = fv_limit(pq[0], l1, l2);
-            if (hit && k - 3 >= 0 && k - 3 < n && !sol[1]) ++c_lim;
+            if (hit && (S || (k - 3 >= 0 && k - 3 < n)) && !sol[1] && valid) ++c_lim;
             T pql[10];
 #pragma unroll
             for (int v = 0; v < 10; ++v) pql[v] = pq[v];
             pql[1] = l1; pql[2] = l2;
             T G[10];
-            if (k >= 3) {
+            if (S || k >= 3) {
                 // donor: cell k-4 when the face velocity is positive, else
                 // cell k-3 seen mirrored (odd-in-s coefficients flipped); a
                 // zero velocity gives a zero slab
@@ -260,40 +396,37 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la, int lb,
                 }
                 slab(dn, sg1, pos ? Lp : Ld, G);
                 const int cw = k - 4;
-                if (cw >= 0 && cw < n) {
-                    long ci = base + cw * sAX;
-                    T o[10];
-                    const bool solid_w = sol[0];
-                    if (solid_w) {
+                const bool wr = S || (cw >= 0 && cw < n);
+                const int cwc = wr ? cw : 0;
+                const unsigned stw = wr ? lst : kNoIdx;
+                T o[10];
+                ppb_update(pqp, sg1 - sg2, T(0.5) * (sg2 + sg1), Gp, G, o);
+                // a solid cell keeps its coefficients as they came in
 #pragma unroll
-                        for (int v = 0; v < 10; ++v) o[v] = in[AI::ppb(v) * nc + ci];
-                    } else {
-                        ppb_update(pqp, sg1 - sg2, T(0.5) * (sg2 + sg1), Gp, G, o);
-                    }
-                    T e = hyd[4];
-                    if (a.heat && !solid_w) {
-                        T xd = ox + (T(cw) + T(0.5)) * dxT;
-                        T zc = AX == 2 ? xd : T(xt[2]);
-                        e = e + heating<T>(g, zc, rtt + xd * xd) * dt;
-                    }
-                    a.out[RHO * nc + ci] = hyd[0];
-                    a.out[(MX + AX) * nc + ci] = hyd[1];
-                    a.out[(MX + AI::t1) * nc + ci] = hyd[2];
-                    a.out[(MX + AI::t2) * nc + ci] = hyd[3];
-                    a.out[EN * nc + ci] = e;
+                for (int v = 0; v < 10; ++v)
+                    o[v] = sol[0] ? (v == 1 ? pqr1 : (v == 2 ? pqr2 : pqp[v])) : o[v];
 #pragma unroll
-                    for (int v = 0; v < 10; ++v) a.out[AI::ppb(v) * nc + ci] = o[v];
-                }
+                for (int v = 0; v < 10; ++v) bst(rout(AI::ppb(v), cwc), stw, o[v]);
 #pragma unroll
                 for (int v = 0; v < 10; ++v) Gp[v] = G[v];
             }
 #pragma unroll
             for (int v = 0; v < 10; ++v) pqp[v] = pql[v];
+            pqr1 = pq[1];
+            pqr2 = pq[2];
             Lp = Ld;
         }
         sg2 = sg1; sg1 = sg;
 #pragma unroll
-        for (int vv = 0; vv < 5; ++vv) { Fp[vv] = F[vv]; hyd[vv] = hn[vv]; }
+        for (int vv = 0; vv < 5; ++vv) Fp[vv] = F[vv];
+    };
+    for (int k = -NG; k < n + NG; ++k) {
+        if (k == NG && NG <= n + 1) {
+            __builtin_amdgcn_s_waitcnt(0);
+            for (; k <= n + 1; ++k) step(k, Phase<true>{});
+            __builtin_amdgcn_s_waitcnt(0);
+        }
+        step(k, Phase<false>{});
     }
 }
 
@@ -312,11 +445,12 @@ void sweep_kernel(BatchArgs<T> b)
     const int ca = (AX == 0) ? 1 : 0;
     const int cb = 3 - AX - ca;
     const int waves = blockDim.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int nblk_a = (g.n[ca] + 63) / 64;
-    const int la = (m.local % nblk_a) * 64 + (threadIdx.x & 63);
-    const int lb = (m.local / nblk_a) * waves + (threadIdx.x >> 6);
+    const int la0 = (m.local % nblk_a) * 64;
+    const int lb = (m.local / nblk_a) * waves + wv;
     unsigned long long c_lim = 0, c_uns = 0, c_rie = 0;
-    if (la < g.n[ca] && lb < g.n[cb]) march<T, AX>(g, a, la, lb, c_lim, c_uns, c_rie);
+    if (lb < g.n[cb]) march<T, AX>(g, a, la0, (int)(threadIdx.x & 63), lb, c_lim, c_uns, c_rie);
     // event counters: one atomic per wave and counter
     unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
     for (int off = 32; off > 0; off >>= 1) {
@@ -398,18 +532,19 @@ __device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, 
     int fl = 1;
     int s = i;
     if (i < 0 || i >= nx) s = bc_source(i, nx, bc, fl);
-    const long ci = row + s;
     o.s = s;
     o.fl = fl;
-    o.cu[0] = in[RHO * nc + ci];
-    o.cu[1] = in[MX * nc + ci];
-    o.cu[2] = in[MY * nc + ci];
-    o.cu[3] = in[MZ * nc + ci];
-    o.cu[4] = in[EN * nc + ci];
+    const T *inr = in + row;
+    auto fld = [&](int q) { return rsrc(inr + opaque_s(nc) * q, nx); };
+    o.cu[0] = bld<T>(fld(RHO), s);
+    o.cu[1] = bld<T>(fld(MX), s);
+    o.cu[2] = bld<T>(fld(MY), s);
+    o.cu[3] = bld<T>(fld(MZ), s);
+    o.cu[4] = bld<T>(fld(EN), s);
 #pragma unroll
-    for (int v = 0; v < 10; ++v) o.pq[v] = in[AI::ppb(v) * nc + ci];
-    o.r0 = rho0[ci];
-    o.pb = p0[ci];
+    for (int v = 0; v < 10; ++v) o.pq[v] = bld<T>(fld(AI::ppb(v)), s);
+    o.r0 = bld<T>(rsrc(rho0 + row, nx), s);
+    o.pb = bld<T>(rsrc(p0 + row, nx), s);
 }
 
 // One wave owns one x-row and walks it in segments of 56 outputs; the
@@ -426,7 +561,7 @@ void sweep_x_kernel(BatchArgs<T> b)
     const SweepArgs<T> a = brick_args(b, B);
     const int lane = threadIdx.x & 63;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    const int rowi = m.local * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+    const int rowi = m.local * (int)(blockDim.x >> 6) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (rowi >= ny * nz) return;                       // whole waves only
     const int y = rowi % ny, z = rowi / ny;
     const int nseg = (nx + kXOut - 1) / kXOut;
@@ -442,24 +577,30 @@ void sweep_x_kernel(BatchArgs<T> b)
     const int bc = g.bc[0];
     unsigned long long c_lim = 0, c_uns = 0, c_rie = 0;
 
-    XIn<T> cur, nxt;
+    XIn<T> cur;
     x_load(a.in, a.rho0, a.p0, nc, row, nx, bc, -NG + lane, cur);
+    // settle the first loads, so that the loop's waits count only the
+    // memory operations of the loop itself
+    __builtin_amdgcn_s_waitcnt(0);
     for (int seg = 0; seg < nseg; ++seg) {
         const int i = seg * kXOut - NG + lane;         // this lane's cell along x
-        if (seg + 1 < nseg) x_load(a.in, a.rho0, a.p0, nc, row, nx, bc, i + kXOut, nxt);
 
-        // (1) this lane's cell: primitives, gravity, solid flag
+        // (1) this lane's cell: its inputs are taken over as new values,
+        //     then the next segment's loads go into the same registers
+        //     (past the row's end they read valid ghost sources, unused)
         const int s = cur.s;
         const T fl = T(cur.fl);
         T cu[5], pq[10];
-        cu[0] = cur.cu[0];
+        cu[0] = fresh(cur.cu[0]);
         cu[1] = fl * cur.cu[1];
-        cu[2] = cur.cu[2];
-        cu[3] = cur.cu[3];
-        cu[4] = cur.cu[4];
+        cu[2] = fresh(cur.cu[2]);
+        cu[3] = fresh(cur.cu[3]);
+        cu[4] = fresh(cur.cu[4]);
 #pragma unroll
-        for (int v = 0; v < 10; ++v) pq[v] = AI::odd(v) ? fl * cur.pq[v] : cur.pq[v];
-        const T r0 = cur.r0, pb = cur.pb;
+        for (int v = 0; v < 10; ++v) pq[v] = AI::odd(v) ? fl * cur.pq[v] : fresh(cur.pq[v]);
+        const T r0 = fresh(cur.r0), pb = fresh(cur.pb);
+        __builtin_amdgcn_sched_barrier(0);
+        x_load(a.in, a.rho0, a.p0, nc, row, nx, bc, i + kXOut, cur);
         const T xd = ox + (T(s) + T(0.5)) * dxT;
         const T gv = fl * gravity<T>(g, 0, xd, rtt + xd * xd);
         const bool so = solid_at(g, centre(g, 0, s), yc, zc);
@@ -556,28 +697,28 @@ void sweep_x_kernel(BatchArgs<T> b)
 #pragma unroll
         for (int v = 0; v < 10; ++v) Gl[v] = from_left(G[v]);
 
-        if (own) {
+        {
+            // stores of the owned cells; the others are switched off by
+            // index; a solid cell keeps its state
             T hn[5], o[10];
-            if (so) {
+            hydro_update(cu, Fl, F, nu, dt, gv, hn);
+            ppb_update(pql, sg - sgl, T(0.5) * (sgl + sg), Gl, G, o);
+            if (a.heat) hn[4] = hn[4] + heating<T>(g, xt2, rtt + xd * xd) * dt;
 #pragma unroll
-                for (int vv = 0; vv < 5; ++vv) hn[vv] = cu[vv];
+            for (int vv = 0; vv < 5; ++vv) hn[vv] = so ? cu[vv] : hn[vv];
 #pragma unroll
-                for (int v = 0; v < 10; ++v) o[v] = pq[v];
-            } else {
-                hydro_update(cu, Fl, F, nu, dt, gv, hn);
-                ppb_update(pql, sg - sgl, T(0.5) * (sgl + sg), Gl, G, o);
-                if (a.heat) hn[4] = hn[4] + heating<T>(g, xt2, rtt + xd * xd) * dt;
-            }
-            const long co = row + i;
-            a.out[RHO * nc + co] = hn[0];
-            a.out[MX * nc + co] = hn[1];
-            a.out[MY * nc + co] = hn[2];
-            a.out[MZ * nc + co] = hn[3];
-            a.out[EN * nc + co] = hn[4];
+            for (int v = 0; v < 10; ++v) o[v] = so ? pq[v] : o[v];
+            const unsigned io = own ? (unsigned)i : kNoIdx;
+            T *outr = a.out + row;
+            auto fo = [&](int q) { return rsrc(outr + opaque_s(nc) * q, nx); };
+            bst(fo(RHO), io, hn[0]);
+            bst(fo(MX), io, hn[1]);
+            bst(fo(MY), io, hn[2]);
+            bst(fo(MZ), io, hn[3]);
+            bst(fo(EN), io, hn[4]);
 #pragma unroll
-            for (int v = 0; v < 10; ++v) a.out[AI::ppb(v) * nc + co] = o[v];
+            for (int v = 0; v < 10; ++v) bst(fo(AI::ppb(v)), io, o[v]);
         }
-        if (seg + 1 < nseg) cur = nxt;
     }
     unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
     for (int off = 32; off > 0; off >>= 1) {
