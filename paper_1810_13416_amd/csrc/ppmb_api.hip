@@ -44,6 +44,10 @@ struct ppmb_ctx {
     std::vector<int> cfirst;
     long nstep = 0;
     unsigned long long steps = 0;
+    // work[] holds the CFL maxima of the current state: the last pass of a
+    // step folds them in, so the next step only needs the final division.
+    // Cleared by anything else that changes the state or the base.
+    bool cfl_ready = false;
     bool profiling = false;
     struct Timed { hipEvent_t a, b; int axis; };
     std::vector<Timed> timed;
@@ -284,8 +288,9 @@ static ppmb_status enqueue_cfl(ppmb_ctx *c, double cfl, int b0, int b1)
     return PPMB_OK;
 }
 
-// One pass along `axis` for bricks [b0, b1), reading arena `from`.
-static ppmb_status enqueue_pass(ppmb_ctx *c, int axis, int heat, int b0, int b1, int from)
+// One pass along `axis` for bricks [b0, b1), reading arena `from`; with
+// `cfl` it also reduces the signal speeds of its output into work[].
+static ppmb_status enqueue_pass(ppmb_ctx *c, int axis, int heat, int b0, int b1, int from, int cfl = 0)
 {
     const int f0 = c->pfirst[axis][b0], f1 = c->pfirst[axis][b1];
     ppmb_ctx::Timed tm{ nullptr, nullptr, axis };
@@ -297,11 +302,12 @@ static ppmb_status enqueue_pass(ppmb_ctx *c, int axis, int heat, int b0, int b1,
     hipError_t e;
     if (c->prec == PPMB_FP64)
         e = launch_sweep<double>(axis, c->shape, c->db, c->pmap[axis] + f0, f1 - f0, arena<double>(c, from),
-                                 arena<double>(c, 1 - from), c->base64, c->dt, c->cnt, heat, c->stream);
+                                 arena<double>(c, 1 - from), c->base64, c->dt, c->cnt, heat, c->base64,
+                                 c->work, cfl, c->stream);
     else
         e = launch_sweep<float>(axis, c->shape, c->db, c->pmap[axis] + f0, f1 - f0, arena<float>(c, from),
                                 arena<float>(c, 1 - from), static_cast<const float *>(c->baseT), c->dt,
-                                c->cnt, heat, c->stream);
+                                c->cnt, heat, c->base64, c->work, cfl, c->stream);
     if (e != hipSuccess) return hipfail(c, e, "sweep launch");
     if (c->profiling) {
         HIPCHK(c, hipEventRecord(tm.b, c->stream));
@@ -317,35 +323,51 @@ static bool any_heat(ppmb_ctx *c)
     return false;
 }
 
-// Three passes (x,y,z on even steps, z,y,x on odd) for bricks [b0, b1).
+// Three passes (x,y,z on even steps, z,y,x on odd) for bricks [b0, b1);
+// the last one also reduces the CFL maxima of the new state.
 static ppmb_status enqueue_passes(ppmb_ctx *c, int b0, int b1, int from)
 {
     const int heat = any_heat(c) ? 1 : 0;
     const int order[2][3] = { { 0, 1, 2 }, { 2, 1, 0 } };
     const int *o = order[c->nstep & 1];
     for (int p = 0; p < 3; ++p) {
-        TRY(enqueue_pass(c, o[p], p == 2 ? heat : 0, b0, b1, from));
+        if (p == 2) HIPCHK(c, launch_cfl_reset(c->work, b0, b1 - b0, c->stream));
+        TRY(enqueue_pass(c, o[p], p == 2 ? heat : 0, b0, b1, from, p == 2 ? 1 : 0));
         from = 1 - from;
     }
     return PPMB_OK;
+}
+
+// dt of bricks [b0, b1) for the coming step: from the maxima the previous
+// step's last pass left in work[] when they describe the current state,
+// else by a CFL reduction over the state.
+static ppmb_status enqueue_dt(ppmb_ctx *c, bool ready, double cfl, int b0, int b1)
+{
+    if (ready) {
+        HIPCHK(c, launch_cfl_finish(c->db, b0, b1 - b0, c->work, cfl, c->dt, c->stream));
+        return PPMB_OK;
+    }
+    return enqueue_cfl(c, cfl, b0, b1);
 }
 
 // One step of every brick: a launch per stage covering all bricks
 // (batched) or one launch per stage and brick (per_brick).
 static ppmb_status enqueue_step(ppmb_ctx *c, bool with_cfl, double cfl, bool per_brick)
 {
+    const bool ready = c->cfl_ready;
     if (per_brick) {
         for (int b = 0; b < c->nb; ++b) {
-            if (with_cfl) TRY(enqueue_cfl(c, cfl, b, b + 1));
+            if (with_cfl) TRY(enqueue_dt(c, ready, cfl, b, b + 1));
             TRY(enqueue_passes(c, b, b + 1, c->cur));
         }
     } else {
-        if (with_cfl) TRY(enqueue_cfl(c, cfl, 0, c->nb));
+        if (with_cfl) TRY(enqueue_dt(c, ready, cfl, 0, c->nb));
         TRY(enqueue_passes(c, 0, c->nb, c->cur));
     }
     c->cur = 1 - c->cur;           // three passes: the state ends in the other arena
     c->nstep++;
     c->steps++;
+    c->cfl_ready = true;
     return PPMB_OK;
 }
 
@@ -359,6 +381,7 @@ static ppmb_status check_flag(ppmb_ctx *c)
     if (bad) {
         HIPCHK(c, launch_zero_u64(c->work, 2 * c->nb, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->cfl_ready = false;
         return fail(c, PPMB_ERR_NONPHYSICAL, "non-positive density or pressure, or NaN, in a fluid cell");
     }
     return PPMB_OK;
@@ -430,6 +453,7 @@ ppmb_status ppmb_bind_state(ppmb_ctx *c, void *a, void *b)
     c->buf[0] = a;
     c->buf[1] = b;
     c->cur = 0;
+    c->cfl_ready = false;
     return PPMB_OK;
 }
 
@@ -446,6 +470,7 @@ ppmb_status ppmb_brick_set_base_state(ppmb_ctx *c, int brick, int kind, const do
     if (brick < 0 || brick >= c->nb) return fail(c, PPMB_ERR_INVALID, "brick index out of range");
     const Brick &B = c->hb[brick];
     if (kind < 0 || kind > 3) return fail(c, PPMB_ERR_INVALID, "set_base_state: unknown kind");
+    c->cfl_ready = false;
     if (kind != PPMB_BASE_NONE && !params) return fail(c, PPMB_ERR_INVALID, "set_base_state: params required");
     if (kind == PPMB_BASE_POLY_Z && B.g.grav_kind != PPMB_GRAV_CONST)
         return fail(c, PPMB_ERR_INVALID, "POLY_Z needs constant gravity");
@@ -505,6 +530,7 @@ ppmb_status ppmb_get_base(ppmb_ctx *c, double *host_rho0, double *host_p0)
 static ppmb_status set_state_dev(ppmb_ctx *c, int brick, const double *const dev_prim[15])
 {
     TRY(check_brick(c, brick));
+    c->cfl_ready = false;
     const Brick &B = c->hb[brick];
     for (int q = 0; q < NF; ++q)
         if (!dev_prim[q]) return fail(c, PPMB_ERR_INVALID, "set_state: null field");
@@ -535,6 +561,7 @@ ppmb_status ppmb_brick_set_state(ppmb_ctx *c, int brick, const double *const hos
 {
     if (!c || !host_prim) return PPMB_ERR_INVALID;
     TRY(check_brick(c, brick));
+    c->cfl_ready = false;
     for (int q = 0; q < NF; ++q)
         if (!host_prim[q]) return fail(c, PPMB_ERR_INVALID, "set_state: null field");
     const Brick &B = c->hb[brick];
@@ -628,6 +655,7 @@ ppmb_status ppmb_set_conserved(ppmb_ctx *c, const double *const host_cons[15])
 {
     if (!c || !host_cons) return PPMB_ERR_INVALID;
     TRY(check_brick(c, 0));
+    c->cfl_ready = false;
     const Brick &B = c->hb[0];
     const long n = B.ncell;
     Staging st;
@@ -650,6 +678,7 @@ ppmb_status ppmb_compute_dt(ppmb_ctx *c, double cfl, double *dt_out)
     if (!c || !dt_out || !(cfl > 0)) return PPMB_ERR_INVALID;
     TRY(need_state(c));
     TRY(enqueue_cfl(c, cfl, 0, c->nb));
+    c->cfl_ready = true;
     TRY(check_flag(c));
     HIPCHK(c, hipMemcpy(dt_out, c->dt, sizeof(double), hipMemcpyDeviceToHost));
     return PPMB_OK;
@@ -678,6 +707,12 @@ static ppmb_status graph_steps(ppmb_ctx *c, double cfl, int nsteps)
 {
     int pairs = nsteps / 2;
     if (pairs > 0) {
+        // the captured steps take dt from the maxima in work[]: make them
+        // describe the current state first
+        if (!c->cfl_ready) {
+            TRY(enqueue_cfl(c, cfl, 0, c->nb));
+            c->cfl_ready = true;
+        }
         if (!c->gexec || c->gkey_cur != c->cur || c->gkey_par != (int)(c->nstep & 1) || c->gkey_cfl != cfl) {
             free_graph(c);
             const int cur0 = c->cur;
@@ -737,6 +772,7 @@ ppmb_status ppmb_pass(ppmb_ctx *c, int axis, double dt, int heat)
     for (int b = 0; b < c->nb; ++b) HIPCHK(c, launch_set_scalar(c->dt + b, dt, c->stream));
     TRY(enqueue_pass(c, axis, heat ? (any_heat(c) ? 1 : 0) : 0, 0, c->nb, c->cur));
     c->cur = 1 - c->cur;
+    c->cfl_ready = false;
     return PPMB_OK;
 }
 
@@ -842,6 +878,7 @@ ppmb_status ppmb_autotune(ppmb_ctx *c, double cfl, int reps, const char *cache_p
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(saved, c->cnt, sizeof saved, hipMemcpyDeviceToHost));
     TRY(enqueue_cfl(c, cfl, 0, c->nb));
+    c->cfl_ready = true;                 // the passes below leave the state as it is
     TRY(check_flag(c));
     const bool prof = c->profiling;
     c->profiling = false;

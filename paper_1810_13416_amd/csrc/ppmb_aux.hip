@@ -295,7 +295,6 @@ __global__ __launch_bounds__(256) void cfl_kernel(const Brick *bricks, const Blo
     const long nc = B.ncell;
     const T *S = arena + B.off;
     const double *rho0 = base64 + B.boff, *p0 = base64 + B.boff + nc;
-    const double gm1 = g.gamma - 1.0;
     const long c0 = (long)m.local * kCflBlockCells;
     const long c1 = c0 + kCflBlockCells < nc ? c0 + kCflBlockCells : nc;
     double smax = 0.0;
@@ -307,14 +306,11 @@ __global__ __launch_bounds__(256) void cfl_kernel(const Brick *bricks, const Blo
             int k = (int)(c / ((long)g.n[0] * g.n[1]));
             if (solid_at(g, centre(g, 0, i), centre(g, 1, j), centre(g, 2, k))) continue;
         }
-        double mx = S[MX * nc + c], my = S[MY * nc + c], mz = S[MZ * nc + c];
-        double rho = rho0[c] + (double)S[RHO * nc + c];
-        double u = mx / rho, v = my / rho, w = mz / rho;
-        double pp = gm1 * ((double)S[EN * nc + c] - 0.5 * (mx * u + my * v + mz * w));
-        double p = p0[c] + pp;
-        double cs = sqrt(g.gamma * p / rho);
-        double sp = fmax(fabs(u), fmax(fabs(v), fabs(w))) + cs;
-        if (!(rho > 0.0) || !(p > 0.0) || !(sp == sp) || sp > 1e300) bad = true;
+        bool b;
+        const double sp = cell_speed(rho0[c], p0[c], (double)S[RHO * nc + c], (double)S[MX * nc + c],
+                                     (double)S[MY * nc + c], (double)S[MZ * nc + c],
+                                     (double)S[EN * nc + c], g.gamma, b);
+        if (b) bad = true;
         else if (sp > smax) smax = sp;
     }
     // wave64 max, then one atomic per wave (positive doubles order like their bits)
@@ -334,6 +330,19 @@ __global__ void cfl_finish_kernel(const Brick *bricks, int b0, int nb, const uns
         double smax = __longlong_as_double((long long)work[2 * (b0 + b)]);
         dt[B.dti] = cfl * B.g.dx / smax;
     }
+}
+
+hipError_t launch_cfl_reset(unsigned long long *work, int b0, int nb, hipStream_t st)
+{
+    hipLaunchKernelGGL(cfl_reset_kernel, dim3(1), dim3(256), 0, st, work, b0, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl_finish(const Brick *bricks, int b0, int nb, const unsigned long long *work, double cfl,
+                             double *dt, hipStream_t st)
+{
+    hipLaunchKernelGGL(cfl_finish_kernel, dim3(1), dim3(256), 0, st, bricks, b0, nb, work, cfl, dt);
+    return hipGetLastError();
 }
 
 template <typename T>

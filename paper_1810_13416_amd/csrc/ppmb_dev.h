@@ -168,6 +168,26 @@ __device__ __forceinline__ void fluid_interval(const Geom &g, int axis, const do
     hi = a;
 }
 
+// Largest signal speed max_d |u_d| + c of one cell from its stored
+// conserved perturbations and FP64 base, in FP64 without contraction, so
+// that it is the same number wherever it is evaluated (the CFL kernel and
+// the last pass of a step).  `bad`: non-positive density or pressure, NaN
+// or overflow.
+__device__ __forceinline__ double cell_speed(double r0, double p0, double rp, double mx, double my,
+                                             double mz, double ep, double gamma, bool &bad)
+{
+#pragma clang fp contract(off)
+    const double gm1 = gamma - 1.0;
+    const double rho = r0 + rp;
+    const double u = mx / rho, v = my / rho, w = mz / rho;
+    const double pp = gm1 * (ep - 0.5 * (mx * u + my * v + mz * w));
+    const double p = p0 + pp;
+    const double cs = sqrt(gamma * p / rho);
+    const double sp = fmax(fabs(u), fmax(fabs(v), fabs(w))) + cs;
+    bad = !(rho > 0.0) || !(p > 0.0) || !(sp == sp) || sp > 1e300;
+    return sp;
+}
+
 // ---------------------------------------------------------------------
 // PPM reconstruction (Sec. 1)
 // ---------------------------------------------------------------------
@@ -206,14 +226,14 @@ __device__ __forceinline__ T smooth_weight(T q0, T q1, T q2, T q3, T q4)
 template <typename T>
 __device__ __forceinline__ T smooth_weight_d(T d0, T d1, T d2)
 {
-    if (d0 == T(0) && d1 == T(0) && d2 == T(0)) return T(1);
-    bool same = (d0 > T(0) && d1 > T(0) && d2 > T(0)) || (d0 < T(0) && d1 < T(0) && d2 < T(0));
-    if (!same) return T(0);
-    T a0 = tabs(d0), a1 = tabs(d1), a2 = tabs(d2);
-    T mx = tmax(a0, tmax(a1, a2)), mn = tmin(a0, tmin(a1, a2));
-    if (mx <= T(2) * mn) return T(1);
-    if (mx >= T(3) * mn) return T(0);
-    return (T(3) * mn - mx) * trcp(mn);
+    // one strict sign <=> the smallest is > 0 or the largest is < 0
+    const T lo = tmin(d0, tmin(d1, d2)), hi = tmax(d0, tmax(d1, d2));
+    const T a0 = tabs(d0), a1 = tabs(d1), a2 = tabs(d2);
+    const T mx = tmax(a0, tmax(a1, a2)), mn = tmin(a0, tmin(a1, a2));
+    const T r = (T(3) * mn - mx) * trcp(mn);
+    T w = mx <= T(2) * mn ? T(1) : (mx >= T(3) * mn ? T(0) : r);
+    w = (lo > T(0) || hi < T(0)) ? w : T(0);
+    return mx == T(0) ? T(1) : w;
 }
 
 // van Leer limited slope (CW84 eq. 1.8).
@@ -512,16 +532,16 @@ template <typename T>
 __device__ __forceinline__ bool parabola(int detect, T q, T qfL, T qfR, T flL, T flR, T d0, T d1, T d2,
                                          T &l, T &r)
 {
-    T ws = detect == 1 ? smooth_weight_d(d0, d1, d2) : T(detect == 2 ? 1 : 0);
-    l = qfL;
-    r = qfR;
-    if (!(ws < T(1))) return false;
+    // branch-free: in a wave some cell is nearly always constrained
+    const T ws = detect == 1 ? smooth_weight_d(d0, d1, d2) : T(detect == 2 ? 1 : 0);
     T lc = flL, rc = flR;
     constrain(q, lc, rc);
-    if (ws > T(0)) { lc = lc + ws * (l - lc); rc = rc + ws * (r - rc); }
-    l = lc;
-    r = rc;
-    return true;
+    const bool con = ws < T(1);
+    const bool blend = ws > T(0);
+    const T lb = lc + ws * (qfL - lc), rb = rc + ws * (qfR - rc);
+    l = con ? (blend ? lb : lc) : qfL;
+    r = con ? (blend ? rb : rc) : qfR;
+    return con;
 }
 
 // Characteristic tracing of one cell (CW84 Sec. 3): the states at its right

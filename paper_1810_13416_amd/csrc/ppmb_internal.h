@@ -38,11 +38,15 @@ struct PassShape {
 int pass_blocks(const Geom &g, int axis, const PassShape &sh);
 
 // Fused 1-D pass along `axis` for the bricks whose blocks are
-// map[0 .. nblocks): one launch, every brick's pencils.
+// map[0 .. nblocks): one launch, every brick's pencils.  With `cfl` set the
+// pass also folds the signal speed of every fluid cell it writes into the
+// CFL reduction slots work[2 brick] (max, as in the CFL kernel) and
+// work[2 brick + 1] (non-physical flag); base64 is the FP64 base arena.
 template <typename T>
 hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, const BlockMap *map,
                         int nblocks, const T *in, T *out, const T *base, const double *dt,
-                        unsigned long long *counters, int heat, hipStream_t st);
+                        unsigned long long *counters, int heat, const double *base64,
+                        unsigned long long *work, int cfl, hipStream_t st);
 
 // hydrostatic base state: FP64 RK4 node table (one thread), then cell values
 hipError_t launch_base_state(const Geom &g, int kind, const double *params, double *table,
@@ -86,6 +90,12 @@ template <typename T>
 hipError_t launch_totals(const Geom &g, const T *state, const double *rho0, const double *p0,
                          double *partials, double *out, hipStream_t st);
 constexpr int kTotalsBlocks = 1024;
+
+// the two ends of launch_cfl on their own: zero the maxima of bricks
+// [b0, b0 + nb); dt from the maxima already in work
+hipError_t launch_cfl_reset(unsigned long long *work, int b0, int nb, hipStream_t st);
+hipError_t launch_cfl_finish(const Brick *bricks, int b0, int nb, const unsigned long long *work, double cfl,
+                             double *dt, hipStream_t st);
 
 hipError_t launch_set_scalar(double *dst, double v, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long *dst, int count, hipStream_t st);

@@ -24,8 +24,11 @@ struct SweepArgs {
     const T *p0;
     const double *dtp;    // this brick's dt
     unsigned long long *counters;   // limiter, unsmooth, riemann
+    const double *r064;   // FP64 base state (for the fused CFL reduction)
+    const double *p064;
     long ncell;
     int heat;             // 1: add the heating source after the update
+    int cfl;              // 1: fold the written cells' signal speeds into the CFL slots
 };
 
 // Arguments of one pass launch over a batch of bricks.
@@ -38,14 +41,43 @@ struct BatchArgs {
     const T *base;
     const double *dt;
     unsigned long long *counters;
+    const double *base64;
+    unsigned long long *work;     // CFL slots, two per brick
     int heat;
+    int cfl;
 };
 
 template <typename T>
 __device__ __forceinline__ SweepArgs<T> brick_args(const BatchArgs<T> &b, const Brick &B)
 {
     return SweepArgs<T>{b.in + B.off, b.out + B.off, b.base + B.boff, b.base + B.boff + B.ncell,
-                        b.dt + B.dti, b.counters, B.ncell, b.heat};
+                        b.dt + B.dti, b.counters, b.base64 + B.boff, b.base64 + B.boff + B.ncell,
+                        B.ncell, b.heat, b.cfl};
+}
+
+// Global (x, y, z) order of a pass's (normal, t1, t2) components.
+template <int AX, typename T>
+__device__ __forceinline__ void to_global(T n, T t1, T t2, T &x, T &y, T &z)
+{
+    T c[3];
+    c[AX] = n;
+    c[(AX + 1) % 3] = t1;
+    c[(AX + 2) % 3] = t2;
+    x = c[0];
+    y = c[1];
+    z = c[2];
+}
+
+// One wave's share of the CFL reduction: maximum and non-physical flag over
+// its lanes into the brick's slots (positive doubles order like their bits).
+__device__ __forceinline__ void cfl_commit(unsigned long long *work, int brick, double smax, bool bad)
+{
+    for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_down(smax, off));
+    const unsigned long long bb = __ballot(bad);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&work[2 * brick], (unsigned long long)__double_as_longlong(smax));
+        if (bb) atomicOr(&work[2 * brick + 1], 1ull);
+    }
 }
 
 template <bool B>
@@ -145,7 +177,7 @@ struct AxisInfo {
 // March one pencil; la / lb index it across the lane and block axes.
 template <typename T, int AX>
 __device__ void march(const Geom &g, const SweepArgs<T> &a, int la0, int lane, int lb,
-                      unsigned long long &c_lim, unsigned long long &c_uns, unsigned long long &c_rie)
+                      unsigned &c_lim, unsigned &c_uns, unsigned &c_rie, double &cmax, bool &cbad)
 {
     using AI = AxisInfo<AX>;
     const int nx = g.n[0], ny = g.n[1];
@@ -263,6 +295,10 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la0, int lane, i
         cu3[2] = bld<T>(rin(MX + AI::t1, c3), ld3);
         cu3[3] = bld<T>(rin(MX + AI::t2, c3), ld3);
         cu3[4] = bld<T>(rin(EN, c3), ld3);
+        // its FP64 base, for the fused CFL reduction of the last pass
+        const unsigned ic = a.cfl ? ld3 : kNoIdx;
+        const double br0 = bld<double>(rsrc(a.r064 + ubase + c3 * sAX, rcnt), ic);
+        const double bp0 = bld<double>(rsrc(a.p064 + ubase + c3 * sAX, rcnt), ic);
         {
             T xd = ox + (T(s) + T(0.5)) * dxT;
             T gv = flT * gravity<T>(g, AX, xd, rtt + xd * xd);
@@ -367,6 +403,15 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la0, int lane, i
             bst(rout(MX + AI::t1, c3), st3, hn[2]);
             bst(rout(MX + AI::t2, c3), st3, hn[3]);
             bst(rout(EN, c3), st3, hn[4]);
+            // the next step's CFL reduction from the values just written
+            if (a.cfl && upd && valid && !sol[1]) {
+                double mx, my, mz;
+                to_global<AX, double>(hn[1], hn[2], hn[3], mx, my, mz);
+                bool bd;
+                const double sp = cell_speed(br0, bp0, (double)hn[0], mx, my, mz, (double)hn[4], g.gamma, bd);
+                if (bd) cbad = true;
+                else cmax = fmax(cmax, sp);
+            }
         }
         // ---- (7) PPB: donor k-3, slab at face (k-4)+1/2, update cell k-4
         if (S || k >= 2) {
@@ -449,8 +494,11 @@ void sweep_kernel(BatchArgs<T> b)
     const int nblk_a = (g.n[ca] + 63) / 64;
     const int la0 = (m.local % nblk_a) * 64;
     const int lb = (m.local / nblk_a) * waves + wv;
-    unsigned long long c_lim = 0, c_uns = 0, c_rie = 0;
-    if (lb < g.n[cb]) march<T, AX>(g, a, la0, (int)(threadIdx.x & 63), lb, c_lim, c_uns, c_rie);
+    unsigned c_lim = 0, c_uns = 0, c_rie = 0;          // per lane; widened below
+    double cmax = 0.0;
+    bool cbad = false;
+    if (lb < g.n[cb]) march<T, AX>(g, a, la0, (int)(threadIdx.x & 63), lb, c_lim, c_uns, c_rie, cmax, cbad);
+    if (b.cfl) cfl_commit(b.work, m.brick, cmax, cbad);
     // event counters: one atomic per wave and counter
     unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
     for (int off = 32; off > 0; off >>= 1) {
@@ -575,7 +623,9 @@ void sweep_x_kernel(BatchArgs<T> b)
     const T gam = T(g.gamma), gm1 = T(g.gamma - 1.0), gfac = T(g.gamma / (g.gamma - 1.0));
     const T ox = T(g.origin[0]), dxT = T(g.dx);
     const int bc = g.bc[0];
-    unsigned long long c_lim = 0, c_uns = 0, c_rie = 0;
+    unsigned c_lim = 0, c_uns = 0, c_rie = 0;          // per lane; widened below
+    double cmax = 0.0;                                 // fused CFL reduction
+    bool cbad = false;
 
     XIn<T> cur;
     x_load(a.in, a.rho0, a.p0, nc, row, nx, bc, -NG + lane, cur);
@@ -718,8 +768,20 @@ void sweep_x_kernel(BatchArgs<T> b)
             bst(fo(EN), io, hn[4]);
 #pragma unroll
             for (int v = 0; v < 10; ++v) bst(fo(AI::ppb(v)), io, o[v]);
+            // the next step's CFL reduction from the values just written
+            const unsigned ic = a.cfl ? (unsigned)s : kNoIdx;
+            const double br0 = bld<double>(rsrc(a.r064 + row, nx), ic);
+            const double bp0 = bld<double>(rsrc(a.p064 + row, nx), ic);
+            if (a.cfl && own && !so) {
+                bool bd;
+                const double sp = cell_speed(br0, bp0, (double)hn[0], (double)hn[1], (double)hn[2],
+                                             (double)hn[3], (double)hn[4], g.gamma, bd);
+                if (bd) cbad = true;
+                else cmax = fmax(cmax, sp);
+            }
         }
     }
+    if (a.cfl) cfl_commit(b.work, m.brick, cmax, cbad);
     unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
     for (int off = 32; off > 0; off >>= 1) {
         s0 += __shfl_down(s0, off);
@@ -755,10 +817,11 @@ int pass_blocks(const Geom &g, int axis, const PassShape &sh)
 template <typename T>
 hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, const BlockMap *map,
                         int nblocks, const T *in, T *out, const T *base, const double *dt,
-                        unsigned long long *counters, int heat, hipStream_t st)
+                        unsigned long long *counters, int heat, const double *base64,
+                        unsigned long long *work, int cfl, hipStream_t st)
 {
     if (nblocks <= 0) return hipErrorInvalidValue;
-    BatchArgs<T> a{bricks, map, in, out, base, dt, counters, heat};
+    BatchArgs<T> a{bricks, map, in, out, base, dt, counters, base64, work, heat, cfl};
     if (axis == 0 && x_lanes_enabled()) {
         hipLaunchKernelGGL((sweep_x_kernel<T>), dim3(nblocks), dim3(64 * sh.x_waves), 0, st, a);
         return hipGetLastError();
@@ -774,9 +837,11 @@ hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, cons
 
 template hipError_t launch_sweep<float>(int, const PassShape &, const Brick *, const BlockMap *, int,
                                         const float *, float *, const float *, const double *,
-                                        unsigned long long *, int, hipStream_t);
+                                        unsigned long long *, int, const double *, unsigned long long *,
+                                        int, hipStream_t);
 template hipError_t launch_sweep<double>(int, const PassShape &, const Brick *, const BlockMap *, int,
                                          const double *, double *, const double *, const double *,
-                                         unsigned long long *, int, hipStream_t);
+                                         unsigned long long *, int, const double *, unsigned long long *,
+                                         int, hipStream_t);
 
 }  // namespace ppmb

@@ -287,3 +287,27 @@ def test_counters_match_oracle_fp64():
     assert cg[3] == co[3] == 5
     assert cg[0] == co[0] and cg[2] == co[2]
     assert abs(cg[1] - co[1]) <= 1e-4 * co[1]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_fused_cfl_reduction_equals_cfl_kernel(prec):
+    # the last pass of a step folds the next step's CFL maxima in; the dt
+    # it gives must be the CFL kernel's dt on the same state, bit for bit
+    # (sphere: solid cells excluded; heating in the last pass)
+    prob = pr.config3(n=24)
+    A = sim(prob.params, prec)
+    A.set_state(prob.state)
+    A.step_auto(prob.cfl, 3)
+    B = sim(prob.params, prec)
+    B.set_state(prob.state)
+    B.step_auto(prob.cfl, 2)
+    assert A.last_dt() == B.dt(prob.cfl)
+    # after a state change the next step recomputes from the state
+    C = sim(prob.params, prec)
+    C.set_state(prob.state)
+    C.step_auto(prob.cfl, 1)
+    C.set_state(prob.state)
+    C.step_auto(prob.cfl, 1)
+    D = sim(prob.params, prec)
+    D.set_state(prob.state)
+    assert C.last_dt() == D.dt(prob.cfl)
