@@ -1,7 +1,7 @@
 """Throughput of the PPM + PPB 3-D step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu]
-                    [--calib-copy-mib M]
+                    [--no-bricks] [--no-accuracy] [--calib-copy-mib M]
 
 Workload: the spherical convection shell on a 512^3 grid (FP32 perturbation
 form on an FP64 radial hydrostatic base, radial gravity, heating, confining
@@ -18,7 +18,14 @@ The JSON carries
                 per launch from the committed hardware-counter summary, or
                 null when the pass sources differ from the ones counted;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same recipe;
-  fp64          the same grid and steps in FP64 on the same GPU.
+  fp64          the same grid and steps in FP64 on the same GPU;
+  bricks        256 independent bricks (16..64 cells per axis) advanced
+                together in FP32: one launch per stage for all bricks, the
+                same replayed from a HIP graph, and one launch per stage and
+                brick, after the launch-shape autotuner;
+  accuracy      the stratified box at 128^3 in FP32 and FP64 against the
+                same at 256^3 in FP64 (fixed dt, restricted to 128^3): the
+                FP32 round-off error against the truncation error.
 """
 from __future__ import annotations
 
@@ -101,6 +108,98 @@ def calib_copy(mib):
     torch.cuda.empty_cache()
 
 
+def run_bricks(steps, warmup):
+    """The batched-brick workload in each launch mode (FP32)."""
+    import numpy as np
+    import torch
+    from paper_1810_13416_amd import ppmb, problems
+    probs = problems.bricks()
+    cells = int(sum(int(np.prod(p.params.n)) for p in probs))
+    cfl = 0.8
+    out = {"bricks": len(probs), "cells": cells, "modes": {}}
+    shape = None
+    for mode, name in ((0, "batched"), (1, "graph"), (2, "per_brick")):
+        B = ppmb.Batch([p.params for p in probs], ppmb.FP32)
+        for b, p in enumerate(probs):
+            B.set_state(b, p.state)
+        if shape is None:
+            shape = B.autotune(cfl, reps=2)
+            out["autotuned_shape"] = {"march_waves": shape[0], "x_waves": shape[1]}
+        else:
+            B.set_shape(*shape)
+        B.step(cfl, warmup, mode)
+        B.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(B.stream)
+        B.step(cfl, steps, mode)
+        e1.record(B.stream)
+        B.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out["modes"][name] = {"ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3)}
+        log(f"bricks {name}: {ms:.3f} ms/step")
+        B.close()
+        del B
+        torch.cuda.empty_cache()
+    return out
+
+
+def _restrict(a):
+    """Average 2x2x2 blocks (z, y, x arrays)."""
+    n0, n1, n2 = a.shape
+    return a.reshape(n0 // 2, 2, n1 // 2, 2, n2 // 2, 2).mean(axis=(1, 3, 5))
+
+
+def run_accuracy(nsteps=200):
+    """FP32 round-off against truncation error on the stratified box."""
+    import numpy as np
+    from paper_1810_13416_amd import ppmb, problems
+    # no per-cell noise: both resolutions sample the same continuous flow
+    fine = problems.config2(n=256, noise=0.0)
+    coarse = problems.config2(n=128, noise=0.0)
+    F = ppmb.Sim(fine.params, ppmb.FP64, device="cuda:0")
+    F.set_state(fine.state)
+    dt = F.dt(fine.cfl)                 # CFL 0.8 on the fine grid, used by all runs
+    for _ in range(nsteps):
+        F.step(dt)
+    sf = F.get_state()
+    bf0, _ = F.base()
+    F.close()
+    del F, fine
+    res = {}
+    for prec, name in ((ppmb.FP64, "fp64"), (ppmb.FP32, "fp32")):
+        C = ppmb.Sim(coarse.params, prec, device="cuda:0")
+        C.set_state(coarse.state)
+        for _ in range(nsteps):
+            C.step(dt)
+        res[name] = C.get_state()
+        if name == "fp64":
+            bc0, _ = C.base()
+        C.close()
+        del C
+
+    def rel(a, b):
+        return float(np.sum(np.abs(a - b)) / max(np.sum(np.abs(b)), 1e-300))
+
+    fields = {"u_x": 1, "u_y": 2, "u_z": 3, "p'": 4}
+    out = {"grid": "128^3 vs 256^3 restricted", "steps": nsteps, "dt": dt, "fields": {}}
+    worst = 0.0
+    for k, q in fields.items():
+        trunc = rel(res["fp64"][q], _restrict(sf[q]))
+        rnd = rel(res["fp32"][q], res["fp64"][q])
+        out["fields"][k] = {"truncation_relL1": trunc, "fp32_roundoff_relL1": rnd,
+                            "ratio": rnd / trunc if trunc > 0 else None}
+        if trunc > 0:
+            worst = max(worst, rnd / trunc)
+    rho_c = bc0 + res["fp64"][0]
+    rho_f = bf0 + sf[0]
+    out["fields"]["rho"] = {"truncation_relL1": rel(rho_c, _restrict(rho_f)),
+                            "fp32_roundoff_relL1": rel(bc0 + res["fp32"][0], rho_c)}
+    out["worst_velocity_pressure_ratio"] = worst
+    out["equal_accuracy"] = bool(worst <= 0.1)
+    return out
+
+
 def cpu_baseline(n=256, steps=8):
     import numpy as np  # noqa: F401
     import oracle
@@ -129,6 +228,8 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-bricks", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -206,6 +307,12 @@ def main():
         out["fp64"] = {"value": cells / (r64["ms_per_step"] * 1e-3), "unit": "cell-updates/s",
                        "ms_per_step": r64["ms_per_step"], "pass_ms": r64["pass_ms"],
                        "speedup_fp32_over_fp64": r64["ms_per_step"] / r32["ms_per_step"]}
+    if not args.no_bricks:
+        log("batched bricks")
+        out["bricks"] = run_bricks(max(5, args.steps // 2), 2)
+    if not args.no_accuracy:
+        log("accuracy: FP32 round-off vs truncation error")
+        out["accuracy"] = run_accuracy()
     if not args.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()

@@ -240,14 +240,16 @@ def config2_gravity(gamma=5.0 / 3.0, ratio=0.1, z_i=0.8, f_jump=0.5):
 
 
 def config2(n: int = 128, seed: int = 1812, base: str = "poly", nsteps: int = 200,
-            mach: float = 0.03) -> Problem:
+            mach: float = 0.03, noise: float = 1e-3) -> Problem:
     """Stratified box: x, y periodic on [0,1), z in [0,1] between reflecting
     walls, constant gravity -g0 z-hat, hydrostatic piecewise-polytrope base
     (density falls 10x over the box; a 0.5 density jump at z = 0.8 marks the
     light, entrainable fluid), heating in z < 0.1, fv = 1 for z >= 0.8,
     seeded 1e-3 pressure noise below z = 0.8, plus a seeded divergence-free
     horizontal flow confined to z < 0.75 at rms Mach `mach`.
-    base = 'poly' (perturbation form) or 'none' (plain: full fields)."""
+    base = 'poly' (perturbation form) or 'none' (plain: full fields).
+    The flow's modes are drawn before the per-cell noise, so that with
+    noise = 0 the data at two resolutions sample one continuous field."""
     rng = np.random.Generator(np.random.PCG64(seed))
     gamma = 5.0 / 3.0
     g0 = config2_gravity(gamma)
@@ -259,14 +261,18 @@ def config2(n: int = 128, seed: int = 1812, base: str = "poly", nsteps: int = 20
     P.base = (1.0, 1.0, 0.0, 0.8, 0.5, 1.0)
     Z, Y, X = _mesh(P)
     rho_cf, p_cf = polytrope_closed_form(Z[:, 0, 0], 1.0, 1.0, gamma, -g0, 0.0, 0.8, 0.5)
-    noise = rng.uniform(-1.0, 1.0, size=P.shape)
-    pp = np.where(Z < 0.8, 1e-3 * p_cf[:, None, None] * noise, 0.0)
+    modes = []
+    for d in range(2):
+        dirs = _lattice_dirs(rng, d, 4)
+        phases = rng.uniform(0.0, 2.0 * math.pi, size=4)
+        modes.append((dirs, phases))
+    cell_noise = rng.uniform(-1.0, 1.0, size=P.shape)
+    pp = np.where(Z < 0.8, noise * p_cf[:, None, None] * cell_noise, 0.0)
     env = np.where(Z < 0.75, np.sin(math.pi * Z / 0.75) ** 2, 0.0)
     c_ref = math.sqrt(gamma)
     vel = [_zeros(P), _zeros(P), _zeros(P)]
     for d in range(2):
-        dirs = _lattice_dirs(rng, d, 4)
-        phases = rng.uniform(0.0, 2.0 * math.pi, size=4)
+        dirs, phases = modes[d]
         u = _zeros(P)
         for k in range(4):
             a = 2.0 * math.pi * (k + 1) * dirs[k]
