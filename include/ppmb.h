@@ -18,8 +18,12 @@
  *   - Returns ppmb_status; 0 (PPMB_OK) is success.  No C++ exception crosses
  *     the ABI.  ppmb_last_error() gives a text for the last failure of a
  *     context.
- *   - Grids are x-fastest structure-of-arrays: field q of cell (i, j, k) sits
- *     at element q * ncell + (k * ny + j) * nx + i, ncell = nx * ny * nz.
+ *   - Host and device exchange arrays (set/get state, conserved, base) are
+ *     dense x-fastest: element (k * ny + j) * nx + i of each field.
+ *   - The library's device state is a pitched structure-of-arrays: field q
+ *     of cell (i, j, k) sits at element q * fs + k * plane + j * px + i,
+ *     with rows padded to px (a multiple of 64), plane = px * ny and a
+ *     padded field stride fs; ppmb_state_layout() gives the numbers.
  *   - Host pointers are named host_*; device pointers dev_*.  The library
  *     never frees memory it did not allocate.
  *   - Calls that take a context enqueue work on the context's HIP stream and
@@ -113,9 +117,17 @@ ppmb_status ppmb_create(const ppmb_grid *grid, ppmb_precision prec, void *hip_st
 /* Synchronise the stream, then free the library's buffers and the context. */
 ppmb_status ppmb_destroy(ppmb_ctx *ctx);
 
-/* Bytes the caller must provide per state buffer: 15 * ncell * elem_size
- * (elem_size 8 for FP64, 4 for FP32). */
+/* Bytes the caller must provide per state buffer: 15 * fs * elem_size
+ * summed over bricks (elem_size 8 for FP64, 4 for FP32). */
 ppmb_status ppmb_state_bytes(const ppmb_ctx *ctx, size_t *bytes, size_t *elem_size);
+
+/* Storage layout of brick `brick` (0 for a single grid) in a state buffer:
+ * field q of cell (i, j, k) at element out[0] + q * out[1] + k * out[2]
+ * + j * out[3] + i (offset, field stride fs, plane stride, row pitch px),
+ * in elements of the working precision.  Padding elements are never read.
+ * Not synchronising.  Errors: INVALID for a NULL argument or a brick out of
+ * range. */
+ppmb_status ppmb_state_layout(const ppmb_ctx *ctx, int brick, long long out[4]);
 
 /* Bind two caller-owned device buffers of ppmb_state_bytes() each.  Passes
  * read one and write the other (ping-pong); ppmb_current_state() names the

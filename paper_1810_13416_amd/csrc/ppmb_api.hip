@@ -23,8 +23,8 @@ struct ppmb_ctx {
     int nb = 0;                         // bricks
     std::vector<Brick> hb;              // brick table (host copy)
     Brick *db = nullptr;                // brick table (device)
-    long total_state = 0;               // elements per state arena (15 * sum ncell)
-    long total_base = 0;                // elements per base arena (2 * sum ncell)
+    long total_state = 0;               // elements per state arena (15 * sum of field strides)
+    long total_base = 0;                // elements per base arena (2 * sum of field strides)
     void *buf[2] = { nullptr, nullptr };
     bool owns_state = false;
     int cur = 0;
@@ -149,7 +149,7 @@ static ppmb_status check_grid(const ppmb_grid *grid)
     if (grid->grav_kind < 0 || grid->grav_kind > 2 || grid->heat_kind < 0 || grid->heat_kind > 2)
         return PPMB_ERR_INVALID;
     if (grid->smooth_detect < 0 || grid->smooth_detect > 2) return PPMB_ERR_INVALID;
-    if ((long)grid->n[0] * grid->n[1] * grid->n[2] > (1L << 34)) return PPMB_ERR_INVALID;
+    if ((long)grid->n[0] * grid->n[1] * grid->n[2] >= (1L << 31)) return PPMB_ERR_INVALID;
     return PPMB_OK;
 }
 
@@ -185,6 +185,12 @@ static Geom geom_of(const ppmb_grid *grid)
     g.heat_kind = grid->heat_kind;
     for (int q = 0; q < 3; ++q) g.heat[q] = grid->heat[q];
     g.smooth_detect = grid->smooth_detect;
+    // pitched storage: rows padded to 64 elements (256-byte aligned in FP32),
+    // fields padded by 17 x 64 elements more, so that corresponding cells of
+    // the 15 fields do not share cache sets
+    g.px = (grid->n[0] + 63) / 64 * 64;
+    g.plane = (long)g.px * grid->n[1];
+    g.fs = (g.plane * grid->n[2] + 63) / 64 * 64 + 17 * 64;
     return g;
 }
 
@@ -208,8 +214,8 @@ static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_preci
         B.off = off;
         B.boff = boff;
         B.dti = b;
-        off += (long)NF * B.ncell;
-        boff += 2 * B.ncell;
+        off += (long)NF * B.g.fs;
+        boff += 2 * B.g.fs;
         long span = (long)(4.0 * (B.g.n[0] + B.g.n[1] + B.g.n[2]) * 8.0) + 64;
         if (span > maxspan) maxspan = span;
         c->hb.push_back(B);
@@ -219,6 +225,7 @@ static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_preci
     c->table_len = 64 + 2 * maxspan;
     hipError_t e = hipMalloc(&c->db, sizeof(Brick) * nbricks);
     if (e == hipSuccess) e = hipMalloc(&c->base64, sizeof(double) * boff);
+    if (e == hipSuccess) e = hipMemset(c->base64, 0, sizeof(double) * boff);   // padding included
     if (e == hipSuccess && prec == PPMB_FP32) e = hipMalloc(&c->baseT, sizeof(float) * boff);
     if (e == hipSuccess) e = hipMalloc(&c->table, sizeof(double) * c->table_len);
     if (e == hipSuccess) e = hipMalloc(&c->dt, sizeof(double) * nbricks);
@@ -245,7 +252,7 @@ static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_preci
     double zero[6] = { 0, 0, 0, 0, 0, 0 };
     for (int b = 0; st == PPMB_OK && b < nbricks; ++b)
         if (launch_base_state(c->hb[b].g, PPMB_BASE_NONE, zero, c->table, c->table_len,
-                              c->base64 + c->hb[b].boff, c->base64 + c->hb[b].boff + c->hb[b].ncell,
+                              c->base64 + c->hb[b].boff, c->base64 + c->hb[b].boff + c->hb[b].g.fs,
                               c->stream) != hipSuccess)
             st = PPMB_ERR_HIP;
     if (st == PPMB_OK && prec == PPMB_FP32 &&
@@ -444,6 +451,17 @@ ppmb_status ppmb_state_bytes(const ppmb_ctx *c, size_t *bytes, size_t *elem_size
     return PPMB_OK;
 }
 
+ppmb_status ppmb_state_layout(const ppmb_ctx *c, int brick, long long out[4])
+{
+    if (!c || !out || brick < 0 || brick >= c->nb) return PPMB_ERR_INVALID;
+    const Brick &B = c->hb[brick];
+    out[0] = B.off;
+    out[1] = B.g.fs;
+    out[2] = B.g.plane;
+    out[3] = B.g.px;
+    return PPMB_OK;
+}
+
 ppmb_status ppmb_bind_state(ppmb_ctx *c, void *a, void *b)
 {
     if (!c) return PPMB_ERR_INVALID;
@@ -494,9 +512,9 @@ ppmb_status ppmb_brick_set_base_state(ppmb_ctx *c, int brick, int kind, const do
         }
     }
     double *r0 = c->base64 + B.boff;
-    HIPCHK(c, launch_base_state(B.g, kind, params, c->table, c->table_len, r0, r0 + B.ncell, c->stream));
+    HIPCHK(c, launch_base_state(B.g, kind, params, c->table, c->table_len, r0, r0 + B.g.fs, c->stream));
     if (c->prec == PPMB_FP32)
-        HIPCHK(c, launch_narrow<float>(r0, static_cast<float *>(c->baseT) + B.boff, 2 * B.ncell, c->stream));
+        HIPCHK(c, launch_narrow<float>(r0, static_cast<float *>(c->baseT) + B.boff, 2 * B.g.fs, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (poly) {
         double nseg = 0;
@@ -511,14 +529,25 @@ ppmb_status ppmb_set_base_state(ppmb_ctx *c, int kind, const double params[6])
     return ppmb_brick_set_base_state(c, 0, kind, params);
 }
 
+// FP64 device staging of 15 fields for host transfers, freed on return
+struct Staging {
+    double *p = nullptr;
+    ~Staging() { if (p) hipFree(p); }
+};
+
 ppmb_status ppmb_brick_get_base(ppmb_ctx *c, int brick, double *host_rho0, double *host_p0)
 {
     if (!c || !host_rho0 || !host_p0) return PPMB_ERR_INVALID;
     if (brick < 0 || brick >= c->nb) return fail(c, PPMB_ERR_INVALID, "brick index out of range");
     const Brick &B = c->hb[brick];
+    const long n = B.ncell;
+    Staging st;
+    if (hipMalloc(&st.p, sizeof(double) * 2 * n) != hipSuccess)
+        return fail(c, PPMB_ERR_NOMEM, "get_base: staging");
+    HIPCHK(c, launch_gather<double>(B.g, 2, c->base64 + B.boff, st.p, c->stream));
+    HIPCHK(c, hipMemcpyAsync(host_rho0, st.p, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(host_p0, st.p + n, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(host_rho0, c->base64 + B.boff, sizeof(double) * B.ncell, hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(host_p0, c->base64 + B.boff + B.ncell, sizeof(double) * B.ncell, hipMemcpyDeviceToHost));
     return PPMB_OK;
 }
 
@@ -547,12 +576,6 @@ ppmb_status ppmb_set_state_device(ppmb_ctx *c, const double *const dev_prim[15])
     return set_state_dev(c, 0, dev_prim);
 }
 
-// FP64 device staging of 15 fields for host transfers, freed on return
-struct Staging {
-    double *p = nullptr;
-    ~Staging() { if (p) hipFree(p); }
-};
-
 // Host transfers go through an FP64 staging buffer of at most kChunk cells
 // per field, so that the largest grids need no full-size staging copy.
 static const long kChunk = 1L << 24;
@@ -578,11 +601,11 @@ ppmb_status ppmb_brick_set_state(ppmb_ctx *c, int brick, const double *const hos
             dev[q] = st.p + q * ch;
         }
         if (c->prec == PPMB_FP64)
-            HIPCHK(c, launch_prim_to_cons_range<double>(B.g, dev, c->base64 + B.boff + c0,
-                                                        arena<double>(c, c->cur) + B.off + c0, m, n, c->stream));
+            HIPCHK(c, launch_prim_to_cons_range<double>(B.g, dev, c->base64 + B.boff,
+                                                        arena<double>(c, c->cur) + B.off, c0, m, c->stream));
         else
-            HIPCHK(c, launch_prim_to_cons_range<float>(B.g, dev, c->base64 + B.boff + c0,
-                                                       arena<float>(c, c->cur) + B.off + c0, m, n, c->stream));
+            HIPCHK(c, launch_prim_to_cons_range<float>(B.g, dev, c->base64 + B.boff,
+                                                       arena<float>(c, c->cur) + B.off, c0, m, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     return PPMB_OK;
@@ -607,11 +630,11 @@ ppmb_status ppmb_brick_get_state(ppmb_ctx *c, int brick, double *const host_prim
     for (long c0 = 0; c0 < n; c0 += ch) {
         const long m = (n - c0) < ch ? (n - c0) : ch;
         if (c->prec == PPMB_FP64)
-            HIPCHK(c, launch_cons_to_prim_range<double>(B.g, arena<double>(c, c->cur) + B.off + c0,
-                                                        c->base64 + B.boff + c0, st.p, m, n, ch, c->stream));
+            HIPCHK(c, launch_cons_to_prim_range<double>(B.g, arena<double>(c, c->cur) + B.off,
+                                                        c->base64 + B.boff, st.p, c0, m, ch, c->stream));
         else
-            HIPCHK(c, launch_cons_to_prim_range<float>(B.g, arena<float>(c, c->cur) + B.off + c0,
-                                                       c->base64 + B.boff + c0, st.p, m, n, ch, c->stream));
+            HIPCHK(c, launch_cons_to_prim_range<float>(B.g, arena<float>(c, c->cur) + B.off,
+                                                       c->base64 + B.boff, st.p, c0, m, ch, c->stream));
         for (int q = 0; q < NF; ++q)
             HIPCHK(c, hipMemcpyAsync(host_prim[q] + c0, st.p + q * ch, sizeof(double) * m,
                                      hipMemcpyDeviceToHost, c->stream));
@@ -635,9 +658,9 @@ ppmb_status ppmb_brick_get_conserved(ppmb_ctx *c, int brick, double *const host_
     if (hipMalloc(&st.p, sizeof(double) * NF * n) != hipSuccess)
         return fail(c, PPMB_ERR_NOMEM, "get_conserved: staging");
     if (c->prec == PPMB_FP64)
-        HIPCHK(c, launch_widen<double>(arena<double>(c, c->cur) + B.off, st.p, NF * n, c->stream));
+        HIPCHK(c, launch_gather<double>(B.g, NF, arena<double>(c, c->cur) + B.off, st.p, c->stream));
     else
-        HIPCHK(c, launch_widen<float>(arena<float>(c, c->cur) + B.off, st.p, NF * n, c->stream));
+        HIPCHK(c, launch_gather<float>(B.g, NF, arena<float>(c, c->cur) + B.off, st.p, c->stream));
     for (int q = 0; q < NF; ++q) {
         if (!host_cons[q]) return fail(c, PPMB_ERR_INVALID, "get_conserved: null field");
         HIPCHK(c, hipMemcpyAsync(host_cons[q], st.p + q * n, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
@@ -666,9 +689,9 @@ ppmb_status ppmb_set_conserved(ppmb_ctx *c, const double *const host_cons[15])
         HIPCHK(c, hipMemcpyAsync(st.p + q * n, host_cons[q], sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
     }
     if (c->prec == PPMB_FP64)
-        HIPCHK(c, launch_narrow<double>(st.p, arena<double>(c, c->cur) + B.off, NF * n, c->stream));
+        HIPCHK(c, launch_scatter<double>(B.g, NF, st.p, arena<double>(c, c->cur) + B.off, c->stream));
     else
-        HIPCHK(c, launch_narrow<float>(st.p, arena<float>(c, c->cur) + B.off, NF * n, c->stream));
+        HIPCHK(c, launch_scatter<float>(B.g, NF, st.p, arena<float>(c, c->cur) + B.off, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PPMB_OK;
 }
@@ -797,10 +820,10 @@ ppmb_status ppmb_brick_totals(ppmb_ctx *c, int brick, double out[8])
     const Brick &B = c->hb[brick];
     if (c->prec == PPMB_FP64)
         HIPCHK(c, launch_totals<double>(B.g, arena<double>(c, c->cur) + B.off, c->base64 + B.boff,
-                                        c->base64 + B.boff + B.ncell, c->partials, c->out8, c->stream));
+                                        c->base64 + B.boff + B.g.fs, c->partials, c->out8, c->stream));
     else
         HIPCHK(c, launch_totals<float>(B.g, arena<float>(c, c->cur) + B.off, c->base64 + B.boff,
-                                       c->base64 + B.boff + B.ncell, c->partials, c->out8, c->stream));
+                                       c->base64 + B.boff + B.g.fs, c->partials, c->out8, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(out, c->out8, sizeof(double) * 8, hipMemcpyDeviceToHost));
     return PPMB_OK;

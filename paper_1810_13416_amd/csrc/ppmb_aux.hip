@@ -98,15 +98,16 @@ __global__ void base_fill_kernel(Geom g, int kind, BaseParams bp, const double *
     long nc = (long)g.n[0] * g.n[1] * g.n[2];
     // a table that did not fit leaves nseg = -1: write NaN, read nothing
     const int nseg_all = (kind == 2 || kind == 3) ? (int)tab[0] : 1;
-    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
+    for (long cd = blockIdx.x * (long)blockDim.x + threadIdx.x; cd < nc; cd += (long)gridDim.x * blockDim.x) {
+        const long c = pitched(g, cd);
         if (kind == 0 || kind == 1) {
             rho0[c] = (kind == 1) ? bp.v[0] : 0.0;
             p0[c] = (kind == 1) ? bp.v[1] : 0.0;
             continue;
         }
-        int i = (int)(c % g.n[0]);
-        int j = (int)((c / g.n[0]) % g.n[1]);
-        int k = (int)(c / ((long)g.n[0] * g.n[1]));
+        int i = (int)(cd % g.n[0]);
+        int j = (int)((cd / g.n[0]) % g.n[1]);
+        int k = (int)(cd / ((long)g.n[0] * g.n[1]));
         double x = centre(g, 0, i), y = centre(g, 1, j), z = centre(g, 2, k);
         double s = (kind == 2) ? z : sqrt(r2_exact(x, y, z));
         if (nseg_all < 1 || nseg_all > MAXSEG) { rho0[c] = NAN; p0[c] = NAN; continue; }
@@ -143,92 +144,74 @@ hipError_t launch_base_state(const Geom &g, int kind, const double *params, doub
 // ---------------------------------------------------------------------
 
 struct PrimPtrs { const double *p[NF]; };
-struct OutPtrs { double *p[NF]; };
 
+// Dense cells [c0, c0 + m) of a brick: FP64 primitive perturbations
+// (field q of the range at P.p[q], dense) to the stored conserved fields
+// (pitched, field stride g.fs); rho0 is the brick's pitched FP64 base.
 template <typename T>
-__global__ void prim_to_cons_kernel(long nc, double gm1, PrimPtrs P, const double *rho0, T *S)
+__global__ void prim_to_cons_kernel(Geom g, long c0, long m, double gm1, PrimPtrs P,
+                                    const double *rho0, T *S)
 {
-    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
-        double rho = rho0[c] + P.p[0][c];
-        double u = P.p[1][c], v = P.p[2][c], w = P.p[3][c];
-        S[RHO * nc + c] = T(P.p[0][c]);
-        S[MX * nc + c] = T(rho * u);
-        S[MY * nc + c] = T(rho * v);
-        S[MZ * nc + c] = T(rho * w);
-        S[EN * nc + c] = T(P.p[4][c] / gm1 + 0.5 * rho * ((u * u + v * v) + w * w));
-        for (int q = 5; q < NF; ++q) S[q * nc + c] = T(P.p[q][c]);
-    }
-}
-
-template <typename T>
-__global__ void cons_to_prim_kernel(long nc, double gm1, const T *S, const double *rho0, double *out)
-{
-    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
-        double rp = S[RHO * nc + c], mx = S[MX * nc + c], my = S[MY * nc + c], mz = S[MZ * nc + c];
-        double e = S[EN * nc + c];
-        double rho = rho0[c] + rp;
-        double u = mx / rho, v = my / rho, w = mz / rho;
-        out[0 * nc + c] = rp;
-        out[1 * nc + c] = u;
-        out[2 * nc + c] = v;
-        out[3 * nc + c] = w;
-        out[4 * nc + c] = gm1 * (e - 0.5 * (mx * u + my * v + mz * w));
-        for (int q = 5; q < NF; ++q) out[q * nc + c] = S[q * nc + c];
-    }
-}
-
-template <typename T>
-__global__ void prim_to_cons_range_kernel(long m, long stride, double gm1, PrimPtrs P,
-                                          const double *rho0, T *S)
-{
+    const long fs = g.fs;
     for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < m; c += (long)gridDim.x * blockDim.x) {
-        double rho = rho0[c] + P.p[0][c];
+        const long e = pitched(g, c0 + c);
+        double rho = rho0[e] + P.p[0][c];
         double u = P.p[1][c], v = P.p[2][c], w = P.p[3][c];
-        S[RHO * stride + c] = T(P.p[0][c]);
-        S[MX * stride + c] = T(rho * u);
-        S[MY * stride + c] = T(rho * v);
-        S[MZ * stride + c] = T(rho * w);
-        S[EN * stride + c] = T(P.p[4][c] / gm1 + 0.5 * rho * ((u * u + v * v) + w * w));
-        for (int q = 5; q < NF; ++q) S[q * stride + c] = T(P.p[q][c]);
+        S[RHO * fs + e] = T(P.p[0][c]);
+        S[MX * fs + e] = T(rho * u);
+        S[MY * fs + e] = T(rho * v);
+        S[MZ * fs + e] = T(rho * w);
+        S[EN * fs + e] = T(P.p[4][c] / gm1 + 0.5 * rho * ((u * u + v * v) + w * w));
+        for (int q = 5; q < NF; ++q) S[q * fs + e] = T(P.p[q][c]);
     }
 }
 
+// The reverse: field q of the range to out + q * ostride (dense).
 template <typename T>
-__global__ void cons_to_prim_range_kernel(long m, long stride, long ostride, double gm1, const T *S,
-                                          const double *rho0, double *out)
+__global__ void cons_to_prim_kernel(Geom g, long c0, long m, long ostride, double gm1, const T *S,
+                                    const double *rho0, double *out)
 {
+    const long fs = g.fs;
     for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < m; c += (long)gridDim.x * blockDim.x) {
-        double rp = S[RHO * stride + c], mx = S[MX * stride + c], my = S[MY * stride + c];
-        double mz = S[MZ * stride + c], e = S[EN * stride + c];
-        double rho = rho0[c] + rp;
+        const long e = pitched(g, c0 + c);
+        double rp = S[RHO * fs + e], mx = S[MX * fs + e], my = S[MY * fs + e];
+        double mz = S[MZ * fs + e], en = S[EN * fs + e];
+        double rho = rho0[e] + rp;
         double u = mx / rho, v = my / rho, w = mz / rho;
         out[0 * ostride + c] = rp;
         out[1 * ostride + c] = u;
         out[2 * ostride + c] = v;
         out[3 * ostride + c] = w;
-        out[4 * ostride + c] = gm1 * (e - 0.5 * (mx * u + my * v + mz * w));
-        for (int q = 5; q < NF; ++q) out[q * ostride + c] = S[q * stride + c];
+        out[4 * ostride + c] = gm1 * (en - 0.5 * (mx * u + my * v + mz * w));
+        for (int q = 5; q < NF; ++q) out[q * ostride + c] = S[q * fs + e];
     }
 }
 
 template <typename T>
 hipError_t launch_prim_to_cons_range(const Geom &g, const double *const *prim, const double *rho0,
-                                     T *state, long m, long stride, hipStream_t st)
+                                     T *state, long c0, long m, hipStream_t st)
 {
     PrimPtrs P;
     for (int q = 0; q < NF; ++q) P.p[q] = prim[q];
-    hipLaunchKernelGGL((prim_to_cons_range_kernel<T>), dim3(4096), dim3(256), 0, st, m, stride,
-                       g.gamma - 1.0, P, rho0, state);
+    hipLaunchKernelGGL((prim_to_cons_kernel<T>), dim3(4096), dim3(256), 0, st, g, c0, m, g.gamma - 1.0, P,
+                       rho0, state);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_cons_to_prim_range(const Geom &g, const T *state, const double *rho0, double *out,
-                                     long m, long stride, long ostride, hipStream_t st)
+                                     long c0, long m, long ostride, hipStream_t st)
 {
-    hipLaunchKernelGGL((cons_to_prim_range_kernel<T>), dim3(4096), dim3(256), 0, st, m, stride, ostride,
+    hipLaunchKernelGGL((cons_to_prim_kernel<T>), dim3(4096), dim3(256), 0, st, g, c0, m, ostride,
                        g.gamma - 1.0, state, rho0, out);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prim_to_cons(const Geom &g, const double *const *prim, const double *rho0,
+                               T *state, hipStream_t st)
+{
+    return launch_prim_to_cons_range<T>(g, prim, rho0, state, 0, (long)g.n[0] * g.n[1] * g.n[2], st);
 }
 
 template <typename A, typename B>
@@ -238,30 +221,39 @@ __global__ void convert_kernel(const A *src, B *dst, long count)
         dst[c] = B(src[c]);
 }
 
+// nf fields of a brick between pitched storage and dense FP64 (field q of
+// the dense side at q * ncell).
 template <typename T>
-hipError_t launch_prim_to_cons(const Geom &g, const double *const *prim, const double *rho0,
-                               T *state, hipStream_t st)
+__global__ void gather_kernel(Geom g, int nf, const T *src, double *dst)
 {
-    PrimPtrs P;
-    for (int q = 0; q < NF; ++q) P.p[q] = prim[q];
-    long nc = (long)g.n[0] * g.n[1] * g.n[2];
-    hipLaunchKernelGGL((prim_to_cons_kernel<T>), dim3(4096), dim3(256), 0, st, nc, g.gamma - 1.0, P, rho0, state);
+    const long n = (long)g.n[0] * g.n[1] * g.n[2];
+    for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < nf * n; x += (long)gridDim.x * blockDim.x) {
+        const long q = x / n, c = x - q * n;
+        dst[x] = double(src[q * g.fs + pitched(g, c)]);
+    }
+}
+
+template <typename T>
+__global__ void scatter_kernel(Geom g, int nf, const double *src, T *dst)
+{
+    const long n = (long)g.n[0] * g.n[1] * g.n[2];
+    for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < nf * n; x += (long)gridDim.x * blockDim.x) {
+        const long q = x / n, c = x - q * n;
+        dst[q * g.fs + pitched(g, c)] = T(src[x]);
+    }
+}
+
+template <typename T>
+hipError_t launch_gather(const Geom &g, int nf, const T *src, double *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL((gather_kernel<T>), dim3(4096), dim3(256), 0, st, g, nf, src, dst);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cons_to_prim(const Geom &g, const T *state, const double *rho0, double *prim,
-                               hipStream_t st)
+hipError_t launch_scatter(const Geom &g, int nf, const double *src, T *dst, hipStream_t st)
 {
-    long nc = (long)g.n[0] * g.n[1] * g.n[2];
-    hipLaunchKernelGGL((cons_to_prim_kernel<T>), dim3(4096), dim3(256), 0, st, nc, g.gamma - 1.0, state, rho0, prim);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_widen(const T *src, double *dst, long count, hipStream_t st)
-{
-    hipLaunchKernelGGL((convert_kernel<T, double>), dim3(4096), dim3(256), 0, st, src, dst, count);
+    hipLaunchKernelGGL((scatter_kernel<T>), dim3(4096), dim3(256), 0, st, g, nf, src, dst);
     return hipGetLastError();
 }
 
@@ -294,22 +286,22 @@ __global__ __launch_bounds__(256) void cfl_kernel(const Brick *bricks, const Blo
     const Geom g = B.g;
     const long nc = B.ncell;
     const T *S = arena + B.off;
-    const double *rho0 = base64 + B.boff, *p0 = base64 + B.boff + nc;
+    const long fs = g.fs;
+    const double *rho0 = base64 + B.boff, *p0 = base64 + B.boff + fs;
     const long c0 = (long)m.local * kCflBlockCells;
     const long c1 = c0 + kCflBlockCells < nc ? c0 + kCflBlockCells : nc;
     double smax = 0.0;
     bool bad = false;
     for (long c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
-        if (g.sphere) {
-            int i = (int)(c % g.n[0]);
-            int j = (int)((c / g.n[0]) % g.n[1]);
-            int k = (int)(c / ((long)g.n[0] * g.n[1]));
-            if (solid_at(g, centre(g, 0, i), centre(g, 1, j), centre(g, 2, k))) continue;
-        }
+        const unsigned nx = (unsigned)g.n[0], ny = (unsigned)g.n[1];
+        const unsigned row = (unsigned)c / nx, i = (unsigned)c - row * nx;
+        const unsigned k = row / ny, j = row - k * ny;
+        if (g.sphere && solid_at(g, centre(g, 0, i), centre(g, 1, j), centre(g, 2, k))) continue;
+        const long e = (long)i + (long)j * g.px + (long)k * g.plane;
         bool b;
-        const double sp = cell_speed(rho0[c], p0[c], (double)S[RHO * nc + c], (double)S[MX * nc + c],
-                                     (double)S[MY * nc + c], (double)S[MZ * nc + c],
-                                     (double)S[EN * nc + c], g.gamma, b);
+        const double sp = cell_speed(rho0[e], p0[e], (double)S[RHO * fs + e], (double)S[MX * fs + e],
+                                     (double)S[MY * fs + e], (double)S[MZ * fs + e],
+                                     (double)S[EN * fs + e], g.gamma, b);
         if (b) bad = true;
         else if (sp > smax) smax = sp;
     }
@@ -370,19 +362,19 @@ __global__ __launch_bounds__(256) void totals_kernel(Geom g, const T *S, const d
     const long nc = (long)g.n[0] * g.n[1] * g.n[2];
     const double gm1 = g.gamma - 1.0;
     double acc[8] = { 0, 0, 0, 0, 0, 0, INFINITY, -INFINITY };
+    const long fs = g.fs;
     for (long c = blockIdx.x * 256L + threadIdx.x; c < nc; c += (long)kTotalsBlocks * 256) {
-        if (g.sphere) {
-            int i = (int)(c % g.n[0]);
-            int j = (int)((c / g.n[0]) % g.n[1]);
-            int k = (int)(c / ((long)g.n[0] * g.n[1]));
-            if (solid_at(g, centre(g, 0, i), centre(g, 1, j), centre(g, 2, k))) continue;
-        }
-        double f0 = S[F0 * nc + c];
-        acc[0] += rho0[c] + (double)S[RHO * nc + c];
-        acc[1] += (double)S[MX * nc + c];
-        acc[2] += (double)S[MY * nc + c];
-        acc[3] += (double)S[MZ * nc + c];
-        acc[4] += p0[c] / gm1 + (double)S[EN * nc + c];
+        const unsigned nx = (unsigned)g.n[0], ny = (unsigned)g.n[1];
+        const unsigned row = (unsigned)c / nx, i = (unsigned)c - row * nx;
+        const unsigned k = row / ny, j = row - k * ny;
+        if (g.sphere && solid_at(g, centre(g, 0, i), centre(g, 1, j), centre(g, 2, k))) continue;
+        const long e = (long)i + (long)j * g.px + (long)k * g.plane;
+        double f0 = S[F0 * fs + e];
+        acc[0] += rho0[e] + (double)S[RHO * fs + e];
+        acc[1] += (double)S[MX * fs + e];
+        acc[2] += (double)S[MY * fs + e];
+        acc[3] += (double)S[MZ * fs + e];
+        acc[4] += p0[e] / gm1 + (double)S[EN * fs + e];
         acc[5] += f0;
         acc[6] = fmin(acc[6], f0);
         acc[7] = fmax(acc[7], f0);
@@ -460,9 +452,8 @@ hipError_t launch_zero_u64(unsigned long long *dst, int count, hipStream_t st)
                                                      double *, long, long, long, hipStream_t);     \
     template hipError_t launch_prim_to_cons<T>(const Geom &, const double *const *, const double *, \
                                                T *, hipStream_t);                                 \
-    template hipError_t launch_cons_to_prim<T>(const Geom &, const T *, const double *, double *,  \
-                                               hipStream_t);                                      \
-    template hipError_t launch_widen<T>(const T *, double *, long, hipStream_t);                   \
+    template hipError_t launch_gather<T>(const Geom &, int, const T *, double *, hipStream_t);      \
+    template hipError_t launch_scatter<T>(const Geom &, int, const double *, T *, hipStream_t);     \
     template hipError_t launch_narrow<T>(const double *, T *, long, hipStream_t);                  \
     template hipError_t launch_cfl<T>(const Brick *, int, int, const BlockMap *, int, const T *,   \
                                       const double *, unsigned long long *, double, double *,     \

@@ -28,7 +28,23 @@ struct Geom {
     int    heat_kind;
     double heat[3];
     int    smooth_detect;
+    // storage: cell (i, j, k) of field q at q * fs + i + j * px + k * plane
+    // (rows start on 256-byte boundaries; fs is padded so that the fields do
+    // not all fall on the same cache sets)
+    int    px;
+    long   plane;
+    long   fs;
 };
+
+// Storage offset of the cell with dense (x fastest) number c.
+__host__ __device__ __forceinline__ long pitched(const Geom &g, long c)
+{
+    const unsigned nx = (unsigned)g.n[0], ny = (unsigned)g.n[1];
+    const unsigned cc = (unsigned)c;                 // bricks hold fewer than 2^32 cells
+    const unsigned row = cc / nx, i = cc - row * nx;
+    const unsigned k = row / ny, j = row - k * ny;
+    return (long)i + (long)j * g.px + (long)k * g.plane;
+}
 
 // Reciprocal, reciprocal square root and square root.  FP32: the hardware
 // instructions (1 ulp), without the denormal rescaling the compiler wraps

@@ -8,9 +8,10 @@
 namespace ppmb {
 
 // One brick of a batch (a single grid is a batch of one): its grid and where
-// its fields live.  State arena: field q of the brick at off + q * ncell.
-// Base arena (working precision and FP64 alike): rho0 at boff, p0 at
-// boff + ncell.  Its time step is dt[dti].
+// its fields live.  State arena: field q of the brick at off + q * g.fs, in
+// the pitched layout of Geom.  Base arena (working precision and FP64
+// alike, same layout): rho0 at boff, p0 at boff + g.fs.  ncell = nx ny nz.
+// Its time step is dt[dti].
 struct Brick {
     Geom g;
     long off;
@@ -52,25 +53,27 @@ hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, cons
 hipError_t launch_base_state(const Geom &g, int kind, const double *params, double *table,
                              long table_len, double *rho0, double *p0, hipStream_t st);
 
-// conversions between FP64 primitive perturbations and the stored conserved
-// fields of the working precision
+// Conversions between FP64 primitive perturbations (dense, x fastest) and
+// the stored conserved fields of the working precision (pitched layout of
+// Geom).  The range forms take dense cells [c0, c0 + m) of one brick: the
+// primitive side holds exactly those cells (field q at prim[q], or at
+// out + q * ostride), state and rho0 are the brick's whole pitched arrays.
 template <typename T>
 hipError_t launch_prim_to_cons(const Geom &g, const double *const *prim, const double *rho0,
                                T *state, hipStream_t st);
 template <typename T>
-hipError_t launch_cons_to_prim(const Geom &g, const T *state, const double *rho0, double *prim,
-                               hipStream_t st);
-// The same on a range of m cells of a brick whose field stride is `stride`:
-// prim[q] / state fields start at the range's first cell; the FP64 staging
-// of cons_to_prim holds field q at out + q * ostride.
-template <typename T>
 hipError_t launch_prim_to_cons_range(const Geom &g, const double *const *prim, const double *rho0,
-                                     T *state, long m, long stride, hipStream_t st);
+                                     T *state, long c0, long m, hipStream_t st);
 template <typename T>
 hipError_t launch_cons_to_prim_range(const Geom &g, const T *state, const double *rho0, double *out,
-                                     long m, long stride, long ostride, hipStream_t st);
+                                     long c0, long m, long ostride, hipStream_t st);
+// nf pitched fields of a brick (stride g.fs) to / from dense FP64 (field q
+// at q * ncell)
 template <typename T>
-hipError_t launch_widen(const T *src, double *dst, long count, hipStream_t st);
+hipError_t launch_gather(const Geom &g, int nf, const T *src, double *dst, hipStream_t st);
+template <typename T>
+hipError_t launch_scatter(const Geom &g, int nf, const double *src, T *dst, hipStream_t st);
+// plain element-wise FP64 -> T copy
 template <typename T>
 hipError_t launch_narrow(const double *src, T *dst, long count, hipStream_t st);
 

@@ -18,7 +18,7 @@ namespace ppmb {
 // base fields, its dt and cell count.
 template <typename T>
 struct SweepArgs {
-    const T *in;          // 15 fields, stride ncell
+    const T *in;          // 15 fields, stride fs (pitched layout of Geom)
     T *out;
     const T *rho0;        // base state, working precision
     const T *p0;
@@ -26,7 +26,7 @@ struct SweepArgs {
     unsigned long long *counters;   // limiter, unsmooth, riemann
     const double *r064;   // FP64 base state (for the fused CFL reduction)
     const double *p064;
-    long ncell;
+    long fs;              // field stride (elements)
     int heat;             // 1: add the heating source after the update
     int cfl;              // 1: fold the written cells' signal speeds into the CFL slots
 };
@@ -50,9 +50,9 @@ struct BatchArgs {
 template <typename T>
 __device__ __forceinline__ SweepArgs<T> brick_args(const BatchArgs<T> &b, const Brick &B)
 {
-    return SweepArgs<T>{b.in + B.off, b.out + B.off, b.base + B.boff, b.base + B.boff + B.ncell,
-                        b.dt + B.dti, b.counters, b.base64 + B.boff, b.base64 + B.boff + B.ncell,
-                        B.ncell, b.heat, b.cfl};
+    return SweepArgs<T>{b.in + B.off, b.out + B.off, b.base + B.boff, b.base + B.boff + B.g.fs,
+                        b.dt + B.dti, b.counters, b.base64 + B.boff, b.base64 + B.boff + B.g.fs,
+                        B.g.fs, b.heat, b.cfl};
 }
 
 // Global (x, y, z) order of a pass's (normal, t1, t2) components.
@@ -180,7 +180,6 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la0, int lane, i
                       unsigned &c_lim, unsigned &c_uns, unsigned &c_rie, double &cmax, bool &cbad)
 {
     using AI = AxisInfo<AX>;
-    const int nx = g.n[0], ny = g.n[1];
     const int n = g.n[AX];
     const int ca = (AX == 0) ? 1 : 0;
     const int cb = 3 - AX - ca;
@@ -192,7 +191,7 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la0, int lane, i
     const int la = la0 + lld;
     int ijk0[3];
     ijk0[ca] = la; ijk0[cb] = lb; ijk0[AX] = 0;
-    const long stride[3] = { 1, (long)nx, (long)nx * ny };
+    const long stride[3] = { 1, (long)g.px, g.plane };
     const long sAX = stride[AX];
     // element index of this lane in the row of 64 pencils (stride 1 for the
     // y and z passes, nx for the x pass), and the row's element count
@@ -214,7 +213,7 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la0, int lane, i
     const T gam = T(g.gamma), gm1 = T(g.gamma - 1.0), gfac = T(g.gamma / (g.gamma - 1.0));
     const int bc = g.bc[AX];
     const T *in = a.in;
-    const long nc = a.ncell;
+    const long nc = a.fs;
     // field q of the 64-lane row at pencil index s (in / out / base)
     const T *inb = in + ubase;
     T *outb = a.out + ubase;
@@ -613,8 +612,8 @@ void sweep_x_kernel(BatchArgs<T> b)
     if (rowi >= ny * nz) return;                       // whole waves only
     const int y = rowi % ny, z = rowi / ny;
     const int nseg = (nx + kXOut - 1) / kXOut;
-    const long nc = a.ncell;
-    const long row = (long)rowi * nx;
+    const long nc = a.fs;
+    const long row = (long)rowi * g.px;
     const double yc = centre(g, 1, y), zc = centre(g, 2, z);
     const T xt1 = T(yc), xt2 = T(zc);
     const T rtt = xt1 * xt1 + xt2 * xt2;

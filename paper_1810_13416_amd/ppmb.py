@@ -19,7 +19,7 @@ FP64, FP32 = 0, 1
 NFIELDS = 15
 
 # every entry point declared in include/ppmb.h
-EXPORTS = ("ppmb_create", "ppmb_destroy", "ppmb_state_bytes", "ppmb_bind_state",
+EXPORTS = ("ppmb_create", "ppmb_destroy", "ppmb_state_bytes", "ppmb_state_layout", "ppmb_bind_state",
            "ppmb_current_state", "ppmb_set_base_state", "ppmb_get_base", "ppmb_set_state",
            "ppmb_set_state_device", "ppmb_get_state", "ppmb_get_conserved",
            "ppmb_set_conserved", "ppmb_compute_dt", "ppmb_step", "ppmb_step_auto",
@@ -65,6 +65,7 @@ def load():
         "ppmb_state_bytes": [p, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
         "ppmb_bind_state": [p, p, p],
         "ppmb_current_state": [p, ctypes.POINTER(p)],
+        "ppmb_state_layout": [p, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)],
         "ppmb_set_base_state": [p, i, _D],
         "ppmb_get_base": [p, _D, _D],
         "ppmb_set_state": [p, _DD],
@@ -277,6 +278,13 @@ class Sim:
 
     def synchronize(self):
         self._check(self.L.ppmb_synchronize(self.h))
+
+    def layout(self):
+        """(offset, field stride, plane stride, row pitch) of the device state,
+        in elements."""
+        out = (ctypes.c_longlong * 4)()
+        self._check(self.L.ppmb_state_layout(self.h, 0, out))
+        return tuple(int(v) for v in out)
 
     def current_state_tensor(self):
         p = ctypes.c_void_p()

@@ -311,3 +311,21 @@ def test_fused_cfl_reduction_equals_cfl_kernel(prec):
     D = sim(prob.params, prec)
     D.set_state(prob.state)
     assert C.last_dt() == D.dt(prob.cfl)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_device_state_layout_is_the_documented_pitched_one(prec):
+    # rows padded to 64 elements, padded field stride: reading the raw device
+    # buffer through ppmb_state_layout gives the conserved fields
+    prob = pr.config1(n=20)
+    S = sim(prob.params, prec)
+    S.set_state(prob.state)
+    S.step_auto(prob.cfl, 1)
+    off, fs, plane, px = S.layout()
+    nz, ny, nx = S.shape
+    assert px % 64 == 0 and px >= nx and plane == px * ny and fs >= nz * plane
+    raw = S.current_state_tensor().cpu().numpy()
+    cons = S.get_conserved()
+    for q in range(15):
+        a = raw[off + q * fs: off + q * fs + nz * plane].reshape(nz, ny, px)[:, :, :nx]
+        assert np.array_equal(a.astype(np.float64), cons[q]), q
