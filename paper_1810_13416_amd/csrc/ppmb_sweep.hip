@@ -523,6 +523,14 @@ void sweep_kernel(BatchArgs<T> b)
 // ---------------------------------------------------------------------
 
 constexpr int kXOut = 56;
+constexpr int kXItems = 8;     // (row, segment) items per wave, at least
+
+// Items per wave: whole rows, at least kXItems items.
+__host__ __device__ __forceinline__ int x_run(int nseg)
+{
+    const int rows = kXItems / nseg;
+    return (rows > 1 ? rows : 1) * nseg;
+}
 
 // Neighbour values inside the wave by DPP whole-wave shifts (wave_shr:1,
 // wave_shl:1): a VALU move, no LDS round trip.  The lane at the wave's edge
@@ -594,9 +602,11 @@ __device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, 
     o.pb = bld<T>(rsrc(p0 + row, nx), s);
 }
 
-// One wave owns one x-row and walks it in segments of 56 outputs; the
-// loads of the next segment are issued before the current one is computed,
-// so their latency hides behind the arithmetic.
+// One wave walks whole x-rows, 56-cell segment by segment, at least
+// kXItems segments (several rows when they are short, as in small bricks),
+// so that each wave has enough work; the loads of the next segment (of the
+// same or the next row) are issued before the current one is computed, so
+// their latency hides behind the arithmetic.
 template <typename T>
 __global__ __launch_bounds__(256)
 void sweep_x_kernel(BatchArgs<T> b)
@@ -608,15 +618,16 @@ void sweep_x_kernel(BatchArgs<T> b)
     const SweepArgs<T> a = brick_args(b, B);
     const int lane = threadIdx.x & 63;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    const int rowi = m.local * (int)(blockDim.x >> 6) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    if (rowi >= ny * nz) return;                       // whole waves only
-    const int y = rowi % ny, z = rowi / ny;
+    // this wave's run of items: item = (x-row, segment), rows in storage
+    // order, segments along the row
     const int nseg = (nx + kXOut - 1) / kXOut;
+    const int items = ny * nz * nseg;
+    const int run = x_run(nseg);
+    const int wv = m.local * (int)(blockDim.x >> 6) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int it0 = wv * run;                          // whole rows: it0 is a row start
+    if (it0 >= items) return;                          // whole waves only
+    const int it1 = min(it0 + run, items);
     const long nc = a.fs;
-    const long row = (long)rowi * g.px;
-    const double yc = centre(g, 1, y), zc = centre(g, 2, z);
-    const T xt1 = T(yc), xt2 = T(zc);
-    const T rtt = xt1 * xt1 + xt2 * xt2;
     const double dt64 = *a.dtp;
     const T dt = T(dt64), nu = T(dt64 / g.dx), hdt = T(0.5 * dt64), rdx = T(1.0 / g.dx);
     const T gam = T(g.gamma), gm1 = T(g.gamma - 1.0), gfac = T(g.gamma / (g.gamma - 1.0));
@@ -626,12 +637,23 @@ void sweep_x_kernel(BatchArgs<T> b)
     double cmax = 0.0;                                 // fused CFL reduction
     bool cbad = false;
 
+    // storage offset of an item's row and its first lane's cell
+    auto item_row = [&](int it) { return (long)(it / nseg) * g.px; };
+    auto item_i0 = [&](int it) { return (it % nseg) * kXOut - NG; };
+
     XIn<T> cur;
-    x_load(a.in, a.rho0, a.p0, nc, row, nx, bc, -NG + lane, cur);
+    x_load(a.in, a.rho0, a.p0, nc, item_row(it0), nx, bc, item_i0(it0) + lane, cur);
     // settle the first loads, so that the loop's waits count only the
     // memory operations of the loop itself
     __builtin_amdgcn_s_waitcnt(0);
-    for (int seg = 0; seg < nseg; ++seg) {
+    for (int rowi = it0 / nseg; rowi * nseg < it1; ++rowi) {
+      const int y = rowi % ny, z = rowi / ny;
+      const long row = (long)rowi * g.px;
+      const double yc = centre(g, 1, y), zc = centre(g, 2, z);
+      const T xt1 = T(yc), xt2 = T(zc);
+      const T rtt = xt1 * xt1 + xt2 * xt2;
+      for (int seg = 0; seg < nseg; ++seg) {
+        const int it = rowi * nseg + seg;
         const int i = seg * kXOut - NG + lane;         // this lane's cell along x
 
         // (1) this lane's cell: its inputs are taken over as new values,
@@ -649,7 +671,10 @@ void sweep_x_kernel(BatchArgs<T> b)
         for (int v = 0; v < 10; ++v) pq[v] = AI::odd(v) ? fl * cur.pq[v] : fresh(cur.pq[v]);
         const T r0 = fresh(cur.r0), pb = fresh(cur.pb);
         __builtin_amdgcn_sched_barrier(0);
-        x_load(a.in, a.rho0, a.p0, nc, row, nx, bc, i + kXOut, cur);
+        {
+            const int nit = it + 1 < it1 ? it + 1 : it;       // past the run: reload, unused
+            x_load(a.in, a.rho0, a.p0, nc, item_row(nit), nx, bc, item_i0(nit) + lane, cur);
+        }
         const T xd = ox + (T(s) + T(0.5)) * dxT;
         const T gv = fl * gravity<T>(g, 0, xd, rtt + xd * xd);
         const bool so = solid_at(g, centre(g, 0, s), yc, zc);
@@ -779,6 +804,7 @@ void sweep_x_kernel(BatchArgs<T> b)
                 else cmax = fmax(cmax, sp);
             }
         }
+      }
     }
     if (a.cfl) cfl_commit(b.work, m.brick, cmax, cbad);
     unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
@@ -805,7 +831,9 @@ static bool x_lanes_enabled()
 int pass_blocks(const Geom &g, int axis, const PassShape &sh)
 {
     if (axis == 0 && x_lanes_enabled()) {
-        const long nw = (long)g.n[1] * g.n[2];            // one wave per x-row
+        const int nseg = (g.n[0] + kXOut - 1) / kXOut;
+        const long items = (long)g.n[1] * g.n[2] * nseg;
+        const long nw = (items + x_run(nseg) - 1) / x_run(nseg);   // whole rows per wave
         return (int)((nw + sh.x_waves - 1) / sh.x_waves);
     }
     const int ca = (axis == 0) ? 1 : 0;
