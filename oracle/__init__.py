@@ -71,6 +71,9 @@ def lib():
         L.or_riemann.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]
         L.or_ppb_pencil.restype = ctypes.c_int
         L.or_ppb_pencil.argtypes = [ctypes.c_int, _DD, _D, _DD]
+        L.or_ppb2d_steps.restype = None
+        L.or_ppb2d_steps.argtypes = [ctypes.c_int, ctypes.c_int] + [ctypes.c_double] * 7 + \
+            [ctypes.c_int, ctypes.c_long, _DD]
         L.or_sizeof_params.restype = ctypes.c_int
         assert L.or_sizeof_params() == ctypes.sizeof(_Params)
         _lib = L
@@ -212,6 +215,17 @@ def riemann(L, R, rho0f=0.0, p0f=0.0, gamma=1.4):
 
 
 NG = 4
+
+
+def ppb2d_steps(coef6, n, dx, origin, centre, omega, dt, nsteps, step0=0):
+    """nsteps steps of 2-D PPB under a rigid rotation (see the C source):
+    coef6 = 6 arrays (ny, nx): f0, fx, fy, fxx, fyy, fxy.  Returns new arrays."""
+    nx, ny = n
+    arrs = [np.array(a, dtype=np.float64, copy=True, order="C") for a in coef6]
+    lib().or_ppb2d_steps(int(nx), int(ny), float(dx), float(origin[0]), float(origin[1]),
+                         float(centre[0]), float(centre[1]), float(omega), float(dt),
+                         int(nsteps), int(step0), _ptrs(arrs))
+    return arrs
 
 
 def ppb_pencil(coef, sigma):

@@ -562,6 +562,71 @@ int or_ppb_pencil(int n, double *const c[10], const double *sig, double *const o
 }
 
 /* ------------------------------------------------------------------ */
+/* 2-D PPB under a prescribed solid-body rotation (Fig. 3)              */
+/* ------------------------------------------------------------------ */
+
+/* [reading] The advection test of Fig. 3: a 2-D grid of nx x ny cells of
+   width dx (cell (i, j) centred at x0 + (i + 1/2) dx, y0 + (j + 1/2) dx),
+   fv carried as its 6 low-order moments (1, x, y, P2(x), P2(y), xy on the
+   unit cell; the 3-D PPB with every z term zero), periodic boundaries, and
+   the velocity of a rigid rotation with angular speed omega about (xc, yc):
+   u = -omega (y - yc), v = omega (x - xc).  A step is an x pass then a y
+   pass on even steps and the reverse on odd steps; a pass moves each pencil
+   by the face Courant numbers of that velocity (u at x-faces depends on y
+   only, so every cell of a pencil keeps its length).
+   c[0..5] = f0, fx, fy, fxx, fyy, fxy, each nx*ny values, x fastest. */
+static void ppb2d_pass(int nx, int ny, double dx, double x0, double y0, double xc, double yc,
+                       double omega, double dt, int axis, double *const c[6])
+{
+    const int n = axis == 0 ? nx : ny;            /* cells along the pass */
+    const int np = axis == 0 ? ny : nx;           /* pencils */
+    const int m = n + 2 * NG;
+    /* pass-local order (quadratic along, transverse linear, transverse
+       linear in z = 0, constants): x pass f0 fx fxx | fy fxy | 0 0 | fyy 0 0,
+       y pass f0 fy fyy | fx fxy | 0 0 | fxx 0 0 */
+    const int map_x[10] = { 0, 1, 3, 2, 5, -1, -1, 4, -1, -1 };
+    const int map_y[10] = { 0, 2, 4, 1, 5, -1, -1, 3, -1, -1 };
+    const int *map = axis == 0 ? map_x : map_y;
+#pragma omp parallel for schedule(static)
+    for (int p = 0; p < np; ++p) {
+        double *in[10], *out[10];
+        double *buf = (double *)calloc((size_t)21 * m, sizeof(double));
+        for (int q = 0; q < 10; ++q) { in[q] = buf + q * m; out[q] = buf + (10 + q) * m; }
+        double *sig = buf + 20 * m;
+        /* the pencil's transverse coordinate and its face Courant number */
+        const double tc = (axis == 0 ? y0 : x0) + (p + 0.5) * dx;
+        const double vel = axis == 0 ? -omega * (tc - yc) : omega * (tc - xc);
+        const double s = vel * dt / dx;
+        for (int J = 0; J < m; ++J) {
+            int j = ((J - NG) % n + n) % n;        /* periodic */
+            long cell = axis == 0 ? (long)p * nx + j : (long)j * nx + p;
+            for (int q = 0; q < 10; ++q) in[q][J] = map[q] < 0 ? 0.0 : c[map[q]][cell];
+            sig[J] = s;
+        }
+        int *solid = (int *)calloc(m, sizeof(int));
+        ppb_pencil(n, in, sig, solid, out);
+        free(solid);
+        for (int j = 0; j < n; ++j) {
+            long cell = axis == 0 ? (long)p * nx + j : (long)j * nx + p;
+            for (int q = 0; q < 10; ++q)
+                if (map[q] >= 0) c[map[q]][cell] = out[q][j + NG];
+        }
+        free(buf);
+    }
+}
+
+/* nsteps steps from step number step0 (its parity picks the pass order). */
+void or_ppb2d_steps(int nx, int ny, double dx, double x0, double y0, double xc, double yc,
+                    double omega, double dt, int nsteps, long step0, double *const c[6])
+{
+    for (int k = 0; k < nsteps; ++k) {
+        int first = ((step0 + k) & 1) ? 1 : 0;
+        ppb2d_pass(nx, ny, dx, x0, y0, xc, yc, omega, dt, first, c);
+        ppb2d_pass(nx, ny, dx, x0, y0, xc, yc, omega, dt, 1 - first, c);
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* One pencil of one pass: PPM hydro + PPB                             */
 /* ------------------------------------------------------------------ */
 

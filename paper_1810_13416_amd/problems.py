@@ -439,3 +439,124 @@ def sod(n: int = 200) -> Problem:
     f[0][:] = np.where(left, 1.0, 0.0)
     return Problem(P, [rho, np.zeros(P.shape), np.zeros(P.shape), np.zeros(P.shape), p] + f,
                    cfl=0.8, nsteps=0, name=f"sod_{n}")
+
+
+# ---------------------------------------------------------------------
+# The advection test of Fig. 3: a slotted disk in a rigid rotation (2-D)
+# ---------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Zalesak:
+    """2-D PPB advection problem: grid, rotation and the 6 fv moments
+    (f0, fx, fy, fxx, fyy, fxy; arrays (ny, nx), x fastest)."""
+    n: tuple
+    dx: float
+    origin: tuple
+    centre: tuple
+    omega: float
+    coef: list
+    disk: tuple          # (xc, yc, radius, slot half-width, slot top)
+
+    def dt(self, courant: float = 0.5) -> float:
+        """dt for the largest face Courant number `courant` on the grid."""
+        nx, ny = self.n
+        ext = max(abs(self.origin[0] - self.centre[0]), abs(self.origin[0] + nx * self.dx - self.centre[0]),
+                  abs(self.origin[1] - self.centre[1]), abs(self.origin[1] + ny * self.dx - self.centre[1]))
+        return courant * self.dx / (abs(self.omega) * ext)
+
+
+def _square_moments(a, b, c, d):
+    """Integrals of 1, s, t, P2(s), P2(t), s t over [a,b] x [c,d] (cell
+    coordinates, P2(s) = s^2 - 1/12)."""
+    w, h = b - a, d - c
+    m1s = (b * b - a * a) / 2.0
+    m1t = (d * d - c * c) / 2.0
+    p2s = (b ** 3 - a ** 3) / 3.0 - w / 12.0
+    p2t = (d ** 3 - c ** 3) / 3.0 - h / 12.0
+    return np.stack([w * h, m1s * h, w * m1t, p2s * h, w * p2t, m1s * m1t])
+
+
+def slotted_disk_moments(n: int = 100, xc: float = 0.5, yc: float = 0.75, radius: float = 0.15,
+                         slot_half: float = 0.025, slot_top: float = 0.85, depth: int = 12):
+    """Exact-to-quadrature-depth moments of the indicator of a disk (centre
+    (xc, yc), radius) minus the vertical slot |x - xc| < slot_half below
+    y = slot_top, on the unit square with n x n cells.  Cut cells are
+    subdivided into quarters down to `depth` levels; a sub-square entirely
+    inside or outside the shape contributes its exact polynomial moments,
+    the last level is decided by its centre."""
+    dx = 1.0 / n
+    acc = np.zeros((6, n, n))
+    # squares: (cell i, cell j, s0, t0, size) in cell coordinates, s0 <= s <= s0 + size
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    ci = ii.ravel().astype(np.int64)
+    cj = jj.ravel().astype(np.int64)
+    s0 = np.full(ci.shape, -0.5)
+    t0 = np.full(ci.shape, -0.5)
+    size = 1.0
+    for level in range(depth + 1):
+        x_lo = (ci + 0.5 + s0) * dx
+        y_lo = (cj + 0.5 + t0) * dx
+        x_hi, y_hi = x_lo + size * dx, y_lo + size * dx
+        # disk: nearest and farthest point of the square from the centre
+        nx_ = np.clip(xc, x_lo, x_hi) - xc
+        ny_ = np.clip(yc, y_lo, y_hi) - yc
+        near2 = nx_ * nx_ + ny_ * ny_
+        fx_ = np.maximum(np.abs(x_lo - xc), np.abs(x_hi - xc))
+        fy_ = np.maximum(np.abs(y_lo - yc), np.abs(y_hi - yc))
+        far2 = fx_ * fx_ + fy_ * fy_
+        disk_in = far2 <= radius * radius
+        disk_out = near2 >= radius * radius
+        # slot: x in (xc - h, xc + h), y < slot_top
+        slot_in = (x_lo >= xc - slot_half) & (x_hi <= xc + slot_half) & (y_hi <= slot_top)
+        slot_out = (x_hi <= xc - slot_half) | (x_lo >= xc + slot_half) | (y_lo >= slot_top)
+        inside = disk_in & slot_out
+        outside = disk_out | slot_in
+        if level == depth:
+            xm, ym = 0.5 * (x_lo + x_hi), 0.5 * (y_lo + y_hi)
+            cen = ((xm - xc) ** 2 + (ym - yc) ** 2 < radius * radius) & \
+                ~((np.abs(xm - xc) < slot_half) & (ym < slot_top))
+            inside = cen
+            outside = ~cen
+        sel = inside
+        if np.any(sel):
+            mom = _square_moments(s0[sel], s0[sel] + size, t0[sel], t0[sel] + size)
+            for q in range(6):
+                np.add.at(acc[q], (cj[sel], ci[sel]), mom[q])
+        cut = ~(inside | outside)
+        if not np.any(cut):
+            break
+        ci, cj, s0, t0 = ci[cut], cj[cut], s0[cut], t0[cut]
+        half = 0.5 * size
+        ci = np.concatenate([ci] * 4)
+        cj = np.concatenate([cj] * 4)
+        s0 = np.concatenate([s0, s0 + half, s0, s0 + half])
+        t0 = np.concatenate([t0, t0, t0 + half, t0 + half])
+        size = half
+    norm = np.array([1.0, 12.0, 12.0, 180.0, 180.0, 144.0])
+    return [acc[q] * norm[q] for q in range(6)]
+
+
+def zalesak(n: int = 100) -> Zalesak:
+    """The slotted disk of the classic Zalesak test on the unit square
+    (n x n cells): disk of radius 0.15 centred at (0.5, 0.75), slot 0.05 wide
+    reaching up to y = 0.85, rotating rigidly about (0.5, 0.5) once per unit
+    time."""
+    coef = slotted_disk_moments(n)
+    return Zalesak(n=(n, n), dx=1.0 / n, origin=(0.0, 0.0), centre=(0.5, 0.5),
+                   omega=2.0 * math.pi, coef=coef, disk=(0.5, 0.75, 0.15, 0.025, 0.85))
+
+
+def render_subcells(coef, sub: int = 4) -> np.ndarray:
+    """fv averaged over sub x sub squares of every cell from its 6 moments
+    (Fig. 3's rendering): array (ny * sub, nx * sub)."""
+    f0, fx, fy, fxx, fyy, fxy = [np.asarray(a, dtype=np.float64) for a in coef]
+    ny, nx = f0.shape
+    edges = np.linspace(-0.5, 0.5, sub + 1)
+    out = np.zeros((ny * sub, nx * sub))
+    area = (1.0 / sub) ** 2
+    for b in range(sub):
+        for a in range(sub):
+            m = _square_moments(edges[a], edges[a + 1], edges[b], edges[b + 1])
+            val = (f0 * m[0] + fx * m[1] + fy * m[2] + fxx * m[3] + fyy * m[4] + fxy * m[5]) / area
+            out[b::sub, a::sub] = val
+    return out
