@@ -1,7 +1,7 @@
 """Throughput of the PPM + PPB 3-D step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu]
-                    [--no-bricks] [--no-accuracy] [--calib-copy-mib M]
+                    [--no-bricks] [--no-accuracy] [--no-ppb2d] [--calib-copy-mib M]
 
 Workload: the spherical convection shell on a 512^3 grid (FP32 perturbation
 form on an FP64 radial hydrostatic base, radial gravity, heating, confining
@@ -25,7 +25,10 @@ The JSON carries
                 brick, after the launch-shape autotuner;
   accuracy      the stratified box at 128^3 in FP32 and FP64 against the
                 same at 256^3 in FP64 (fixed dt, restricted to 128^3): the
-                FP32 round-off error against the truncation error.
+                FP32 round-off error against the truncation error;
+  ppb2d         the slotted-disk advection test of Fig. 3 (2-D PPB, FP32,
+                100^2 cells, 1 / 10 / 100 revolutions: shape error, mass,
+                bounds) and the throughput of its pass kernel on 4096^2.
 """
 from __future__ import annotations
 
@@ -200,6 +203,54 @@ def run_accuracy(nsteps=200):
     return out
 
 
+def run_ppb2d():
+    """The slotted-disk test and the 2-D PPB pass kernel's throughput."""
+    import numpy as np
+    import torch
+    from paper_1810_13416_amd import ppmb, problems
+    z = problems.zalesak(100)
+    nrev = int(round(1.0 / z.dt(0.5)))
+    dt = 1.0 / nrev
+    G = ppmb.PPB2D(z.n, z.dx, z.origin, z.centre, z.omega, ppmb.FP32)
+    G.set(z.coef)
+    g0 = z.coef[0]
+    out = {"grid": [100, 100], "steps_per_revolution": nrev, "precision": "fp32", "revolutions": {}}
+    done = 0
+    for rev in (1, 10, 100):
+        G.steps(dt, (rev - done) * nrev)
+        done = rev
+        f = G.get()[0]
+        out["revolutions"][str(rev)] = {"shape_L1_over_area": float(np.abs(f - g0).sum() / g0.sum()),
+                                         "mass_drift": float(f.sum() / g0.sum() - 1.0),
+                                         "fv_min": float(f.min()), "fv_max": float(f.max())}
+        log(f"ppb2d: {rev} revolution(s), shape error {out['revolutions'][str(rev)]['shape_L1_over_area']:.4f}")
+    G.close()
+    # throughput of the pass kernel on a large grid
+    n = 4096
+    coef = problems.slotted_disk_moments(n, depth=4)
+    G = ppmb.PPB2D((n, n), 1.0 / n, (0.0, 0.0), (0.5, 0.5), 2.0 * np.pi, ppmb.FP32)
+    G.set(coef)
+    del coef
+    dtb = 0.5 * (1.0 / n) / (2.0 * np.pi * 0.5)
+    G.steps(dtb, 3)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    steps = 50
+    e0.record(G.stream)
+    G.steps(dtb, steps)
+    e1.record(G.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    G.close()
+    cells = n * n
+    gbs = 2 * (2 * 6 * 4 * cells) / (ms * 1e-3) / 1e9      # two passes per step
+    out["throughput"] = {"grid": [n, n], "ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3),
+                         "bytes_per_cell_per_pass": 48, "achieved_GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+    log(f"ppb2d {n}^2: {ms:.3f} ms/step, {gbs:.0f} GB/s")
+    return out
+
+
 def cpu_baseline(n=256, steps=8):
     import numpy as np  # noqa: F401
     import oracle
@@ -230,6 +281,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bricks", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-ppb2d", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -313,6 +365,9 @@ def main():
     if not args.no_accuracy:
         log("accuracy: FP32 round-off vs truncation error")
         out["accuracy"] = run_accuracy()
+    if not args.no_ppb2d:
+        log("2-D PPB: slotted disk")
+        out["ppb2d"] = run_ppb2d()
     if not args.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()

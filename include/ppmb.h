@@ -270,6 +270,49 @@ ppmb_status ppmb_synchronize(ppmb_ctx *ctx);
 const char *ppmb_status_string(ppmb_status s);
 const char *ppmb_last_error(const ppmb_ctx *ctx);
 
+/* ------------------------------------------------------------------ */
+/* 2-D PPB advection under a rigid rotation: the slotted-disk test of  */
+/* Fig. 3 (a gas filling a slotted circle, tracked by PPB on a uniform */
+/* 2-D grid as it rotates about the grid centre).                      */
+/* ------------------------------------------------------------------ */
+
+/* nx x ny cells of width dx; cell (i, j) centred at origin + (i + 1/2,
+ * j + 1/2) dx; periodic boundaries; velocity u = -omega (y - centre_y),
+ * v = omega (x - centre_x). */
+typedef struct {
+    int n[2];
+    double dx;
+    double origin[2];
+    double centre[2];
+    double omega;
+} ppmb_ppb2d_grid;
+
+typedef struct ppmb_ppb2d ppmb_ppb2d;
+
+/* Create a context with its two device buffers for the 6 fv moments of
+ * each cell (f0, fx, fy, fxx, fyy, fxy in the basis 1, x, y, P2(x), P2(y),
+ * xy of the unit cell).  Work goes to hip_stream.  Errors: INVALID for a
+ * bad grid or precision, NOMEM, HIP. */
+ppmb_status ppmb_ppb2d_create(const ppmb_ppb2d_grid *grid, ppmb_precision prec, void *hip_stream,
+                              ppmb_ppb2d **out);
+ppmb_status ppmb_ppb2d_destroy(ppmb_ppb2d *ctx);
+
+/* Set / read the moments from / to 6 dense FP64 host arrays (nx * ny each,
+ * x fastest); rounded to the working precision on set.  Synchronising. */
+ppmb_status ppmb_ppb2d_set(ppmb_ppb2d *ctx, const double *const host_coef[6]);
+ppmb_status ppmb_ppb2d_get(ppmb_ppb2d *ctx, double *const host_coef[6]);
+
+/* nsteps steps of size dt: an x pass then a y pass on even steps (counted
+ * by the context from 0), the reverse on odd steps; each pass moves every
+ * pencil by the PPB transport of the 1-D pass (Sec. 1, Sec. 4) with the
+ * face Courant numbers of the rotation.  Asynchronous.  Errors: INVALID
+ * for dt <= 0 or |omega| dt / dx times the largest lever arm >= 1. */
+ppmb_status ppmb_ppb2d_steps(ppmb_ppb2d *ctx, double dt, int nsteps);
+
+/* Step counter (its parity selects the pass order). */
+ppmb_status ppmb_ppb2d_get_nstep(const ppmb_ppb2d *ctx, long *nstep);
+ppmb_status ppmb_ppb2d_set_nstep(ppmb_ppb2d *ctx, long nstep);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,6 +25,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-fno-gpu-flush-denormals-to-zero", "-Wall", "-Wno-unused-result"]
 UNITS = {
     "ppmb_sweep.hip": ["-ffp-contract=fast", "-fno-hip-fp32-correctly-rounded-divide-sqrt"],
+    "ppmb_ppb2d.hip": ["-ffp-contract=fast", "-fno-hip-fp32-correctly-rounded-divide-sqrt"],
     "ppmb_aux.hip": ["-ffp-contract=off"],
     "ppmb_api.hip": ["-ffp-contract=off"],
 }

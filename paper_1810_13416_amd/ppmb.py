@@ -29,7 +29,9 @@ EXPORTS = ("ppmb_create", "ppmb_destroy", "ppmb_state_bytes", "ppmb_state_layout
            "ppmb_brick_count", "ppmb_brick_set_base_state", "ppmb_brick_get_base",
            "ppmb_brick_set_state", "ppmb_brick_get_state", "ppmb_brick_get_conserved",
            "ppmb_brick_totals", "ppmb_brick_last_dt", "ppmb_batch_step", "ppmb_set_pass_shape",
-           "ppmb_get_pass_shape", "ppmb_autotune")
+           "ppmb_get_pass_shape", "ppmb_autotune", "ppmb_ppb2d_create", "ppmb_ppb2d_destroy",
+           "ppmb_ppb2d_set", "ppmb_ppb2d_get", "ppmb_ppb2d_steps", "ppmb_ppb2d_get_nstep",
+           "ppmb_ppb2d_set_nstep")
 
 
 class PPMBError(RuntimeError):
@@ -42,6 +44,11 @@ class Grid(ctypes.Structure):
                 ("sphere_r", ctypes.c_double), ("grav_kind", ctypes.c_int),
                 ("grav", ctypes.c_double * 4), ("heat_kind", ctypes.c_int),
                 ("heat", ctypes.c_double * 3), ("smooth_detect", ctypes.c_int)]
+
+
+class Grid2D(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 2), ("dx", ctypes.c_double), ("origin", ctypes.c_double * 2),
+                ("centre", ctypes.c_double * 2), ("omega", ctypes.c_double)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -98,6 +105,13 @@ def load():
         "ppmb_set_pass_shape": [p, i, i],
         "ppmb_get_pass_shape": [p, ctypes.POINTER(i), ctypes.POINTER(i)],
         "ppmb_autotune": [p, d, i, ctypes.c_char_p, ctypes.POINTER(i)],
+        "ppmb_ppb2d_create": [ctypes.POINTER(Grid2D), i, p, ctypes.POINTER(p)],
+        "ppmb_ppb2d_destroy": [p],
+        "ppmb_ppb2d_set": [p, _DD],
+        "ppmb_ppb2d_get": [p, _DD],
+        "ppmb_ppb2d_steps": [p, d, i],
+        "ppmb_ppb2d_get_nstep": [p, ctypes.POINTER(ctypes.c_long)],
+        "ppmb_ppb2d_set_nstep": [p, ctypes.c_long],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -379,3 +393,56 @@ class Batch:
 
     def synchronize(self):
         self._check(self.L.ppmb_synchronize(self.h))
+
+
+class PPB2D:
+    """2-D PPB advection of the 6 fv moments (f0, fx, fy, fxx, fyy, fxy)
+    under a rigid rotation (the slotted-disk test); the HIP library does all
+    the work, this class only marshals arguments."""
+
+    def __init__(self, n, dx, origin, centre, omega, precision=FP64, device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise PPMBError("no GPU: the PPB path runs only in the HIP library")
+        self.L = load()
+        self.n = (int(n[0]), int(n[1]))
+        self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+        g = Grid2D()
+        g.n[:] = list(self.n)
+        g.dx = float(dx)
+        g.origin[:] = [float(v) for v in origin]
+        g.centre[:] = [float(v) for v in centre]
+        g.omega = float(omega)
+        h = ctypes.c_void_p()
+        st = self.L.ppmb_ppb2d_create(ctypes.byref(g), precision, ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(h))
+        if st != 0:
+            raise PPMBError(f"ppmb_ppb2d_create failed: {st}")
+        self.h = h
+
+    def _check(self, st):
+        if st != 0:
+            raise PPMBError(self.L.ppmb_status_string(st).decode())
+
+    def set(self, coef):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in coef]
+        self._check(self.L.ppmb_ppb2d_set(self.h, _ptrs(arrs)))
+
+    def get(self):
+        out = [np.empty((self.n[1], self.n[0])) for _ in range(6)]
+        self._check(self.L.ppmb_ppb2d_get(self.h, _ptrs(out)))
+        return out
+
+    def steps(self, dt, nsteps):
+        self._check(self.L.ppmb_ppb2d_steps(self.h, float(dt), int(nsteps)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ppmb_ppb2d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -79,6 +79,30 @@ int main(void) {
     assert vals == got
 
 
+def test_grid2d_struct_layout_matches_header():
+    from paper_1810_13416_amd.ppmb import Grid2D
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "ppmb.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\n", sizeof(ppmb_ppb2d_grid), offsetof(ppmb_ppb2d_grid, dx),
+         offsetof(ppmb_ppb2d_grid, origin), offsetof(ppmb_ppb2d_grid, centre),
+         offsetof(ppmb_ppb2d_grid, omega));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        vals = [int(v) for v in subprocess.check_output([exe]).split()]
+    got = [ctypes.sizeof(Grid2D), Grid2D.dx.offset, Grid2D.origin.offset, Grid2D.centre.offset,
+           Grid2D.omega.offset]
+    assert vals == got
+
+
 def test_binding_refuses_to_run_without_gpu():
     import torch
     if torch.cuda.is_available():
@@ -86,6 +110,8 @@ def test_binding_refuses_to_run_without_gpu():
     from paper_1810_13416_amd import ppmb, problems
     with pytest.raises(ppmb.PPMBError):
         ppmb.Sim(problems.uniform().params)
+    with pytest.raises(ppmb.PPMBError):
+        ppmb.PPB2D((8, 8), 0.1, (0, 0), (0.4, 0.4), 1.0)
 
 
 def test_product_path_does_not_import_oracle():
