@@ -4,6 +4,8 @@
     python -m paper_1810_13416_amd.profsum traffic <fetch counter_collection.csv>
            <write counter_collection.csv> <calib MiB> <cells> <out.txt> <command...>
     python -m paper_1810_13416_amd.profsum counters <out.md> <title> <csv> [<csv> ...] -- <command...>
+    python -m paper_1810_13416_amd.profsum dispatches <kernel_trace.csv> <out.md> <name part>
+           <min grid threads> <command...>
 
 `stats` turns a `--kernel-trace --stats` run into a table of kernels by
 total time; `counters` tabulates any `--pmc` counters per kernel (mean per
@@ -12,7 +14,11 @@ both in KiB per dispatch) into HBM bytes per launch of each pass kernel,
 scaled by what the same counters read for one plain elementwise copy of
 known size (`bench.py --calib-copy-mib M`, which reads M MiB and writes M
 MiB), and records a hash of the pass sources so that a reader can tell
-whether the figures still describe the kernels as built.
+whether the figures still describe the kernels as built.  `dispatches`
+summarises, from the per-dispatch trace of a `--kernel-trace` run, the
+launches of the kernels whose name contains a given part and whose grid has
+at least a given number of work-items (so that launches of one problem size
+are not averaged with those of another).
 """
 from __future__ import annotations
 
@@ -172,6 +178,38 @@ def write_traffic(fetch_csv, write_csv, mib, cells, out_path, command):
         f.write("\n".join(lines) + "\n")
 
 
+def write_dispatches(trace_csv, out_path, part, min_grid, command):
+    with open(trace_csv, newline="") as f:
+        rows = list(csv.reader(f))
+    hdr, body = rows[0], rows[1:]
+    iname = _col(hdr, "kernel_name")
+    i0 = _col(hdr, "start_timestamp")
+    i1 = _col(hdr, "end_timestamp")
+    ig = [_col(hdr, "grid_size_" + a) for a in "xyz"]
+    per = {}
+    for r in body:
+        if not r or part not in r[iname]:
+            continue
+        grid = 1
+        for i in ig:
+            grid *= int(r[i])
+        if grid < min_grid:
+            continue
+        d = per.setdefault(short_name(r[iname]), {"grid": grid, "ns": []})
+        d["ns"].append(int(r[i1]) - int(r[i0]))
+    lines = ["# Kernel time per dispatch, rocprofv3 --kernel-trace", "",
+             "Command:", "", "    " + command, "",
+             f"Dispatches of kernels named `*{part}*` with a grid of at least {min_grid} work-items.", "",
+             "| kernel | grid work-items | dispatches | avg ms | min ms | max ms |",
+             "|---|---|---|---|---|---|"]
+    for k in sorted(per):
+        ns = per[k]["ns"]
+        lines.append(f"| `{k}` | {per[k]['grid']} | {len(ns)} | "
+                     f"{sum(ns) / len(ns) * 1e-6:.4f} | {min(ns) * 1e-6:.4f} | {max(ns) * 1e-6:.4f} |")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def read_all_counters(path):
     """{kernel: {counter: [value per dispatch]}} for every counter in a run."""
     with open(path, newline="") as f:
@@ -233,6 +271,8 @@ def main(argv):
     elif len(argv) >= 5 and argv[0] == "counters" and "--" in argv:
         j = argv.index("--")
         write_counters(argv[1], argv[2], argv[3:j], " ".join(argv[j + 1:]))
+    elif len(argv) >= 5 and argv[0] == "dispatches":
+        write_dispatches(argv[1], argv[2], argv[3], int(argv[4]), " ".join(argv[5:]))
     elif len(argv) >= 6 and argv[0] == "traffic":
         write_traffic(argv[1], argv[2], int(argv[3]), int(argv[4]), argv[5], " ".join(argv[6:]))
     else:
