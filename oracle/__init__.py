@@ -62,6 +62,9 @@ def lib():
         L.or_nstep.argtypes = [ctypes.c_void_p]
         L.or_set_nstep.argtypes = [ctypes.c_void_p, ctypes.c_long]
         L.or_totals.argtypes = [ctypes.c_void_p, _D]
+        L.or_spin_add.argtypes = [ctypes.c_void_p, ctypes.c_double]
+        L.or_set_spinup.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_long]
+        L.or_shell_profile.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _D]
         L.or_counters.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_ulonglong)]
         L.or_face4.restype = ctypes.c_double
         L.or_face4.argtypes = [ctypes.c_double] * 4
@@ -176,6 +179,17 @@ class Oracle:
     def totals(self):
         out = np.zeros(8)
         lib().or_totals(self.h, out.ctypes.data_as(_D))
+        return out
+
+    def spin_add(self, domega: float):
+        lib().or_spin_add(self.h, domega)
+
+    def set_spinup(self, omega: float, nramp: int):
+        lib().or_set_spinup(self.h, omega, nramp)
+
+    def shell_profile(self, nbins: int, dr: float):
+        out = np.zeros((nbins, 8))
+        lib().or_shell_profile(self.h, nbins, dr, out.ctypes.data_as(_D))
         return out
 
     def counters(self):

@@ -76,6 +76,8 @@ typedef struct {
     long      nstep;
     unsigned long long cnt[4]; /* fv limiter hits, unsmooth cell-variables, non-converged Riemann, steps */
     int       nthreads;
+    double    spin_omega;  /* spin-up: final angular velocity about the z axis */
+    long      spin_nramp;  /* ... reached over the steps 0 .. spin_nramp-1 */
 } or_sim;
 
 static long cidx(const or_sim *S, int i, int j, int k)
@@ -1040,10 +1042,105 @@ double or_compute_dt(void *h, double cfl)
     return cfl * P->dx / smax;
 }
 
+/* ------------------------------------------------------------------ */
+/* Rotation and shell averages (Sec. 1, Sec. 3)                          */
+/* ------------------------------------------------------------------ */
+
+/* Spin-up (Sec. 3: a solid-body rotational flow is added gradually over
+   the first steps of a run, in the inertial frame).  [reading] Every fluid
+   cell gets the velocity increment domega * (z-hat x x) = domega * (-y, x, 0)
+   at its centre, the density and the pressure perturbation are left as they
+   are; m and E' are rebuilt from the new velocity. */
+void or_spin_add(void *h, double domega)
+{
+    or_sim *S = (or_sim *)h;
+    const or_params *P = &S->P;
+    double gm1 = P->gamma - 1.0;
+    for (int k = 0; k < P->n[2]; ++k)
+        for (int j = 0; j < P->n[1]; ++j)
+            for (int i = 0; i < P->n[0]; ++i) {
+                double x[3];
+                cell_pos(P, i, j, k, x);
+                if (solid_at(P, x)) continue;
+                long c = cidx(S, i, j, k);
+                double rho = S->rho0[c] + S->U[RHO][c];
+                double u = S->U[MX][c] / rho, v = S->U[MY][c] / rho, w = S->U[MZ][c] / rho;
+                double pp = gm1 * (S->U[EN][c] - 0.5 * (S->U[MX][c] * u + S->U[MY][c] * v + S->U[MZ][c] * w));
+                u += -domega * x[1];
+                v += domega * x[0];
+                S->U[MX][c] = rho * u;
+                S->U[MY][c] = rho * v;
+                S->U[EN][c] = pp / gm1 + 0.5 * rho * ((u * u + v * v) + w * w);
+            }
+}
+
+/* Ramp: the steps with index 0 .. nramp-1 each end with an increment of
+   omega / nramp, so that the rotation reaches omega after nramp steps.
+   nramp <= 0 or omega == 0 switches the ramp off. */
+void or_set_spinup(void *h, double omega, long nramp)
+{
+    or_sim *S = (or_sim *)h;
+    S->spin_omega = omega;
+    S->spin_nramp = (omega != 0.0 && nramp > 0) ? nramp : 0;
+}
+
+/* Averages on spherical surfaces (Sec. 1: the runs produce averages over
+   spheres that inform 1-D models).  Shell k holds the fluid cells whose
+   centre radius r (from the coordinate origin) has (k dr)^2 <= r^2 <
+   ((k+1) dr)^2, all in FP64 with r^2 = (x^2 + y^2) + z^2.  Per shell,
+   out[8k + q] is the sum over its cells of dV times
+     q = 0: 1            (volume)
+         1: rho          (mass)
+         2: fv           (entrained-fluid volume)
+         3: rho u_r      (radial mass flux; u_r = x.u / r)
+         4: rho u_r^2
+         5: rho |u|^2
+         6: rho (x v - y u)  (angular momentum about z)
+         7: fv^2
+   so that volume-weighted and mass-weighted shell averages are ratios. */
+void or_shell_profile(void *h, int nbins, double dr, double *out)
+{
+    or_sim *S = (or_sim *)h;
+    const or_params *P = &S->P;
+    double dv = P->dx * P->dx * P->dx;
+    double rmax2 = ((double)nbins * dr) * ((double)nbins * dr);
+    for (long q = 0; q < 8L * nbins; ++q) out[q] = 0.0;
+    for (int k = 0; k < P->n[2]; ++k)
+        for (int j = 0; j < P->n[1]; ++j)
+            for (int i = 0; i < P->n[0]; ++i) {
+                double x[3];
+                cell_pos(P, i, j, k, x);
+                if (solid_at(P, x)) continue;
+                double r2 = (x[0] * x[0] + x[1] * x[1]) + x[2] * x[2];
+                if (!(r2 < rmax2)) continue;
+                /* shell index from the squared bounds */
+                int b = (int)(sqrt(r2) / dr);
+                if (b > nbins - 1) b = nbins - 1;
+                while (b > 0 && ((double)b * dr) * ((double)b * dr) > r2) --b;
+                while (b < nbins - 1 && ((double)(b + 1) * dr) * ((double)(b + 1) * dr) <= r2) ++b;
+                long c = cidx(S, i, j, k);
+                double rho = S->rho0[c] + S->U[RHO][c];
+                double u = S->U[MX][c] / rho, v = S->U[MY][c] / rho, w = S->U[MZ][c] / rho;
+                double r = sqrt(r2);
+                double ur = r > 0.0 ? (x[0] * u + x[1] * v + x[2] * w) / r : 0.0;
+                double f = S->U[F0][c];
+                double *o = out + 8L * b;
+                o[0] += dv;
+                o[1] += rho * dv;
+                o[2] += f * dv;
+                o[3] += rho * ur * dv;
+                o[4] += rho * ur * ur * dv;
+                o[5] += rho * ((u * u + v * v) + w * w) * dv;
+                o[6] += rho * (x[0] * v - x[1] * u) * dv;
+                o[7] += f * f * dv;
+            }
+}
+
 void or_pass(void *h, int axis, double dt) { do_pass((or_sim *)h, axis, dt); }
 
 /* One step: three passes, x,y,z on even steps and z,y,x on odd ones
-   [reading: the paper only says three 1-D passes], then the heating source. */
+   [reading: the paper only says three 1-D passes], then the heating source,
+   then, during a spin-up ramp, the rotation increment. */
 void or_step(void *h, double dt)
 {
     or_sim *S = (or_sim *)h;
@@ -1060,6 +1157,7 @@ void or_step(void *h, double dt)
                     S->U[EN][cidx(S, i, j, k)] += heating_at(P, x) * dt;
                 }
     }
+    if (S->nstep < S->spin_nramp) or_spin_add(h, S->spin_omega / (double)S->spin_nramp);
     S->nstep++;
     S->cnt[3]++;
 }

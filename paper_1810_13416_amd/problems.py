@@ -363,6 +363,18 @@ def uniform(n=(16, 16, 16), rho=1.3, vel=(0.3, -0.2, 0.1), p=0.7, fv=0.4,
     return Problem(P, st + f, cfl=0.8, nsteps=10, name="uniform")
 
 
+def ball(n: int = 32, rho: float = 1.3, p: float = 0.7, fv: float = 0.4) -> Problem:
+    """Uniform gas at rest inside the confining sphere r = 1 inscribed in
+    the cube [-1,1]^3 (Sec. 3), no gravity, no base state (the solid cells
+    outside hold the same values and are never updated)."""
+    P = GridParams(n=(n, n, n), dx=2.0 / n, origin=(-1.0, -1.0, -1.0), bc=(BC_REFLECT,) * 3,
+                   gamma=5.0 / 3.0, sphere=1, sphere_r=1.0)
+    st = [np.full(P.shape, rho), _zeros(P), _zeros(P), _zeros(P), np.full(P.shape, p)]
+    f = [np.zeros(P.shape) for _ in range(10)]
+    f[0][:] = fv
+    return Problem(P, st + f, cfl=0.8, nsteps=10, name=f"ball_{n}")
+
+
 def bricks(count: int = 256, seed: int = 1814, nmin: int = 16, nmax: int = 64):
     """Batched-brick workload: `count` independent bricks with per-axis sizes
     drawn uniformly from [nmin, nmax]; each is, by a fair coin, a periodic
