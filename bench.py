@@ -34,6 +34,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -53,7 +54,42 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_gpu(prob, precision, steps, warmup, dev_prims):
+def run_rotation(sim, n, reps=5):
+    """The spin-up increment and the spherical-shell sums on the bench state:
+    time per call (HIP events on the library's stream) and algorithmic HBM
+    rate over the fluid cells, the only ones either touches.  FP32 state:
+    the increment reads rho', m_x, m_y, E' and the FP64 rho0 and writes m_x,
+    m_y, E' (36 B per fluid cell); the shell sums read rho', m (3), f0 and
+    rho0 (28 B per fluid cell)."""
+    import torch
+    st = sim.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(reps):
+        sim.spin_add(1e-3)
+    e1.record(st)
+    torch.cuda.synchronize()
+    spin_ms = e0.elapsed_time(e1) / reps
+    nbins, dr = n // 2, 2.0 / n               # shells of width dx out to the sphere r = 1
+    first = sim.shell_profile(nbins, dr)      # workspace allocation outside the timing
+    cells = int(round(first[:, 0].sum() / dr ** 3))
+    torch.cuda.synchronize()
+    e0.record(st)
+    prof = sim.shell_profile(nbins, dr)
+    e1.record(st)
+    torch.cuda.synchronize()
+    shell_ms = e0.elapsed_time(e1)
+    vol = float(prof[:, 0].sum())
+    return {"fluid_cells": cells,
+            "spin_add": {"ms": spin_ms, "bytes_per_cell": 36,
+                         "achieved_GBs": 36 * cells / (spin_ms * 1e-3) / 1e9},
+            "shell_profile": {"ms": shell_ms, "bins": nbins, "bytes_per_cell": 28,
+                              "achieved_GBs": 28 * cells / (shell_ms * 1e-3) / 1e9,
+                              "fluid_volume_over_4pi_3": vol / (4.0 * math.pi / 3.0)}}
+
+
+def run_gpu(prob, precision, steps, warmup, dev_prims, rotation=False):
     import torch
     from paper_1810_13416_amd import ppmb
     sim = ppmb.Sim(prob.params, precision, device="cuda:0")
@@ -78,6 +114,8 @@ def run_gpu(prob, precision, steps, warmup, dev_prims):
     info = {"ms_per_step": ms_step, "wall_ms_per_step": 1e3 * wall / steps,
             "pass_ms": {ax: (ms[i] / counts[i] if counts[i] else None) for i, ax in enumerate("xyz")},
             "totals": [float(v) for v in tot], "counters": cnt, "dt_last": sim.last_dt()}
+    if rotation:
+        info["rotation"] = run_rotation(sim, prob.params.n[0])
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -282,6 +320,7 @@ def main():
     ap.add_argument("--no-bricks", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-ppb2d", action="store_true")
+    ap.add_argument("--no-rotation", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -305,7 +344,7 @@ def main():
     cells = args.n ** 3
 
     log("FP32 run")
-    r32 = run_gpu(prob, ppmb.FP32, args.steps, args.warmup, dev)
+    r32 = run_gpu(prob, ppmb.FP32, args.steps, args.warmup, dev, rotation=not args.no_rotation)
     log(f"FP32: {r32['ms_per_step']:.3f} ms/step, passes {r32['pass_ms']}")
     r64 = None
     if not args.no_fp64:
@@ -355,6 +394,10 @@ def main():
         "fraction_of_hbm_roofline": value / (HBM_PEAK_GBS * 1e9 / (3 * 2 * N_FIELDS * 4)),
         "counters": r32["counters"],
     }
+    if "rotation" in r32:
+        out["rotation"] = r32["rotation"]
+        log(f"spin-up increment {r32['rotation']['spin_add']['ms']:.3f} ms, shell sums "
+            f"{r32['rotation']['shell_profile']['ms']:.3f} ms")
     if r64:
         out["fp64"] = {"value": cells / (r64["ms_per_step"] * 1e-3), "unit": "cell-updates/s",
                        "ms_per_step": r64["ms_per_step"], "pass_ms": r64["pass_ms"],

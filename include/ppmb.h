@@ -202,6 +202,46 @@ ppmb_status ppmb_set_nstep(ppmb_ctx *ctx, long nstep);
  * included), fv volume, min f0, max f0 }.  Synchronising. */
 ppmb_status ppmb_reduce_totals(ppmb_ctx *ctx, double out[8]);
 
+/* ---- rotation and spherical averages (Sec. 1, Sec. 3) ------------------
+ *
+ * Spin-up (Sec. 3: a solid-body rotation is added to the flow gradually
+ * over the first steps of a run; the frame stays inertial).  The increment
+ * domega gives every fluid cell of every brick the velocity change
+ * domega * (z-hat x x) = domega * (-y, x, 0), x the cell centre in grid
+ * coordinates (the rotation axis is the z axis through the coordinate
+ * origin), and keeps rho' and p' unchanged: m_x += rho du_x,
+ * m_y += rho du_y, E' += m.du + rho |du|^2 / 2, evaluated in FP64 and
+ * stored in the working precision.  Solid cells are not touched. */
+
+/* Ramp: each step whose index (ppmb_get_nstep before the step) lies in
+ * [0, nramp) ends, after its passes and heating, with an increment of
+ * omega / nramp, so the rotation reaches omega after nramp steps.  omega = 0
+ * or nramp = 0 switches it off.  Steps in the ramp are never HIP-graph
+ * captured (ppmb_batch_step mode 1 launches them directly), and the step
+ * after an increment takes its dt from a full CFL reduction.  INVALID for a
+ * non-finite omega or nramp < 0.  Host-side setting only. */
+ppmb_status ppmb_set_spinup(ppmb_ctx *ctx, double omega, long nramp);
+
+/* One increment domega now, on the current state of every brick.
+ * Asynchronous; INVALID for a non-finite domega or unbound state. */
+ppmb_status ppmb_spin_add(ppmb_ctx *ctx, double domega);
+
+/* Spherical-shell sums of one brick (Sec. 1: averages on spherical
+ * surfaces).  Shell k holds the fluid cells whose centre radius r (from the
+ * coordinate origin, r^2 = (x^2 + y^2) + z^2 in FP64) has
+ * (k dr)^2 <= r^2 < ((k+1) dr)^2; cells with r >= nbins dr are left out.
+ * host_out[8 k + q] (nbins * 8 doubles, caller-owned host memory) is the
+ * FP64 sum over shell k of dV times q = 0: 1 (volume), 1: rho, 2: f0,
+ * 3: rho u_r, 4: rho u_r^2, 5: rho |u|^2, 6: rho (x u_y - y u_x) (angular
+ * momentum about z), 7: f0^2, with u_r = x.u / r (0 at r = 0).  Averages
+ * over a shell are ratios (f0 by volume: q2 / q0; rms velocity by mass:
+ * sqrt(q5 / q1)).  The summation order is fixed, so the result is bitwise
+ * reproducible.  The library keeps a workspace of up to 8 * nbins * 4161
+ * doubles (per-block partial sums), grown on demand.  Synchronising.  INVALID for nbins outside
+ * [1, 1024], dr <= 0 or not finite, a bad brick index or unbound state;
+ * NOMEM if the workspace cannot be allocated. */
+ppmb_status ppmb_shell_profile(ppmb_ctx *ctx, int brick, int nbins, double dr, double *host_out);
+
 /* Event counters since create: { fv limiter activations that changed a
  * profile by more than round-off, unsmooth (cell, variable) pairs
  * constrained, Riemann problems re-solved in FP64 (FP32) or not converged

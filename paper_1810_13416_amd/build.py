@@ -27,6 +27,7 @@ UNITS = {
     "ppmb_sweep.hip": ["-ffp-contract=fast", "-fno-hip-fp32-correctly-rounded-divide-sqrt"],
     "ppmb_ppb2d.hip": ["-ffp-contract=fast", "-fno-hip-fp32-correctly-rounded-divide-sqrt"],
     "ppmb_aux.hip": ["-ffp-contract=off"],
+    "ppmb_rotation.hip": ["-ffp-contract=off"],
     "ppmb_api.hip": ["-ffp-contract=off"],
 }
 

@@ -55,6 +55,11 @@ struct ppmb_ctx {
     hipGraphExec_t gexec = nullptr;
     int gkey_cur = -1, gkey_par = -1;
     double gkey_cfl = 0.0;
+    // spin-up ramp: steps 0 .. spin_nramp-1 end with + spin_omega / spin_nramp
+    double spin_omega = 0.0;
+    long spin_nramp = 0;
+    double *shell_ws = nullptr;         // shell-sum block partials + result
+    size_t shell_ws_bytes = 0;
     std::string err;
 };
 
@@ -357,8 +362,24 @@ static ppmb_status enqueue_dt(ppmb_ctx *c, bool ready, double cfl, int b0, int b
     return enqueue_cfl(c, cfl, b0, b1);
 }
 
+// Spin-up increment on the current state of every brick.  The CFL maxima
+// of the last pass no longer describe the state afterwards.
+static ppmb_status enqueue_spin(ppmb_ctx *c, double domega)
+{
+    const int nblk = c->cfirst[c->nb];
+    if (c->prec == PPMB_FP64)
+        HIPCHK(c, launch_spin<double>(c->db, c->cmap, nblk, arena<double>(c, c->cur), c->base64, domega,
+                                      c->stream));
+    else
+        HIPCHK(c, launch_spin<float>(c->db, c->cmap, nblk, arena<float>(c, c->cur), c->base64, domega,
+                                     c->stream));
+    c->cfl_ready = false;
+    return PPMB_OK;
+}
+
 // One step of every brick: a launch per stage covering all bricks
-// (batched) or one launch per stage and brick (per_brick).
+// (batched) or one launch per stage and brick (per_brick); during a
+// spin-up ramp the step ends with the rotation increment.
 static ppmb_status enqueue_step(ppmb_ctx *c, bool with_cfl, double cfl, bool per_brick)
 {
     const bool ready = c->cfl_ready;
@@ -372,9 +393,10 @@ static ppmb_status enqueue_step(ppmb_ctx *c, bool with_cfl, double cfl, bool per
         TRY(enqueue_passes(c, 0, c->nb, c->cur));
     }
     c->cur = 1 - c->cur;           // three passes: the state ends in the other arena
+    c->cfl_ready = true;
+    if (c->nstep < c->spin_nramp) TRY(enqueue_spin(c, c->spin_omega / (double)c->spin_nramp));
     c->nstep++;
     c->steps++;
-    c->cfl_ready = true;
     return PPMB_OK;
 }
 
@@ -439,6 +461,7 @@ ppmb_status ppmb_destroy(ppmb_ctx *c)
     hipFree(c->work);
     hipFree(c->partials);
     hipFree(c->out8);
+    hipFree(c->shell_ws);
     delete c;
     return PPMB_OK;
 }
@@ -725,9 +748,11 @@ ppmb_status ppmb_step_auto(ppmb_ctx *c, double cfl, int nsteps)
 
 // Two steps (an even and an odd pass order) captured once into a hipGraph
 // and replayed; recaptured when the arena, the step parity or cfl differ
-// from the captured ones.
+// from the captured ones.  Steps inside a spin-up ramp are never captured.
 static ppmb_status graph_steps(ppmb_ctx *c, double cfl, int nsteps)
 {
+    // steps of a spin-up ramp differ from one another: launched directly
+    for (; nsteps > 0 && c->nstep < c->spin_nramp; --nsteps) TRY(enqueue_step(c, true, cfl, false));
     int pairs = nsteps / 2;
     if (pairs > 0) {
         // the captured steps take dt from the maxima in work[]: make them
@@ -830,6 +855,53 @@ ppmb_status ppmb_brick_totals(ppmb_ctx *c, int brick, double out[8])
 }
 
 ppmb_status ppmb_reduce_totals(ppmb_ctx *c, double out[8]) { return ppmb_brick_totals(c, 0, out); }
+
+ppmb_status ppmb_set_spinup(ppmb_ctx *c, double omega, long nramp)
+{
+    if (!c || !std::isfinite(omega) || nramp < 0) return PPMB_ERR_INVALID;
+    c->spin_omega = omega;
+    c->spin_nramp = (omega != 0.0 && nramp > 0) ? nramp : 0;
+    return PPMB_OK;
+}
+
+ppmb_status ppmb_spin_add(ppmb_ctx *c, double domega)
+{
+    if (!c || !std::isfinite(domega)) return PPMB_ERR_INVALID;
+    TRY(need_state(c));
+    return enqueue_spin(c, domega);
+}
+
+ppmb_status ppmb_shell_profile(ppmb_ctx *c, int brick, int nbins, double dr, double *out)
+{
+    if (!c || !out || nbins < 1 || nbins > kShellMaxBins || !(dr > 0) || !std::isfinite(dr))
+        return PPMB_ERR_INVALID;
+    if (!((double)nbins * dr < 1e300)) return PPMB_ERR_INVALID;
+    TRY(check_brick(c, brick));
+    const Brick &B = c->hb[brick];
+    const long nwork = shell_work_doubles(B.g, nbins);
+    const size_t need = sizeof(double) * ((size_t)nwork + 8 * (size_t)nbins);
+    if (need > c->shell_ws_bytes) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        hipFree(c->shell_ws);
+        c->shell_ws = nullptr;
+        c->shell_ws_bytes = 0;
+        if (hipMalloc(&c->shell_ws, need) != hipSuccess) {
+            c->shell_ws = nullptr;
+            return fail(c, PPMB_ERR_NOMEM, "shell-sum workspace");
+        }
+        c->shell_ws_bytes = need;
+    }
+    double *res = c->shell_ws + nwork;
+    if (c->prec == PPMB_FP64)
+        HIPCHK(c, launch_shell<double>(B.g, arena<double>(c, c->cur) + B.off, c->base64 + B.boff, nbins, dr,
+                                       c->shell_ws, res, c->stream));
+    else
+        HIPCHK(c, launch_shell<float>(B.g, arena<float>(c, c->cur) + B.off, c->base64 + B.boff, nbins, dr,
+                                      c->shell_ws, res, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(out, res, sizeof(double) * 8 * nbins, hipMemcpyDeviceToHost));
+    return PPMB_OK;
+}
 
 ppmb_status ppmb_counters(ppmb_ctx *c, unsigned long long out[4])
 {

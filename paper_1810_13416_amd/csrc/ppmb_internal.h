@@ -100,6 +100,23 @@ hipError_t launch_cfl_reset(unsigned long long *work, int b0, int nb, hipStream_
 hipError_t launch_cfl_finish(const Brick *bricks, int b0, int nb, const unsigned long long *work, double cfl,
                              double *dt, hipStream_t st);
 
+// Spin-up increment (Sec. 3): velocity += domega * (-y, x, 0) in every
+// fluid cell of the bricks the CFL block map covers, in place, p' kept.
+template <typename T>
+hipError_t launch_spin(const Brick *bricks, const BlockMap *map, int nblocks, T *state, const double *base64,
+                       double domega, hipStream_t st);
+
+// Spherical-shell sums (8 per shell, FP64, fixed order) of one brick:
+// block partials and group sums in work (shell_work_doubles(g, nbins)
+// doubles), result out[8 * shell + quantity] on the device, times dV.
+constexpr int kShellMaxBins = 1024;
+constexpr int kShellMaxBlocks = 4096;
+int shell_blocks(const Geom &g, int *rows_per_block);
+long shell_work_doubles(const Geom &g, int nbins);
+template <typename T>
+hipError_t launch_shell(const Geom &g, const T *state, const double *rho0, int nbins, double dr, double *work,
+                        double *out, hipStream_t st);
+
 hipError_t launch_set_scalar(double *dst, double v, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long *dst, int count, hipStream_t st);
 

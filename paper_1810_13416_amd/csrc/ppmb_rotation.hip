@@ -1,0 +1,285 @@
+// ppmb_rotation.hip -- the spin-up increment and the spherical-shell sums
+// (gfx950).
+//
+// Sec. 3 adds a solid-body rotation to a run gradually, in the inertial
+// frame; Sec. 1 describes the runs' averages over spherical surfaces.  Both
+// kernels are FP64 throughout and built without FP contraction.  Neither is
+// on the per-pass path: the increment runs once per step while a spin-up
+// ramp lasts, the shell sums when a caller asks for them.
+#include "ppmb_internal.h"
+
+#include <climits>
+#include <cmath>
+
+namespace ppmb {
+
+// ---------------------------------------------------------------------
+// Spin-up increment: u += domega * (z-hat x x) = domega * (-y, x, 0) in
+// every fluid cell, density and pressure perturbation unchanged:
+//   m_x += rho du_x,  m_y += rho du_y,
+//   E'  += m . du + rho |du|^2 / 2   (the kinetic-energy change at fixed p').
+// In place on the current state arena; one thread per cell, the blocks of
+// the CFL map (kCflBlockCells cells each, any number of bricks).
+// ---------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void spin_kernel(const Brick *bricks, const BlockMap *map, T *arena,
+                                                   const double *base64, double domega)
+{
+    const BlockMap m = map[blockIdx.x];
+    const Brick &B = bricks[m.brick];
+    const Geom g = B.g;
+    const long nc = B.ncell;
+    T *S = arena + B.off;
+    const long fs = g.fs;
+    const double *rho0 = base64 + B.boff;
+    const long c0 = (long)m.local * kCflBlockCells;
+    const long c1 = c0 + kCflBlockCells < nc ? c0 + kCflBlockCells : nc;
+    for (long c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+        const unsigned nx = (unsigned)g.n[0], ny = (unsigned)g.n[1];
+        const unsigned row = (unsigned)c / nx, i = (unsigned)c - row * nx;
+        const unsigned k = row / ny, j = row - k * ny;
+        const double x = centre(g, 0, i), y = centre(g, 1, j);
+        if (g.sphere && solid_at(g, x, y, centre(g, 2, k))) continue;
+        const long e = (long)i + (long)j * g.px + (long)k * g.plane;
+        const double rho = rho0[e] + (double)S[RHO * fs + e];
+        const double mx = (double)S[MX * fs + e], my = (double)S[MY * fs + e];
+        const double en = (double)S[EN * fs + e];
+        const double dux = -domega * y, duy = domega * x;
+        S[MX * fs + e] = T(mx + rho * dux);
+        S[MY * fs + e] = T(my + rho * duy);
+        S[EN * fs + e] = T(en + (mx * dux + my * duy) + 0.5 * rho * (dux * dux + duy * duy));
+    }
+}
+
+template <typename T>
+hipError_t launch_spin(const Brick *bricks, const BlockMap *map, int nblocks, T *state, const double *base64,
+                       double domega, hipStream_t st)
+{
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((spin_kernel<T>), dim3(nblocks), dim3(256), 0, st, bricks, map, state, base64, domega);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// Shell sums.  Shell b holds the fluid cells whose centre has
+// (b dr)^2 <= r^2 < ((b+1) dr)^2, r^2 = (x^2 + y^2) + z^2 in FP64; per shell
+// eight sums of dV times: 1, rho, f0, rho u_r, rho u_r^2, rho |u|^2,
+// rho (x u_y - y u_x), f0^2 (u_r = x.u / r, 0 at r = 0), from the momenta:
+// rho u_r = x.m / r, rho u_r^2 = (x.m / r)^2 / rho, rho |u|^2 = |m|^2 / rho.
+//
+// Along an x-row r^2 = x^2 + const falls for x < 0 and rises for x >= 0, so
+// on each side of x = 0 the cells of one shell are one contiguous run.
+// Block b (one wave) walks a fixed run of rows in chunks of 64 cells (the
+// next chunk's loads in flight while the current one is reduced); a
+// segmented inclusive scan over the lanes (runs = equal shell and side)
+// leaves each run's sum in its last lane, which adds it to the block's
+// shell array in LDS, the x < 0 side first: the runs of one side have
+// distinct shells, so no two lanes of one LDS update share an address.
+// The block arrays go to `work`; they are added per (shell, quantity) in
+// two fixed levels (groups of consecutive blocks, then the groups).  Every association is fixed, so the result is
+// bitwise reproducible.
+// ---------------------------------------------------------------------
+
+// shell of a radius: a first guess from r / dr, then the squared bounds
+// decide (so the guess only has to be close)
+__device__ __forceinline__ int shell_of(double r2, double r, double inv_dr, double dr, int nbins)
+{
+    int b = (int)(r * inv_dr);
+    b = b < 0 ? 0 : (b > nbins - 1 ? nbins - 1 : b);
+    while (b > 0 && __dmul_rn((double)b * dr, (double)b * dr) > r2) --b;
+    while (b < nbins - 1 && __dmul_rn((double)(b + 1) * dr, (double)(b + 1) * dr) <= r2) ++b;
+    return b;
+}
+
+// one lane's cell of a chunk: where it is, its shell key, its raw inputs
+template <typename T>
+struct ShellCell {
+    int key;              // 2 shell + (x >= 0), -1 if the cell takes no part
+    double x, y, z, r;
+    double r0;
+    T rp, mx, my, mz, f;
+};
+
+template <typename T>
+__global__ __launch_bounds__(64) void shell_kernel(Geom g, const T *S, const double *rho0, int nbins,
+                                                   double dr, int rows_per_block, double *work)
+{
+    extern __shared__ double bins[];           // nbins * 8
+    const int lane = threadIdx.x;
+    for (int q = lane; q < nbins * 8; q += 64) bins[q] = 0.0;
+    __syncthreads();
+    const int ny = g.n[1];
+    const long nrows = (long)ny * g.n[2];
+    const long r0 = (long)blockIdx.x * rows_per_block;
+    const long r1 = r0 + rows_per_block < nrows ? r0 + rows_per_block : nrows;
+    const int cpr = (g.n[0] + 63) / 64;        // chunks per row
+    const long nchunk = (r1 - r0) * cpr;
+    const double rmax = (double)nbins * dr;
+    const double rmax2 = __dmul_rn(rmax, rmax);
+    const double inv_dr = 1.0 / dr;
+    const long fs = g.fs;
+
+    auto fetch = [&](int ci, int j, int k, ShellCell<T> &c) {
+        const int i = ci * 64 + lane;
+        const bool in = i < g.n[0];
+        c.x = centre(g, 0, in ? i : 0);
+        c.y = centre(g, 1, j);
+        c.z = centre(g, 2, k);
+        const long e = (long)(in ? i : 0) + (long)j * g.px + (long)k * g.plane;
+        const double r2 = r2_exact(c.x, c.y, c.z);
+        c.r = sqrt(r2);
+        c.key = -1;
+        if (in && !(g.sphere && r2 >= g.sphere_t) && r2 < rmax2)
+            c.key = 2 * shell_of(r2, c.r, inv_dr, dr, nbins) + (c.x >= 0.0 ? 1 : 0);
+        c.r0 = 0.0;
+        c.rp = c.mx = c.my = c.mz = c.f = T(0);
+        if (c.key >= 0) {                      // solid cells and cells beyond the shells: no loads
+            c.r0 = rho0[e];
+            c.rp = S[RHO * fs + e];
+            c.mx = S[MX * fs + e];
+            c.my = S[MY * fs + e];
+            c.mz = S[MZ * fs + e];
+            c.f = S[F0 * fs + e];
+        }
+    };
+
+    int ci = 0, j = (int)(r0 % ny), k = (int)(r0 / ny);
+    ShellCell<T> cur, nxt;
+    if (nchunk > 0) fetch(ci, j, k, cur);
+    for (long c = 0; c < nchunk; ++c) {
+        // the next chunk (this row, else the next row) goes in flight first
+        if (++ci == cpr) {
+            ci = 0;
+            if (++j == ny) { j = 0; ++k; }
+        }
+        if (c + 1 < nchunk) fetch(ci, j, k, nxt);
+        const int key = cur.key;
+        if (__ballot(key >= 0) == 0) {         // no cell of this chunk takes part
+            cur = nxt;
+            continue;
+        }
+        double v[8];
+        {
+            const bool on = key >= 0;
+            const double rho = cur.r0 + (double)cur.rp;
+            const double irho = on ? 1.0 / rho : 0.0;
+            const double mx = (double)cur.mx, my = (double)cur.my, mz = (double)cur.mz;
+            const double f = (double)cur.f;
+            const double mr = cur.r > 0.0 ? ((cur.x * mx + cur.y * my) + cur.z * mz) / cur.r : 0.0;
+            v[0] = on ? 1.0 : 0.0;
+            v[1] = on ? rho : 0.0;
+            v[2] = on ? f : 0.0;
+            v[3] = on ? mr : 0.0;
+            v[4] = on ? mr * mr * irho : 0.0;
+            v[5] = on ? ((mx * mx + my * my) + mz * mz) * irho : 0.0;
+            v[6] = on ? cur.x * my - cur.y * mx : 0.0;
+            v[7] = on ? f * f : 0.0;
+        }
+        // segmented inclusive scan: a lane adds the partial d lanes below
+        // while no run boundary lies between them
+        const int kprev = __shfl_up(key, 1);
+        int head = (lane == 0 || kprev != key) ? 1 : 0;
+        // after the step with shift d a lane's window spans 2d lanes; stop
+        // once every window that could still grow already meets a boundary
+        for (int d = 1; d < 64; d <<= 1) {
+            const int hup = __shfl_up(head, d);
+            double up[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) up[q] = __shfl_up(v[q], d);
+            const bool take = lane >= d && !head;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = take ? up[q] + v[q] : v[q];
+            head = lane >= d ? (head | hup) : head;
+            if (__ballot(lane >= 2 * d && !head) == 0) break;
+        }
+        const int knext = __shfl_down(key, 1);
+        const bool last = key >= 0 && (lane == 63 || knext != key);
+        for (int side = 0; side < 2; ++side) {
+            if (last && (key & 1) == side) {
+                const int b = key >> 1;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) bins[b * 8 + q] += v[q];
+            }
+        }
+        cur = nxt;
+    }
+    __syncthreads();
+    double *P = work + (long)blockIdx.x * nbins * 8;
+    for (int q = lane; q < nbins * 8; q += 64) P[q] = bins[q];
+}
+
+// Block partials are added in two fixed levels: groups of kShellGroup
+// consecutive blocks (in block order), then the group sums (in group order).
+constexpr int kShellGroup = 64;
+
+__global__ __launch_bounds__(256) void shell_group_kernel(const double *work, int nblocks, int m, double *gsum)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= m) return;
+    const int b0 = blockIdx.y * kShellGroup;
+    const int b1 = b0 + kShellGroup < nblocks ? b0 + kShellGroup : nblocks;
+    double s = 0.0;
+    int b = b0;
+    for (; b + 8 <= b1; b += 8) {               // loads in flight together, adds in block order
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = work[(long)(b + u) * m + t];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += a[u];
+    }
+    for (; b < b1; ++b) s += work[(long)b * m + t];
+    gsum[(long)blockIdx.y * m + t] = s;
+}
+
+__global__ __launch_bounds__(256) void shell_finish_kernel(const double *gsum, int ngroups, int m, double dv,
+                                                           double *out)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= m) return;
+    double s = 0.0;
+    for (int gi = 0; gi < ngroups; ++gi) s += gsum[(long)gi * m + t];
+    out[t] = s * dv;
+}
+
+int shell_blocks(const Geom &g, int *rows_per_block)
+{
+    const long nrows = (long)g.n[1] * g.n[2];
+    long nb = nrows < kShellMaxBlocks ? nrows : kShellMaxBlocks;
+    const long rpb = (nrows + nb - 1) / nb;
+    *rows_per_block = (int)rpb;
+    return (int)((nrows + rpb - 1) / rpb);
+}
+
+long shell_work_doubles(const Geom &g, int nbins)
+{
+    int rpb = 0;
+    const long nb = shell_blocks(g, &rpb);
+    return 8L * nbins * (nb + (nb + kShellGroup - 1) / kShellGroup);
+}
+
+template <typename T>
+hipError_t launch_shell(const Geom &g, const T *state, const double *rho0, int nbins, double dr, double *work,
+                        double *out, hipStream_t st)
+{
+    int rpb = 0;
+    const int nb = shell_blocks(g, &rpb);
+    const size_t lds = sizeof(double) * 8 * (size_t)nbins;
+    const int m = nbins * 8, ng = (nb + kShellGroup - 1) / kShellGroup;
+    double *gsum = work + (long)nb * m;
+    hipLaunchKernelGGL((shell_kernel<T>), dim3(nb), dim3(64), lds, st, g, state, rho0, nbins, dr, rpb, work);
+    hipLaunchKernelGGL(shell_group_kernel, dim3((m + 255) / 256, ng), dim3(256), 0, st, work, nb, m, gsum);
+    hipLaunchKernelGGL(shell_finish_kernel, dim3((m + 255) / 256), dim3(256), 0, st, gsum, ng, m,
+                       g.dx * g.dx * g.dx, out);
+    return hipGetLastError();
+}
+
+#define PPMB_ROT_INST(T)                                                                          \
+    template hipError_t launch_spin<T>(const Brick *, const BlockMap *, int, T *, const double *,  \
+                                       double, hipStream_t);                                      \
+    template hipError_t launch_shell<T>(const Geom &, const T *, const double *, int, double,       \
+                                        double *, double *, hipStream_t);
+PPMB_ROT_INST(float)
+PPMB_ROT_INST(double)
+
+}  // namespace ppmb

@@ -31,7 +31,7 @@ EXPORTS = ("ppmb_create", "ppmb_destroy", "ppmb_state_bytes", "ppmb_state_layout
            "ppmb_brick_totals", "ppmb_brick_last_dt", "ppmb_batch_step", "ppmb_set_pass_shape",
            "ppmb_get_pass_shape", "ppmb_autotune", "ppmb_ppb2d_create", "ppmb_ppb2d_destroy",
            "ppmb_ppb2d_set", "ppmb_ppb2d_get", "ppmb_ppb2d_steps", "ppmb_ppb2d_get_nstep",
-           "ppmb_ppb2d_set_nstep")
+           "ppmb_ppb2d_set_nstep", "ppmb_set_spinup", "ppmb_spin_add", "ppmb_shell_profile")
 
 
 class PPMBError(RuntimeError):
@@ -112,6 +112,9 @@ def load():
         "ppmb_ppb2d_steps": [p, d, i],
         "ppmb_ppb2d_get_nstep": [p, ctypes.POINTER(ctypes.c_long)],
         "ppmb_ppb2d_set_nstep": [p, ctypes.c_long],
+        "ppmb_set_spinup": [p, d, ctypes.c_long],
+        "ppmb_spin_add": [p, d],
+        "ppmb_shell_profile": [p, i, i, d, _D],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -280,6 +283,22 @@ class Sim:
         self._check(self.L.ppmb_counters(self.h, out))
         return [int(v) for v in out]
 
+    def set_spinup(self, omega: float, nramp: int):
+        """Steps 0 .. nramp-1 each end with a solid-body rotation increment
+        omega / nramp about the z axis."""
+        self._check(self.L.ppmb_set_spinup(self.h, float(omega), int(nramp)))
+
+    def spin_add(self, domega: float):
+        self._check(self.L.ppmb_spin_add(self.h, float(domega)))
+
+    def shell_profile(self, nbins: int, dr: float, brick: int = 0):
+        """(nbins, 8) FP64 shell sums: volume, mass, f0, rho u_r, rho u_r^2,
+        rho |u|^2, angular momentum about z, f0^2 (each times dV)."""
+        out = np.zeros((int(nbins), 8))
+        self._check(self.L.ppmb_shell_profile(self.h, int(brick), int(nbins), float(dr),
+                                              out.ctypes.data_as(_D)))
+        return out
+
     def profile(self, enable=True):
         self._check(self.L.ppmb_profile_enable(self.h, 1 if enable else 0))
 
@@ -390,6 +409,22 @@ class Batch:
         out = (ctypes.c_ulonglong * 4)()
         self._check(self.L.ppmb_counters(self.h, out))
         return [int(v) for v in out]
+
+    def set_spinup(self, omega: float, nramp: int):
+        """Steps 0 .. nramp-1 each end with a solid-body rotation increment
+        omega / nramp about the z axis."""
+        self._check(self.L.ppmb_set_spinup(self.h, float(omega), int(nramp)))
+
+    def spin_add(self, domega: float):
+        self._check(self.L.ppmb_spin_add(self.h, float(domega)))
+
+    def shell_profile(self, nbins: int, dr: float, brick: int = 0):
+        """(nbins, 8) FP64 shell sums: volume, mass, f0, rho u_r, rho u_r^2,
+        rho |u|^2, angular momentum about z, f0^2 (each times dV)."""
+        out = np.zeros((int(nbins), 8))
+        self._check(self.L.ppmb_shell_profile(self.h, int(brick), int(nbins), float(dr),
+                                              out.ctypes.data_as(_D)))
+        return out
 
     def synchronize(self):
         self._check(self.L.ppmb_synchronize(self.h))

@@ -4,7 +4,7 @@
     python -m paper_1810_13416_amd.profsum traffic <fetch counter_collection.csv>
            <write counter_collection.csv> <calib MiB> <cells> <out.txt> <command...>
     python -m paper_1810_13416_amd.profsum counters <out.md> <title> <csv> [<csv> ...] -- <command...>
-    python -m paper_1810_13416_amd.profsum dispatches <kernel_trace.csv> <out.md> <name part>
+    python -m paper_1810_13416_amd.profsum dispatches <kernel_trace.csv> <out.md> <name part[,part...]>
            <min grid threads> <command...>
 
 `stats` turns a `--kernel-trace --stats` run into a table of kernels by
@@ -16,7 +16,7 @@ known size (`bench.py --calib-copy-mib M`, which reads M MiB and writes M
 MiB), and records a hash of the pass sources so that a reader can tell
 whether the figures still describe the kernels as built.  `dispatches`
 summarises, from the per-dispatch trace of a `--kernel-trace` run, the
-launches of the kernels whose name contains a given part and whose grid has
+launches of the kernels whose name contains one of the given parts and whose grid has
 at least a given number of work-items (so that launches of one problem size
 are not averaged with those of another).
 """
@@ -186,9 +186,10 @@ def write_dispatches(trace_csv, out_path, part, min_grid, command):
     i0 = _col(hdr, "start_timestamp")
     i1 = _col(hdr, "end_timestamp")
     ig = [_col(hdr, "grid_size_" + a) for a in "xyz"]
+    parts = [p for p in part.split(",") if p]
     per = {}
     for r in body:
-        if not r or part not in r[iname]:
+        if not r or not any(p in r[iname] for p in parts):
             continue
         grid = 1
         for i in ig:
@@ -199,7 +200,8 @@ def write_dispatches(trace_csv, out_path, part, min_grid, command):
         d["ns"].append(int(r[i1]) - int(r[i0]))
     lines = ["# Kernel time per dispatch, rocprofv3 --kernel-trace", "",
              "Command:", "", "    " + command, "",
-             f"Dispatches of kernels named `*{part}*` with a grid of at least {min_grid} work-items.", "",
+             "Dispatches of kernels named " + " or ".join(f"`*{p}*`" for p in parts) +
+             f" with a grid of at least {min_grid} work-items.", "",
              "| kernel | grid work-items | dispatches | avg ms | min ms | max ms |",
              "|---|---|---|---|---|---|"]
     for k in sorted(per):

@@ -1,0 +1,151 @@
+"""GPU parity of the spin-up increment, the spin-up ramp inside steps and
+the spherical-shell sums (through the C ABI) against the FP64 oracle on the
+same inputs.  Both sides start from the same conserved values (the GPU's
+own, copied into the oracle), so FP32 contexts are compared on identical
+FP32-representable inputs.  Tolerances: FP64 relative 1e-12 (evaluation
+order only); FP32 stores round each updated value once (relative 6e-8),
+checked at 1e-6; shell sums are FP64 on both sides, checked at 1e-11 of
+each quantity's largest shell value, and the cell count of every shell
+exactly."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1810_13416_amd import problems as pr
+
+pytestmark = pytest.mark.gpu
+
+
+def sim(params, prec="fp64"):
+    from paper_1810_13416_amd import ppmb
+    return ppmb.Sim(params, ppmb.FP64 if prec == "fp64" else ppmb.FP32)
+
+
+def pair(prob, prec):
+    S = sim(prob.params, prec)
+    S.set_state(prob.state)
+    O = oracle.Oracle(prob.params, threads=8)
+    O.set_conserved(S.get_conserved())
+    return S, O
+
+
+def close(a, b, rel):
+    for q in range(15):
+        scale = max(float(np.max(np.abs(b[q]))), 1e-300)
+        err = float(np.max(np.abs(a[q] - b[q]))) / scale
+        assert err <= rel, (q, err)
+
+
+def profiles_close(g, o, dv, rel=1e-11):
+    # same cells in every shell: the volume column counts them exactly
+    assert np.array_equal(np.rint(g[:, 0] / dv), np.rint(o[:, 0] / dv))
+    for q in range(8):
+        scale = max(float(np.max(np.abs(o[:, q]))), 1e-300)
+        err = float(np.max(np.abs(g[:, q] - o[:, q]))) / scale
+        assert err <= rel, (q, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_spin_add_matches_oracle(prec):
+    prob = pr.config3(n=32)
+    S, O = pair(prob, prec)
+    S.spin_add(0.37)
+    S.spin_add(-0.11)
+    O.spin_add(0.37)
+    O.spin_add(-0.11)
+    close(S.get_conserved(), O.get_conserved(), 1e-13 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_shell_profile_matches_oracle(prec):
+    prob = pr.config3(n=32)
+    S, O = pair(prob, prec)
+    S.spin_add(0.5)
+    O.set_conserved(S.get_conserved())
+    for nbins, dr in ((40, 1.0 / 32), (7, 0.13), (1, 2.0)):
+        profiles_close(S.shell_profile(nbins, dr), O.shell_profile(nbins, dr), prob.params.dx ** 3)
+
+
+def test_shell_profile_long_ragged_rows_and_bricks():
+    # rows longer than one 256-cell chunk with a ragged tail, and a second
+    # brick of another shape: each brick's sums against its own oracle
+    from paper_1810_13416_amd import ppmb
+    rod = pr.GridParams(n=(300, 3, 2), dx=2.0 / 300, origin=(-1.0, -0.01, -0.0066),
+                        bc=(pr.BC_REFLECT,) * 3, gamma=5.0 / 3.0)
+    rng = np.random.default_rng(7)
+    st = [1.0 + 0.1 * rng.uniform(size=rod.shape)] + \
+         [0.1 * rng.uniform(-1, 1, size=rod.shape) for _ in range(3)] + \
+         [np.full(rod.shape, 0.8)] + [rng.uniform(size=rod.shape)] + \
+         [np.zeros(rod.shape) for _ in range(9)]
+    ball = pr.config3(n=20)
+    B = ppmb.Batch([ball.params, rod], ppmb.FP64)
+    B.set_state(0, ball.state)
+    B.set_state(1, st)
+    for b, params in ((0, ball.params), (1, rod)):
+        O = oracle.Oracle(params, threads=8)
+        O.set_conserved(B.get_conserved(b))
+        for nbins, dr in ((300, 1.0 / 150), (5, 0.3)):
+            profiles_close(B.shell_profile(nbins, dr, brick=b), O.shell_profile(nbins, dr), params.dx ** 3)
+        O.close()
+    B.close()
+
+
+def test_shell_profile_is_deterministic_and_validates_arguments():
+    from paper_1810_13416_amd import ppmb
+    prob = pr.config3(n=24)
+    S = sim(prob.params, "fp32")
+    S.set_state(prob.state)
+    a = S.shell_profile(30, 1.0 / 24)
+    b = S.shell_profile(30, 1.0 / 24)
+    assert np.array_equal(a, b)
+    for nbins, dr in ((0, 0.1), (1025, 0.1), (10, 0.0), (10, float("nan"))):
+        with pytest.raises(ppmb.PPMBError):
+            S.shell_profile(nbins, dr)
+
+
+@pytest.mark.parametrize("auto", [False, True])
+def test_spin_ramp_steps_match_oracle_fp64(auto):
+    prob = pr.config3(n=24)
+    S, O = pair(prob, "fp64")
+    S.set_spinup(0.6, 3)
+    O.set_spinup(0.6, 3)
+    if auto:
+        S.step_auto(prob.cfl, 5)
+        for _ in range(5):
+            dt = O.dt(prob.cfl)
+            O.step(dt)
+        assert abs(S.last_dt() / dt - 1.0) <= 4e-16
+    else:
+        for _ in range(5):
+            dt = O.dt(prob.cfl)
+            O.step(dt)
+            S.step(dt)
+    a, b = S.get_conserved(), O.get_conserved()
+    for q in range(15):
+        scale = max(float(np.sum(np.abs(b[q]))), 1e-300)
+        assert float(np.sum(np.abs(a[q] - b[q]))) / scale <= 1e-12, q
+    # the ramp added 0.6 about z: angular momentum of the fluid
+    dv = prob.params.dx ** 3
+    z, y, x = np.meshgrid(*(pr._centres(prob.params, ax) for ax in (2, 1, 0)), indexing="ij")
+    lz = float(np.sum(x * a[2] - y * a[1]) * dv)
+    assert lz > 0.0
+
+
+def test_spin_ramp_graph_mode_is_bitwise_the_direct_mode():
+    probs = pr.bricks(count=5, seed=11, nmin=8, nmax=20)
+    from paper_1810_13416_amd import ppmb
+    out = []
+    for mode in (0, 1):
+        B = ppmb.Batch([p.params for p in probs], ppmb.FP32)
+        for b, p in enumerate(probs):
+            B.set_state(b, p.state)
+        B.set_spinup(0.2, 3)
+        B.step(0.8, 7, mode=mode)
+        B.synchronize()
+        out.append([B.get_conserved(b) for b in range(len(probs))])
+        B.close()
+    for b in range(len(probs)):
+        for q in range(15):
+            assert np.array_equal(out[0][b][q], out[1][b][q]), (b, q)
