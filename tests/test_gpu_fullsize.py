@@ -133,3 +133,40 @@ def test_fullsize_fused_dt_equals_cfl_kernel(shell):
     del cons
     assert B.dt(shell.cfl) == fused
     B.close()
+
+
+def test_fullsize_brick_batch_matches_oracle_on_sampled_bricks():
+    # the 256-brick workload of the benchmark (FP32, autotuned launch shape,
+    # graph replay): one step, sampled bricks against the oracle from the
+    # same FP32-representable inputs and the GPU's per-brick dt; density
+    # and energy compared as full fields (base added back), as the FP32
+    # figure is defined
+    from paper_1810_13416_amd import ppmb
+    probs = pr.bricks()
+    B = ppmb.Batch([p.params for p in probs], ppmb.FP32)
+    for b, p in enumerate(probs):
+        B.set_state(b, p.state)
+    B.autotune(0.8, reps=1)
+    picks = [0, 17, 101, 200, 255]
+    start = {b: B.get_conserved(b) for b in picks}
+    B.step(0.8, 1, mode=1)
+    B.synchronize()
+    for b in picks:
+        O = oracle.Oracle(probs[b].params, threads=8)
+        O.set_conserved(start[b])
+        O.step(B.last_dt(b))
+        ref = O.get_conserved()
+        got = B.get_conserved(b)
+        r0, p0 = O.base()
+        gm1 = probs[b].params.gamma - 1.0
+        for c in (ref, got):
+            c[0] = c[0] + r0
+            c[4] = c[4] + p0 / gm1
+        O.close()
+        for q in range(15):
+            group = [5] if q >= 5 else ([1, 2, 3] if q in (1, 2, 3) else [q])
+            l1 = max(sum(float(np.sum(np.abs(ref[g]))) for g in group) / len(group), 1e-300)
+            li = max(max(float(np.max(np.abs(ref[g]))) for g in group), 1e-300)
+            d = np.abs(got[q] - ref[q])
+            assert float(np.sum(d)) / l1 <= 1e-5 and float(np.max(d)) / li <= 1e-5, (b, q)
+    B.close()
