@@ -117,21 +117,45 @@ __device__ __forceinline__ double grav_taper(const Geom &g, double r)
     return (g.grav[3] - r) / (g.grav[3] - g.grav[2]);
 }
 
+// The gravity and heating parameters of a grid on their own, so that a
+// kernel can take them from memory where it uses them.
+struct GravParams {
+    int kind;
+    double g[4];
+};
+struct HeatParams {
+    int kind;
+    double h[3];
+};
+__device__ __forceinline__ GravParams grav_params(const Geom &g)
+{
+    return GravParams{ g.grav_kind, { g.grav[0], g.grav[1], g.grav[2], g.grav[3] } };
+}
+__device__ __forceinline__ HeatParams heat_params(const Geom &g)
+{
+    return HeatParams{ g.heat_kind, { g.heat[0], g.heat[1], g.heat[2] } };
+}
+
 // Component `axis` of the gravitational acceleration at a point, in the
 // working precision; rt2 is the squared distance to the centre.
 template <typename T>
-__device__ __forceinline__ T gravity(const Geom &g, int axis, T xd, T rt2)
+__device__ __forceinline__ T gravity(const GravParams &p, int axis, T xd, T rt2)
 {
-    if (g.grav_kind == 1) return T(g.grav[axis]);
-    if (g.grav_kind == 2) {
+    if (p.kind == 1) return T(p.g[axis]);
+    if (p.kind == 2) {
         T r = tsqrt(rt2);
-        T rc = T(g.grav[1]);
-        T h = (r < rc) ? T(1.0 / g.grav[1]) : (rc * rc) * trcp(rt2 * r);
-        T r1 = T(g.grav[2]), r2 = T(g.grav[3]);
-        T t = r <= r1 ? T(1) : (r >= r2 ? T(0) : (r2 - r) * T(1.0 / (g.grav[3] - g.grav[2])));
-        return -T(g.grav[0]) * xd * h * t;
+        T rc = T(p.g[1]);
+        T h = (r < rc) ? T(1.0 / p.g[1]) : (rc * rc) * trcp(rt2 * r);
+        T r1 = T(p.g[2]), r2 = T(p.g[3]);
+        T t = r <= r1 ? T(1) : (r >= r2 ? T(0) : (r2 - r) * T(1.0 / (p.g[3] - p.g[2])));
+        return -T(p.g[0]) * xd * h * t;
     }
     return T(0);
+}
+template <typename T>
+__device__ __forceinline__ T gravity(const Geom &g, int axis, T xd, T rt2)
+{
+    return gravity<T>(grav_params(g), axis, xd, rt2);
 }
 
 // Heating profile: full below half the extent, smoothstep to zero at it.
@@ -145,11 +169,16 @@ __device__ __forceinline__ T heat_shape(T xi)
 }
 
 template <typename T>
+__device__ __forceinline__ T heating(const HeatParams &p, T z, T rt2)
+{
+    if (p.kind == 1) return T(p.h[0]) * heat_shape((z - T(p.h[2])) * T(1.0 / p.h[1]));
+    if (p.kind == 2) return T(p.h[0]) * heat_shape(tsqrt(rt2) * T(1.0 / p.h[1]));
+    return T(0);
+}
+template <typename T>
 __device__ __forceinline__ T heating(const Geom &g, T z, T rt2)
 {
-    if (g.heat_kind == 1) return T(g.heat[0]) * heat_shape((z - T(g.heat[2])) * T(1.0 / g.heat[1]));
-    if (g.heat_kind == 2) return T(g.heat[0]) * heat_shape(tsqrt(rt2) * T(1.0 / g.heat[1]));
-    return T(0);
+    return heating<T>(heat_params(g), z, rt2);
 }
 
 // Fluid cells of a pencil along `axis` through the cell centres with

@@ -100,6 +100,30 @@ __device__ __forceinline__ long opaque_s(long v)
     return v;
 }
 
+// Gravity and heating parameters read from the brick table where they are
+// used: scalar loads through a constant-memory pointer that the loop cannot
+// hoist (waited for on the scalar counter), instead of values kept in
+// vector registers across the loop, which at the register limit would be
+// spilled; a spill reload is a vector memory load, and waiting for it
+// waits for every load issued before it, the prefetches included.
+using GeomC = const __attribute__((address_space(4))) Geom;
+__device__ __forceinline__ GeomC *geom_c(const Geom *p)
+{
+    GeomC *q = (GeomC *)p;
+    asm volatile("" : "+s"(q));
+    return q;
+}
+__device__ __forceinline__ GravParams grav_now(const Geom *p)
+{
+    GeomC *q = geom_c(p);
+    return GravParams{ q->grav_kind, { q->grav[0], q->grav[1], q->grav[2], q->grav[3] } };
+}
+__device__ __forceinline__ HeatParams heat_now(const Geom *p)
+{
+    GeomC *q = geom_c(p);
+    return HeatParams{ q->heat_kind, { q->heat[0], q->heat[1], q->heat[2] } };
+}
+
 template <typename T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const T *p, int count)
 {
@@ -174,9 +198,10 @@ struct AxisInfo {
     static __device__ __forceinline__ bool odd(int q) { return q == 1 || q == 4 || q == 6; }
 };
 
-// March one pencil; la / lb index it across the lane and block axes.
+// March one pencil; la / lb index it across the lane and block axes;
+// gmem is the brick's grid in the brick table.
 template <typename T, int AX>
-__device__ void march(const Geom &g, const SweepArgs<T> &a, int la0, int lane, int lb,
+__device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, int la0, int lane, int lb,
                       unsigned &c_lim, unsigned &c_uns, unsigned &c_rie, double &cmax, bool &cbad)
 {
     using AI = AxisInfo<AX>;
@@ -300,7 +325,7 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la0, int lane, i
         const double bp0 = bld<double>(rsrc(a.p064 + ubase + c3 * sAX, rcnt), ic);
         {
             T xd = ox + (T(s) + T(0.5)) * dxT;
-            T gv = flT * gravity<T>(g, AX, xd, rtt + xd * xd);
+            T gv = flT * gravity<T>(grav_now(gmem), AX, xd, rtt + xd * xd);
             bool so = s < flo || s > fhi;
             T rho = r0 + rp;
             T ir = trcp(rho);
@@ -393,7 +418,7 @@ __device__ void march(const Geom &g, const SweepArgs<T> &a, int la0, int lane, i
             if (a.heat) {
                 T xd = ox + (T(cu_) + T(0.5)) * dxT;
                 T zc = AX == 2 ? xd : T(xt[2]);
-                hn[4] = hn[4] + heating<T>(g, zc, rtt + xd * xd) * dt;
+                hn[4] = hn[4] + heating<T>(heat_now(gmem), zc, rtt + xd * xd) * dt;
             }
 #pragma unroll
             for (int vv = 0; vv < 5; ++vv) hn[vv] = sol[1] ? cu3[vv] : hn[vv];
@@ -496,7 +521,7 @@ void sweep_kernel(BatchArgs<T> b)
     unsigned c_lim = 0, c_uns = 0, c_rie = 0;          // per lane; widened below
     double cmax = 0.0;
     bool cbad = false;
-    if (lb < g.n[cb]) march<T, AX>(g, a, la0, (int)(threadIdx.x & 63), lb, c_lim, c_uns, c_rie, cmax, cbad);
+    if (lb < g.n[cb]) march<T, AX>(g, &B.g, a, la0, (int)(threadIdx.x & 63), lb, c_lim, c_uns, c_rie, cmax, cbad);
     if (b.cfl) cfl_commit(b.work, m.brick, cmax, cbad);
     // event counters: one atomic per wave and counter
     unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
@@ -676,7 +701,7 @@ void sweep_x_kernel(BatchArgs<T> b)
             x_load(a.in, a.rho0, a.p0, nc, item_row(nit), nx, bc, item_i0(nit) + lane, cur);
         }
         const T xd = ox + (T(s) + T(0.5)) * dxT;
-        const T gv = fl * gravity<T>(g, 0, xd, rtt + xd * xd);
+        const T gv = fl * gravity<T>(grav_now(&B.g), 0, xd, rtt + xd * xd);
         const bool so = solid_at(g, centre(g, 0, s), yc, zc);
         const T rho = r0 + cu[0];
         const T ir = trcp(rho);
@@ -777,7 +802,7 @@ void sweep_x_kernel(BatchArgs<T> b)
             T hn[5], o[10];
             hydro_update(cu, Fl, F, nu, dt, gv, hn);
             ppb_update(pql, sg - sgl, T(0.5) * (sgl + sg), Gl, G, o);
-            if (a.heat) hn[4] = hn[4] + heating<T>(g, xt2, rtt + xd * xd) * dt;
+            if (a.heat) hn[4] = hn[4] + heating<T>(heat_now(&B.g), xt2, rtt + xd * xd) * dt;
 #pragma unroll
             for (int vv = 0; vv < 5; ++vv) hn[vv] = so ? cu[vv] : hn[vv];
 #pragma unroll
