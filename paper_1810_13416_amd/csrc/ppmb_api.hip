@@ -35,6 +35,7 @@ struct ppmb_ctx {
     double *dt = nullptr;               // per-brick dt
     unsigned long long *cnt = nullptr;  // [0..2] event counters
     unsigned long long *work = nullptr; // per brick: smax bits, non-physical flag
+    unsigned long long *cband = nullptr; // per brick: band edge of the fused CFL reduction, redo flag
     double *partials = nullptr;         // totals block partials
     double *out8 = nullptr;             // totals result
     PassShape shape{ 1, 4 };
@@ -236,6 +237,7 @@ static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_preci
     if (e == hipSuccess) e = hipMalloc(&c->dt, sizeof(double) * nbricks);
     if (e == hipSuccess) e = hipMalloc(&c->cnt, sizeof(unsigned long long) * 4);
     if (e == hipSuccess) e = hipMalloc(&c->work, sizeof(unsigned long long) * 2 * nbricks);
+    if (e == hipSuccess) e = hipMalloc(&c->cband, sizeof(unsigned long long) * 2 * nbricks);
     if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * 8 * kTotalsBlocks);
     if (e == hipSuccess) e = hipMalloc(&c->out8, sizeof(double) * 8);
     if (e == hipSuccess && own_state) {
@@ -250,7 +252,8 @@ static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_preci
     ppmb_status st = PPMB_OK;
     if (hipMemcpy(c->db, c->hb.data(), sizeof(Brick) * nbricks, hipMemcpyHostToDevice) != hipSuccess ||
         launch_zero_u64(c->cnt, 4, c->stream) != hipSuccess ||
-        launch_zero_u64(c->work, 2 * nbricks, c->stream) != hipSuccess)
+        launch_zero_u64(c->work, 2 * nbricks, c->stream) != hipSuccess ||
+        launch_zero_u64(c->cband, 2 * nbricks, c->stream) != hipSuccess)
         st = PPMB_ERR_HIP;
     if (st == PPMB_OK) st = build_maps(c);
     // base state NONE until set
@@ -315,11 +318,11 @@ static ppmb_status enqueue_pass(ppmb_ctx *c, int axis, int heat, int b0, int b1,
     if (c->prec == PPMB_FP64)
         e = launch_sweep<double>(axis, c->shape, c->db, c->pmap[axis] + f0, f1 - f0, arena<double>(c, from),
                                  arena<double>(c, 1 - from), c->base64, c->dt, c->cnt, heat, c->base64,
-                                 c->work, cfl, c->stream);
+                                 c->work, c->cband, cfl, c->stream);
     else
         e = launch_sweep<float>(axis, c->shape, c->db, c->pmap[axis] + f0, f1 - f0, arena<float>(c, from),
                                 arena<float>(c, 1 - from), static_cast<const float *>(c->baseT), c->dt,
-                                c->cnt, heat, c->base64, c->work, cfl, c->stream);
+                                c->cnt, heat, c->base64, c->work, c->cband, cfl, c->stream);
     if (e != hipSuccess) return hipfail(c, e, "sweep launch");
     if (c->profiling) {
         HIPCHK(c, hipEventRecord(tm.b, c->stream));
@@ -343,7 +346,7 @@ static ppmb_status enqueue_passes(ppmb_ctx *c, int b0, int b1, int from)
     const int order[2][3] = { { 0, 1, 2 }, { 2, 1, 0 } };
     const int *o = order[c->nstep & 1];
     for (int p = 0; p < 3; ++p) {
-        if (p == 2) HIPCHK(c, launch_cfl_reset(c->work, b0, b1 - b0, c->stream));
+        if (p == 2) HIPCHK(c, launch_cfl_arm(c->work, c->cband, b0, b1 - b0, c->stream));
         TRY(enqueue_pass(c, o[p], p == 2 ? heat : 0, b0, b1, from, p == 2 ? 1 : 0));
         from = 1 - from;
     }
@@ -356,7 +359,13 @@ static ppmb_status enqueue_passes(ppmb_ctx *c, int b0, int b1, int from)
 static ppmb_status enqueue_dt(ppmb_ctx *c, bool ready, double cfl, int b0, int b1)
 {
     if (ready) {
-        HIPCHK(c, launch_cfl_finish(c->db, b0, b1 - b0, c->work, cfl, c->dt, c->stream));
+        const int f0 = c->cfirst[b0], f1 = c->cfirst[b1];
+        if (c->prec == PPMB_FP64)
+            HIPCHK(c, launch_cfl_finish<double>(c->db, b0, b1 - b0, c->cmap + f0, f1 - f0, arena<double>(c, c->cur),
+                                                c->base64, c->work, c->cband, cfl, c->dt, c->stream));
+        else
+            HIPCHK(c, launch_cfl_finish<float>(c->db, b0, b1 - b0, c->cmap + f0, f1 - f0, arena<float>(c, c->cur),
+                                               c->base64, c->work, c->cband, cfl, c->dt, c->stream));
         return PPMB_OK;
     }
     return enqueue_cfl(c, cfl, b0, b1);
@@ -459,6 +468,7 @@ ppmb_status ppmb_destroy(ppmb_ctx *c)
     hipFree(c->dt);
     hipFree(c->cnt);
     hipFree(c->work);
+    hipFree(c->cband);
     hipFree(c->partials);
     hipFree(c->out8);
     hipFree(c->shell_ws);

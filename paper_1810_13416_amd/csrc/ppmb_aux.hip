@@ -276,12 +276,15 @@ __global__ void cfl_reset_kernel(unsigned long long *work, int b0, int nb)
     for (int b = threadIdx.x; b < nb; b += blockDim.x) work[2 * (b0 + b)] = 0ull;
 }
 
+// `only`: when given, blocks of bricks whose redo flag only[2 brick + 1] is
+// clear return at once.
 template <typename T>
 __global__ __launch_bounds__(256) void cfl_kernel(const Brick *bricks, const BlockMap *map,
                                                   const T *arena, const double *base64,
-                                                  unsigned long long *work)
+                                                  unsigned long long *work, const unsigned long long *only)
 {
     const BlockMap m = map[blockIdx.x];
+    if (only && only[2 * m.brick + 1] == 0ull) return;
     const Brick &B = bricks[m.brick];
     const Geom g = B.g;
     const long nc = B.ncell;
@@ -324,16 +327,63 @@ __global__ void cfl_finish_kernel(const Brick *bricks, int b0, int nb, const uns
     }
 }
 
-hipError_t launch_cfl_reset(unsigned long long *work, int b0, int nb, hipStream_t st)
+__global__ void cfl_arm_kernel(unsigned long long *work, unsigned long long *cband, int b0, int nb)
 {
-    hipLaunchKernelGGL(cfl_reset_kernel, dim3(1), dim3(256), 0, st, work, b0, nb);
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const int k = b0 + b;
+        const double prev = __longlong_as_double((long long)work[2 * k]);
+        cband[2 * k] = (unsigned long long)__double_as_longlong(prev * (1.0 - kCflBand));
+        work[2 * k] = 0ull;
+    }
+}
+
+// dt where the fused maximum reached the band edge; else clear the
+// maximum and raise the brick's redo flag
+__global__ void cfl_check_kernel(const Brick *bricks, int b0, int nb, unsigned long long *work,
+                                 unsigned long long *cband, double cfl, double *dt)
+{
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const int k = b0 + b;
+        const Brick &B = bricks[k];
+        const double smax = __longlong_as_double((long long)work[2 * k]);
+        const double edge = __longlong_as_double((long long)cband[2 * k]);
+        if (smax >= edge) {
+            dt[B.dti] = cfl * B.g.dx / smax;
+            cband[2 * k + 1] = 0ull;
+        } else {
+            work[2 * k] = 0ull;
+            cband[2 * k + 1] = 1ull;
+        }
+    }
+}
+
+__global__ void cfl_redo_finish_kernel(const Brick *bricks, int b0, int nb, const unsigned long long *work,
+                                       unsigned long long *cband, double cfl, double *dt)
+{
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const int k = b0 + b;
+        if (cband[2 * k + 1] == 0ull) continue;
+        const Brick &B = bricks[k];
+        dt[B.dti] = cfl * B.g.dx / __longlong_as_double((long long)work[2 * k]);
+        cband[2 * k + 1] = 0ull;
+    }
+}
+
+hipError_t launch_cfl_arm(unsigned long long *work, unsigned long long *cband, int b0, int nb, hipStream_t st)
+{
+    hipLaunchKernelGGL(cfl_arm_kernel, dim3(1), dim3(256), 0, st, work, cband, b0, nb);
     return hipGetLastError();
 }
 
-hipError_t launch_cfl_finish(const Brick *bricks, int b0, int nb, const unsigned long long *work, double cfl,
-                             double *dt, hipStream_t st)
+template <typename T>
+hipError_t launch_cfl_finish(const Brick *bricks, int b0, int nb, const BlockMap *map, int nblocks,
+                             const T *state, const double *base64, unsigned long long *work,
+                             unsigned long long *cband, double cfl, double *dt, hipStream_t st)
 {
-    hipLaunchKernelGGL(cfl_finish_kernel, dim3(1), dim3(256), 0, st, bricks, b0, nb, work, cfl, dt);
+    hipLaunchKernelGGL(cfl_check_kernel, dim3(1), dim3(256), 0, st, bricks, b0, nb, work, cband, cfl, dt);
+    hipLaunchKernelGGL((cfl_kernel<T>), dim3(nblocks), dim3(256), 0, st, bricks, map, state, base64, work,
+                       (const unsigned long long *)cband);
+    hipLaunchKernelGGL(cfl_redo_finish_kernel, dim3(1), dim3(256), 0, st, bricks, b0, nb, work, cband, cfl, dt);
     return hipGetLastError();
 }
 
@@ -343,7 +393,8 @@ hipError_t launch_cfl(const Brick *bricks, int b0, int nb, const BlockMap *map, 
                       double *dt, hipStream_t st)
 {
     hipLaunchKernelGGL(cfl_reset_kernel, dim3(1), dim3(256), 0, st, work, b0, nb);
-    hipLaunchKernelGGL((cfl_kernel<T>), dim3(nblocks), dim3(256), 0, st, bricks, map, state, base64, work);
+    hipLaunchKernelGGL((cfl_kernel<T>), dim3(nblocks), dim3(256), 0, st, bricks, map, state, base64, work,
+                       (const unsigned long long *)nullptr);
     hipLaunchKernelGGL(cfl_finish_kernel, dim3(1), dim3(256), 0, st, bricks, b0, nb, work, cfl, dt);
     return hipGetLastError();
 }
@@ -459,7 +510,10 @@ hipError_t launch_zero_u64(unsigned long long *dst, int count, hipStream_t st)
                                       const double *, unsigned long long *, double, double *,     \
                                       hipStream_t);                                               \
     template hipError_t launch_totals<T>(const Geom &, const T *, const double *, const double *,  \
-                                         double *, double *, hipStream_t);
+                                         double *, double *, hipStream_t);                          \
+    template hipError_t launch_cfl_finish<T>(const Brick *, int, int, const BlockMap *, int, const T *, \
+                                             const double *, unsigned long long *, unsigned long long *, \
+                                             double, double *, hipStream_t);
 PPMB_INST(float)
 PPMB_INST(double)
 

@@ -233,6 +233,27 @@ __device__ __forceinline__ double cell_speed(double r0, double p0, double rp, do
     return sp;
 }
 
+// Whether a cell's signal speed can reach `thr`, from the working-precision
+// values the pass holds: an upper bound of cell_speed (base from the
+// working-precision copy, rounding of every operation covered a hundred
+// times over by the 1e-5 margins) compared with thr.  A cell whose density
+// is not clearly positive or whose pressure bound is not positive always
+// answers yes, so that cell_speed sees every possibly non-physical cell.
+template <typename T>
+__device__ __forceinline__ bool speed_may_reach(T r0, T p0, T rp, T m1, T m2, T m3, T ep, T gam, T gm1, T thr)
+{
+    const T rho = r0 + rp;
+    if (!(rho > T(0.5) * r0) || !(rho > T(0))) return true;
+    const T ir = trcp(rho);
+    const T ke2 = (m1 * m1 + m2 * m2 + m3 * m3) * ir;
+    const T p = p0 + gm1 * (ep - T(0.5) * ke2);
+    const T err = T(1e-5) * (tabs(p0) + gm1 * (tabs(ep) + T(0.5) * ke2));
+    if (!(p - err > T(0))) return true;
+    const T umax = tmax(tabs(m1), tmax(tabs(m2), tabs(m3))) * ir;
+    const T s = (umax + tsqrt(gam * (p + err) * ir)) * T(1.00001);
+    return !(s < thr);
+}
+
 // ---------------------------------------------------------------------
 // PPM reconstruction (Sec. 1)
 // ---------------------------------------------------------------------

@@ -40,14 +40,17 @@ int pass_blocks(const Geom &g, int axis, const PassShape &sh);
 
 // Fused 1-D pass along `axis` for the bricks whose blocks are
 // map[0 .. nblocks): one launch, every brick's pencils.  With `cfl` set the
-// pass also folds the signal speed of every fluid cell it writes into the
+// pass also folds the signal speed of the fluid cells it writes into the
 // CFL reduction slots work[2 brick] (max, as in the CFL kernel) and
-// work[2 brick + 1] (non-physical flag); base64 is the FP64 base arena.
+// work[2 brick + 1] (non-physical flag): the exact FP64 speed of every cell
+// whose working-precision bound reaches the band edge cband[2 brick] (FP64
+// bits, set by launch_cfl_arm), so the slot holds the exact maximum
+// whenever that maximum reaches the edge; base64 is the FP64 base arena.
 template <typename T>
 hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, const BlockMap *map,
                         int nblocks, const T *in, T *out, const T *base, const double *dt,
                         unsigned long long *counters, int heat, const double *base64,
-                        unsigned long long *work, int cfl, hipStream_t st);
+                        unsigned long long *work, const unsigned long long *cband, int cfl, hipStream_t st);
 
 // hydrostatic base state: FP64 RK4 node table (one thread), then cell values
 hipError_t launch_base_state(const Geom &g, int kind, const double *params, double *table,
@@ -94,11 +97,20 @@ hipError_t launch_totals(const Geom &g, const T *state, const double *rho0, cons
                          double *partials, double *out, hipStream_t st);
 constexpr int kTotalsBlocks = 1024;
 
-// the two ends of launch_cfl on their own: zero the maxima of bricks
-// [b0, b0 + nb); dt from the maxima already in work
-hipError_t launch_cfl_reset(unsigned long long *work, int b0, int nb, hipStream_t st);
-hipError_t launch_cfl_finish(const Brick *bricks, int b0, int nb, const unsigned long long *work, double cfl,
-                             double *dt, hipStream_t st);
+// The fused reduction of the last pass, around it.  Arm (before the pass):
+// per brick of [b0, b0 + nb) the band edge cband[2 brick] = (1 - kCflBand)
+// times the maximum now in work[2 brick] (that of the state the pass
+// starts from), then zero that maximum.  Finish (before the next step):
+// dt = cfl dx / max where the maximum reached the edge; the other bricks
+// (whose fastest cell may have been passed over) get a full CFL reduction
+// over the blocks of `map` (nblocks, CFL block map of the same bricks) and
+// then their dt.  Every launch is a kernel: no host decision, graph-safe.
+constexpr double kCflBand = 1e-4;
+hipError_t launch_cfl_arm(unsigned long long *work, unsigned long long *cband, int b0, int nb, hipStream_t st);
+template <typename T>
+hipError_t launch_cfl_finish(const Brick *bricks, int b0, int nb, const BlockMap *map, int nblocks,
+                             const T *state, const double *base64, unsigned long long *work,
+                             unsigned long long *cband, double cfl, double *dt, hipStream_t st);
 
 // Spin-up increment (Sec. 3): velocity += domega * (-y, x, 0) in every
 // fluid cell of the bricks the CFL block map covers, in place, p' kept.

@@ -29,6 +29,7 @@ struct SweepArgs {
     long fs;              // field stride (elements)
     int heat;             // 1: add the heating source after the update
     int cfl;              // 1: fold the written cells' signal speeds into the CFL slots
+    T cthr;               // cells whose speed bound is below this need no FP64 speed
 };
 
 // Arguments of one pass launch over a batch of bricks.
@@ -43,16 +44,22 @@ struct BatchArgs {
     unsigned long long *counters;
     const double *base64;
     unsigned long long *work;     // CFL slots, two per brick
+    const unsigned long long *cband;   // per brick: FP64 bits of the band's lower edge, redo flag
     int heat;
     int cfl;
 };
 
 template <typename T>
-__device__ __forceinline__ SweepArgs<T> brick_args(const BatchArgs<T> &b, const Brick &B)
+__device__ __forceinline__ float band_edge(double v, float) { return __double2float_rd(v); }
+__device__ __forceinline__ double band_edge(double v, double) { return v; }
+
+template <typename T>
+__device__ __forceinline__ SweepArgs<T> brick_args(const BatchArgs<T> &b, const Brick &B, int brick)
 {
+    const T thr = b.cfl ? band_edge(__longlong_as_double((long long)b.cband[2 * brick]), T(0)) : T(0);
     return SweepArgs<T>{b.in + B.off, b.out + B.off, b.base + B.boff, b.base + B.boff + B.g.fs,
                         b.dt + B.dti, b.counters, b.base64 + B.boff, b.base64 + B.boff + B.g.fs,
-                        B.g.fs, b.heat, b.cfl};
+                        B.g.fs, b.heat, b.cfl, thr};
 }
 
 // Global (x, y, z) order of a pass's (normal, t1, t2) components.
@@ -319,10 +326,6 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
         cu3[2] = bld<T>(rin(MX + AI::t1, c3), ld3);
         cu3[3] = bld<T>(rin(MX + AI::t2, c3), ld3);
         cu3[4] = bld<T>(rin(EN, c3), ld3);
-        // its FP64 base, for the fused CFL reduction of the last pass
-        const unsigned ic = a.cfl ? ld3 : kNoIdx;
-        const double br0 = bld<double>(rsrc(a.r064 + ubase + c3 * sAX, rcnt), ic);
-        const double bp0 = bld<double>(rsrc(a.p064 + ubase + c3 * sAX, rcnt), ic);
         {
             T xd = ox + (T(s) + T(0.5)) * dxT;
             T gv = flT * gravity<T>(grav_now(gmem), AX, xd, rtt + xd * xd);
@@ -427,14 +430,25 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
             bst(rout(MX + AI::t1, c3), st3, hn[2]);
             bst(rout(MX + AI::t2, c3), st3, hn[3]);
             bst(rout(EN, c3), st3, hn[4]);
-            // the next step's CFL reduction from the values just written
-            if (a.cfl && upd && valid && !sol[1]) {
-                double mx, my, mz;
-                to_global<AX, double>(hn[1], hn[2], hn[3], mx, my, mz);
-                bool bd;
-                const double sp = cell_speed(br0, bp0, (double)hn[0], mx, my, mz, (double)hn[4], g.gamma, bd);
-                if (bd) cbad = true;
-                else cmax = fmax(cmax, sp);
+            // the next step's CFL reduction from the values just written:
+            // the exact FP64 speed only where the bound reaches the band
+            // below the last maximum (in few waves), with its FP64 base
+            if (a.cfl) {
+                const bool need = upd && valid && !sol[1] &&
+                                  speed_may_reach(b0[0], b1[0], hn[0], hn[1], hn[2], hn[3], hn[4], gam, gm1, a.cthr);
+                if (__ballot(need)) {
+                    const unsigned ic = need ? ld3 : kNoIdx;
+                    const double br0 = bld<double>(rsrc(a.r064 + ubase + c3 * sAX, rcnt), ic);
+                    const double bp0 = bld<double>(rsrc(a.p064 + ubase + c3 * sAX, rcnt), ic);
+                    if (need) {
+                        double mx, my, mz;
+                        to_global<AX, double>(hn[1], hn[2], hn[3], mx, my, mz);
+                        bool bd;
+                        const double sp = cell_speed(br0, bp0, (double)hn[0], mx, my, mz, (double)hn[4], g.gamma, bd);
+                        if (bd) cbad = true;
+                        else cmax = fmax(cmax, sp);
+                    }
+                }
             }
         }
         // ---- (7) PPB: donor k-3, slab at face (k-4)+1/2, update cell k-4
@@ -510,7 +524,7 @@ void sweep_kernel(BatchArgs<T> b)
     const BlockMap m = b.map[blockIdx.x];
     const Brick &B = b.bricks[m.brick];
     const Geom g = B.g;
-    const SweepArgs<T> a = brick_args(b, B);
+    const SweepArgs<T> a = brick_args(b, B, m.brick);
     const int ca = (AX == 0) ? 1 : 0;
     const int cb = 3 - AX - ca;
     const int waves = blockDim.x >> 6;
@@ -640,7 +654,7 @@ void sweep_x_kernel(BatchArgs<T> b)
     const BlockMap m = b.map[blockIdx.x];
     const Brick &B = b.bricks[m.brick];
     const Geom g = B.g;
-    const SweepArgs<T> a = brick_args(b, B);
+    const SweepArgs<T> a = brick_args(b, B, m.brick);
     const int lane = threadIdx.x & 63;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     // this wave's run of items: item = (x-row, segment), rows in storage
@@ -817,16 +831,24 @@ void sweep_x_kernel(BatchArgs<T> b)
             bst(fo(EN), io, hn[4]);
 #pragma unroll
             for (int v = 0; v < 10; ++v) bst(fo(AI::ppb(v)), io, o[v]);
-            // the next step's CFL reduction from the values just written
-            const unsigned ic = a.cfl ? (unsigned)s : kNoIdx;
-            const double br0 = bld<double>(rsrc(a.r064 + row, nx), ic);
-            const double bp0 = bld<double>(rsrc(a.p064 + row, nx), ic);
-            if (a.cfl && own && !so) {
-                bool bd;
-                const double sp = cell_speed(br0, bp0, (double)hn[0], (double)hn[1], (double)hn[2],
-                                             (double)hn[3], (double)hn[4], g.gamma, bd);
-                if (bd) cbad = true;
-                else cmax = fmax(cmax, sp);
+            // the next step's CFL reduction from the values just written:
+            // the exact FP64 speed only where the bound reaches the band
+            // below the last maximum (in few waves), with its FP64 base
+            if (a.cfl) {
+                const bool need = own && !so &&
+                                  speed_may_reach(r0, pb, hn[0], hn[1], hn[2], hn[3], hn[4], gam, gm1, a.cthr);
+                if (__ballot(need)) {
+                    const unsigned ic = need ? (unsigned)s : kNoIdx;
+                    const double br0 = bld<double>(rsrc(a.r064 + row, nx), ic);
+                    const double bp0 = bld<double>(rsrc(a.p064 + row, nx), ic);
+                    if (need) {
+                        bool bd;
+                        const double sp = cell_speed(br0, bp0, (double)hn[0], (double)hn[1], (double)hn[2],
+                                                     (double)hn[3], (double)hn[4], g.gamma, bd);
+                        if (bd) cbad = true;
+                        else cmax = fmax(cmax, sp);
+                    }
+                }
             }
         }
       }
@@ -870,10 +892,10 @@ template <typename T>
 hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, const BlockMap *map,
                         int nblocks, const T *in, T *out, const T *base, const double *dt,
                         unsigned long long *counters, int heat, const double *base64,
-                        unsigned long long *work, int cfl, hipStream_t st)
+                        unsigned long long *work, const unsigned long long *cband, int cfl, hipStream_t st)
 {
     if (nblocks <= 0) return hipErrorInvalidValue;
-    BatchArgs<T> a{bricks, map, in, out, base, dt, counters, base64, work, heat, cfl};
+    BatchArgs<T> a{bricks, map, in, out, base, dt, counters, base64, work, cband, heat, cfl};
     if (axis == 0 && x_lanes_enabled()) {
         hipLaunchKernelGGL((sweep_x_kernel<T>), dim3(nblocks), dim3(64 * sh.x_waves), 0, st, a);
         return hipGetLastError();
@@ -890,10 +912,10 @@ hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, cons
 template hipError_t launch_sweep<float>(int, const PassShape &, const Brick *, const BlockMap *, int,
                                         const float *, float *, const float *, const double *,
                                         unsigned long long *, int, const double *, unsigned long long *,
-                                        int, hipStream_t);
+                                        const unsigned long long *, int, hipStream_t);
 template hipError_t launch_sweep<double>(int, const PassShape &, const Brick *, const BlockMap *, int,
                                          const double *, double *, const double *, const double *,
                                          unsigned long long *, int, const double *, unsigned long long *,
-                                         int, hipStream_t);
+                                         const unsigned long long *, int, hipStream_t);
 
 }  // namespace ppmb

@@ -314,6 +314,31 @@ def test_fused_cfl_reduction_equals_cfl_kernel(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_fused_cfl_reduction_falls_back_when_the_maximum_drops(prec):
+    # one fast cell in a gas at rest: after a step its speed has spread out
+    # and the maximum falls far below the band under the previous maximum
+    # inside which the last pass evaluates speeds exactly; the next dt must
+    # still be the CFL kernel's, bit for bit
+    prob = pr.ball(24)
+    st = [a.copy() for a in prob.state]
+    c0 = math.sqrt(5.0 / 3.0 * 0.7 / 1.3)
+    st[1][12, 12, 12] = 0.8 * c0
+    A = sim(prob.params, prec)
+    A.set_state(st)
+    d0 = A.dt(prob.cfl)
+    A.step_auto(prob.cfl, 1)
+    d1 = A.dt(prob.cfl)
+    assert d1 > d0 * 1.05               # the maximum did drop by more than the band
+    B = sim(prob.params, prec)
+    B.set_state(st)
+    B.step_auto(prob.cfl, 3)
+    C = sim(prob.params, prec)
+    C.set_state(st)
+    C.step_auto(prob.cfl, 2)
+    assert B.last_dt() == C.dt(prob.cfl)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_device_state_layout_is_the_documented_pitched_one(prec):
     # rows padded to 64 elements, padded field stride: reading the raw device
     # buffer through ppmb_state_layout gives the conserved fields
