@@ -191,6 +191,21 @@ static Geom geom_of(const ppmb_grid *grid)
     g.heat_kind = grid->heat_kind;
     for (int q = 0; q < 3; ++q) g.heat[q] = grid->heat[q];
     g.smooth_detect = grid->smooth_detect;
+    // the pass kernels' gravity and heating constants, once
+    double gc[6] = { 0, 0, 0, 0, 0, 0 };
+    if (g.grav_kind == 1) {
+        for (int q = 0; q < 3; ++q) gc[q] = g.grav[q];
+    } else if (g.grav_kind == 2) {
+        gc[0] = g.grav[0];
+        gc[1] = g.grav[1];
+        gc[2] = 1.0 / g.grav[1];
+        gc[3] = g.grav[2];
+        gc[4] = g.grav[3];
+        gc[5] = 1.0 / (g.grav[3] - g.grav[2]);
+    }
+    for (int q = 0; q < 6; ++q) { g.gcd[q] = gc[q]; g.gcf[q] = (float)gc[q]; }
+    const double hc[3] = { g.heat[0], g.heat_kind ? 1.0 / g.heat[1] : 0.0, g.heat[2] };
+    for (int q = 0; q < 3; ++q) { g.hcd[q] = hc[q]; g.hcf[q] = (float)hc[q]; }
     // pitched storage: rows padded to 64 elements (256-byte aligned in FP32),
     // fields padded by 17 x 64 elements more, so that corresponding cells of
     // the 15 fields do not share cache sets

@@ -28,6 +28,14 @@ struct Geom {
     int    heat_kind;
     double heat[3];
     int    smooth_detect;
+    // The pass kernels' gravity and heating constants in both working
+    // precisions, derived once on the host (each the FP64 value rounded):
+    // gravity kind 1: gx, gy, gz; kind 2: g0, rc, 1/rc, r1, r2, 1/(r2 - r1);
+    // heating: Q0, 1/extent, z0.
+    float  gcf[6];
+    double gcd[6];
+    float  hcf[3];
+    double hcd[3];
     // storage: cell (i, j, k) of field q at q * fs + i + j * px + k * plane
     // (rows start on 256-byte boundaries; fs is padded so that the fields do
     // not all fall on the same cache sets)
@@ -117,45 +125,20 @@ __device__ __forceinline__ double grav_taper(const Geom &g, double r)
     return (g.grav[3] - r) / (g.grav[3] - g.grav[2]);
 }
 
-// The gravity and heating parameters of a grid on their own, so that a
-// kernel can take them from memory where it uses them.
-struct GravParams {
-    int kind;
-    double g[4];
-};
-struct HeatParams {
-    int kind;
-    double h[3];
-};
-__device__ __forceinline__ GravParams grav_params(const Geom &g)
-{
-    return GravParams{ g.grav_kind, { g.grav[0], g.grav[1], g.grav[2], g.grav[3] } };
-}
-__device__ __forceinline__ HeatParams heat_params(const Geom &g)
-{
-    return HeatParams{ g.heat_kind, { g.heat[0], g.heat[1], g.heat[2] } };
-}
-
 // Component `axis` of the gravitational acceleration at a point, in the
-// working precision; rt2 is the squared distance to the centre.
-template <typename T>
-__device__ __forceinline__ T gravity(const GravParams &p, int axis, T xd, T rt2)
+// working precision; rt2 is the squared distance to the centre; c the
+// grid's constants in that precision (gcf / gcd of Geom).
+template <typename T, typename C>
+__device__ __forceinline__ T gravity(int kind, const C *c, int axis, T xd, T rt2)
 {
-    if (p.kind == 1) return T(p.g[axis]);
-    if (p.kind == 2) {
+    if (kind == 1) return c[axis];
+    if (kind == 2) {
         T r = tsqrt(rt2);
-        T rc = T(p.g[1]);
-        T h = (r < rc) ? T(1.0 / p.g[1]) : (rc * rc) * trcp(rt2 * r);
-        T r1 = T(p.g[2]), r2 = T(p.g[3]);
-        T t = r <= r1 ? T(1) : (r >= r2 ? T(0) : (r2 - r) * T(1.0 / (p.g[3] - p.g[2])));
-        return -T(p.g[0]) * xd * h * t;
+        T h = (r < c[1]) ? T(c[2]) : (c[1] * c[1]) * trcp(rt2 * r);
+        T t = r <= c[3] ? T(1) : (r >= c[4] ? T(0) : (c[4] - r) * c[5]);
+        return -c[0] * xd * h * t;
     }
     return T(0);
-}
-template <typename T>
-__device__ __forceinline__ T gravity(const Geom &g, int axis, T xd, T rt2)
-{
-    return gravity<T>(grav_params(g), axis, xd, rt2);
 }
 
 // Heating profile: full below half the extent, smoothstep to zero at it.
@@ -168,17 +151,13 @@ __device__ __forceinline__ T heat_shape(T xi)
     return T(1) - t * t * (T(3) - T(2) * t);
 }
 
-template <typename T>
-__device__ __forceinline__ T heating(const HeatParams &p, T z, T rt2)
+// c: the grid's heating constants in the working precision (hcf / hcd).
+template <typename T, typename C>
+__device__ __forceinline__ T heating(int kind, const C *c, T z, T rt2)
 {
-    if (p.kind == 1) return T(p.h[0]) * heat_shape((z - T(p.h[2])) * T(1.0 / p.h[1]));
-    if (p.kind == 2) return T(p.h[0]) * heat_shape(tsqrt(rt2) * T(1.0 / p.h[1]));
+    if (kind == 1) return c[0] * heat_shape((z - c[2]) * c[1]);
+    if (kind == 2) return c[0] * heat_shape(tsqrt(rt2) * c[1]);
     return T(0);
-}
-template <typename T>
-__device__ __forceinline__ T heating(const Geom &g, T z, T rt2)
-{
-    return heating<T>(heat_params(g), z, rt2);
 }
 
 // Fluid cells of a pencil along `axis` through the cell centres with

@@ -120,15 +120,21 @@ __device__ __forceinline__ GeomC *geom_c(const Geom *p)
     asm volatile("" : "+s"(q));
     return q;
 }
-__device__ __forceinline__ GravParams grav_now(const Geom *p)
+__device__ __forceinline__ auto grav_c(GeomC *q, float) { return q->gcf; }
+__device__ __forceinline__ auto grav_c(GeomC *q, double) { return q->gcd; }
+__device__ __forceinline__ auto heat_c(GeomC *q, float) { return q->hcf; }
+__device__ __forceinline__ auto heat_c(GeomC *q, double) { return q->hcd; }
+template <typename T>
+__device__ __forceinline__ T gravity_now(const Geom *p, int axis, T xd, T rt2)
 {
     GeomC *q = geom_c(p);
-    return GravParams{ q->grav_kind, { q->grav[0], q->grav[1], q->grav[2], q->grav[3] } };
+    return gravity<T>(q->grav_kind, grav_c(q, T(0)), axis, xd, rt2);
 }
-__device__ __forceinline__ HeatParams heat_now(const Geom *p)
+template <typename T>
+__device__ __forceinline__ T heating_now(const Geom *p, T z, T rt2)
 {
     GeomC *q = geom_c(p);
-    return HeatParams{ q->heat_kind, { q->heat[0], q->heat[1], q->heat[2] } };
+    return heating<T>(q->heat_kind, heat_c(q, T(0)), z, rt2);
 }
 
 template <typename T>
@@ -328,7 +334,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
         cu3[4] = bld<T>(rin(EN, c3), ld3);
         {
             T xd = ox + (T(s) + T(0.5)) * dxT;
-            T gv = flT * gravity<T>(grav_now(gmem), AX, xd, rtt + xd * xd);
+            T gv = flT * gravity_now<T>(gmem, AX, xd, rtt + xd * xd);
             bool so = s < flo || s > fhi;
             T rho = r0 + rp;
             T ir = trcp(rho);
@@ -421,7 +427,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
             if (a.heat) {
                 T xd = ox + (T(cu_) + T(0.5)) * dxT;
                 T zc = AX == 2 ? xd : T(xt[2]);
-                hn[4] = hn[4] + heating<T>(heat_now(gmem), zc, rtt + xd * xd) * dt;
+                hn[4] = hn[4] + heating_now<T>(gmem, zc, rtt + xd * xd) * dt;
             }
 #pragma unroll
             for (int vv = 0; vv < 5; ++vv) hn[vv] = sol[1] ? cu3[vv] : hn[vv];
@@ -715,7 +721,7 @@ void sweep_x_kernel(BatchArgs<T> b)
             x_load(a.in, a.rho0, a.p0, nc, item_row(nit), nx, bc, item_i0(nit) + lane, cur);
         }
         const T xd = ox + (T(s) + T(0.5)) * dxT;
-        const T gv = fl * gravity<T>(grav_now(&B.g), 0, xd, rtt + xd * xd);
+        const T gv = fl * gravity_now<T>(&B.g, 0, xd, rtt + xd * xd);
         const bool so = solid_at(g, centre(g, 0, s), yc, zc);
         const T rho = r0 + cu[0];
         const T ir = trcp(rho);
@@ -816,7 +822,7 @@ void sweep_x_kernel(BatchArgs<T> b)
             T hn[5], o[10];
             hydro_update(cu, Fl, F, nu, dt, gv, hn);
             ppb_update(pql, sg - sgl, T(0.5) * (sgl + sg), Gl, G, o);
-            if (a.heat) hn[4] = hn[4] + heating<T>(heat_now(&B.g), xt2, rtt + xd * xd) * dt;
+            if (a.heat) hn[4] = hn[4] + heating_now<T>(&B.g, xt2, rtt + xd * xd) * dt;
 #pragma unroll
             for (int vv = 0; vv < 5; ++vv) hn[vv] = so ? cu[vv] : hn[vv];
 #pragma unroll
