@@ -44,6 +44,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_traffic_shell512_fp32.txt")
+SQ_SUMMARY = os.path.join(ROOT, "profiles", "sweep_sq_counters_shell512_fp32.md")
+# VALU issue peak without packed FP32 (disabled in this build): 256 CUs x 4
+# SIMDs x 16 lanes per cycle x 2.4 GHz, in 10^12 lane-instructions per second
+VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 # the kernels behind each pass of the FP32 step
 PASS_KERNELS = {"x": "sweep_x_kernel<float>", "y": "sweep_kernel<float, 1>", "z": "sweep_kernel<float, 2>"}
 N_FIELDS = 15
@@ -128,6 +132,19 @@ def measured_traffic():
     from paper_1810_13416_amd import profsum
     try:
         info = profsum.read_traffic_summary(TRAFFIC_SUMMARY)
+    except OSError:
+        return None
+    if info.get("sweep_sources_sha256") != profsum.sweep_sources_hash():
+        return None
+    return info
+
+
+def measured_valu():
+    """VALU instructions per launch of each pass kernel, from the committed
+    SQ counter summary, if it was taken from the pass sources as they are now."""
+    from paper_1810_13416_amd import profsum
+    try:
+        info = profsum.read_counters_summary(SQ_SUMMARY)
     except OSError:
         return None
     if info.get("sweep_sources_sha256") != profsum.sweep_sources_hash():
@@ -394,6 +411,19 @@ def main():
         "fraction_of_hbm_roofline": value / (HBM_PEAK_GBS * 1e9 / (3 * 2 * N_FIELDS * 4)),
         "counters": r32["counters"],
     }
+    valu = measured_valu()
+    if valu:
+        per = {}
+        for k, v in kernels.items():
+            n = valu["kernels"].get(k, {}).get("SQ_INSTS_VALU")
+            if n:
+                per[k] = {"valu_per_cell": 64 * n / cells,
+                          "achieved": 64 * n / (v["avg_launch_ms"] * 1e-3) / 1e12}
+        if dom in per:
+            out["roofline_alu"] = {"bound": "alu", "kernel": dom, "achieved": per[dom]["achieved"],
+                                   "peak": VALU_PEAK_T, "unit": "T VALU lane-instructions/s",
+                                   "frac": per[dom]["achieved"] / VALU_PEAK_T, "kernels": per,
+                                   "source": os.path.relpath(SQ_SUMMARY, ROOT)}
     if "rotation" in r32:
         out["rotation"] = r32["rotation"]
         log(f"spin-up increment {r32['rotation']['spin_add']['ms']:.3f} ms, shell sums "

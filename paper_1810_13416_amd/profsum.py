@@ -240,6 +240,7 @@ def write_counters(out_path, title, csvs, command, only_prefix=("sweep", "cfl_ke
             per.setdefault(k, {}).update(cs)
     names = sorted({c for cs in per.values() for c in cs})
     lines = [f"# {title}", "", "Command (one run per counter group):", "", "    " + command, "",
+             f"sweep_sources_sha256: {sweep_sources_hash()}", "",
              "Mean per dispatch.", "",
              "| kernel | " + " | ".join(names) + " |", "|---|" + "---|" * len(names)]
     for k in sorted(per):
@@ -252,6 +253,24 @@ def write_counters(out_path, title, csvs, command, only_prefix=("sweep", "cfl_ke
         lines.append(f"| `{k}` | " + " | ".join(vals) + " |")
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
+
+
+def read_counters_summary(path):
+    """{kernel: {counter: mean per dispatch}} and the recorded sources hash."""
+    info = {"kernels": {}}
+    names = None
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("sweep_sources_sha256:"):
+                info["sweep_sources_sha256"] = line.split(":", 1)[1].strip()
+            elif line.startswith("| kernel |"):
+                names = [c.strip() for c in line.strip("|").split("|")][1:]
+            elif names and line.startswith("| `"):
+                cells = [c.strip() for c in line.strip("|").split("|")]
+                k = cells[0].strip("`")
+                info["kernels"][k] = {n: float(v) for n, v in zip(names, cells[1:]) if v}
+    return info
 
 
 def read_traffic_summary(path):
