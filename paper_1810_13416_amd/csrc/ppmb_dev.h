@@ -371,7 +371,7 @@ __device__ __forceinline__ Face<T> face_setup(const St<T> &L, const St<T> &R, T 
     return F;
 }
 
-template <typename T, bool FIXED = false>
+template <typename T>
 __device__ __forceinline__ bool two_shock(const St<T> &L, const St<T> &R, const Face<T> &F, T p0f,
                                           T gamma, int maxit, T tol, T &ps, T &us, T &iWL, T &iWR)
 {
@@ -384,27 +384,10 @@ __device__ __forceinline__ bool two_shock(const St<T> &L, const St<T> &R, const 
     iWR = F.iCR;
     us = T(0.5) * (L.u + R.u);
     const T CL2 = F.CL * F.CL, CR2 = F.CR * F.CR;
-    if (FIXED) {
-        // a fixed number of iterations, no early exit (a further Newton
-        // step from a converged state only moves it closer), then the
-        // residual test: no divergent loop exit, for the latency-bound
-        // marching kernel
-        T du = T(0);
-        for (int it = 0; it < maxit; ++it) {
-            iWL = F.iCL * trsq(T(1) + A * (ps - L.p) * F.ipL);
-            iWR = F.iCR * trsq(T(1) + A * (ps - R.p) * F.ipR);
-            T uLs = L.u - (ps - L.p) * iWL;
-            T uRs = R.u + (ps - R.p) * iWR;
-            T iZL = T(0.5) * iWL * (T(1) + CL2 * iWL * iWL);
-            T iZR = T(0.5) * iWR * (T(1) + CR2 * iWR * iWR);
-            T rden = trcp(iZL + iZR);
-            du = uRs - uLs;
-            us = (uLs * iZR + uRs * iZL) * rden;
-            ps = ps - du * rden;
-            if (ps < pfl) ps = pfl;
-        }
-        return tabs(du) <= tol * cs;
-    }
+    // Newton steps until the velocity residual at the current p* is within
+    // tol (cL + cR); the step taken with it is kept.  A wave leaves the
+    // loop when all its lanes have: at low Mach numbers the acoustic guess
+    // already passes, after one step
     for (int it = 0; it < maxit; ++it) {
         iWL = F.iCL * trsq(T(1) + A * (ps - L.p) * F.ipL);
         iWR = F.iCR * trsq(T(1) + A * (ps - R.p) * F.ipR);
@@ -462,7 +445,6 @@ __device__ __forceinline__ St<double> riemann64(const St<double> &L, const St<do
 template <typename T> struct Solver;
 
 template <> struct Solver<double> {
-    template <bool FIXED>
     __device__ static St<double> solve(const St<double> &L, const St<double> &R, double r0f,
                                        double p0f, double gamma, bool &counted)
     {
@@ -471,13 +453,12 @@ template <> struct Solver<double> {
 };
 
 template <> struct Solver<float> {
-    template <bool FIXED>
     __device__ static St<float> solve(const St<float> &L, const St<float> &R, float r0f,
                                       float p0f, float gamma, bool &counted)
     {
         Face<float> F = face_setup<float>(L, R, r0f, p0f, gamma);
         float ps, us, iWL, iWR;
-        bool ok = two_shock<float, FIXED>(L, R, F, p0f, gamma, 2, 1e-5f, ps, us, iWL, iWR);
+        bool ok = two_shock<float>(L, R, F, p0f, gamma, 2, 1e-5f, ps, us, iWL, iWR);
         counted = false;
         if (!ok) {
             counted = true;
@@ -693,8 +674,7 @@ __device__ __forceinline__ void trace_cell(const T *qL, const T *qR, const T *dq
 // reflecting wall (Sec. 3): the solid side takes the mirrored fluid state.
 // F = mass, normal, two transverse momenta, energy; sg = u* dt/dx.
 // Returns true when the Riemann problem was counted (FP64 re-solve).
-// FIXED: the FP32 Newton iteration without early exit (see two_shock).
-template <typename T, bool FIXED = false>
+template <typename T>
 __device__ __forceinline__ bool face_flux(St<T> Ls, St<T> Rs, bool sa, bool sb, T r0f, T p0f, T gam,
                                           T gfac, T nu, T *F, T &sg)
 {
@@ -711,7 +691,7 @@ __device__ __forceinline__ bool face_flux(St<T> Ls, St<T> Rs, bool sa, bool sb, 
     Ls.r = sa ? Rs.r : Ls.r; Ls.u = sa ? -Rs.u : Ls.u; Ls.v = sa ? Rs.v : Ls.v;
     Ls.w = sa ? Rs.w : Ls.w; Ls.p = sa ? Rs.p : Ls.p;
     bool cnt;
-    St<T> f = Solver<T>::template solve<FIXED>(Ls, Rs, r0f, p0f, gam, cnt);
+    St<T> f = Solver<T>::solve(Ls, Rs, r0f, p0f, gam, cnt);
     T rf = r0f + f.r;
     T Fr = rf * f.u;
     F[0] = Fr;

@@ -416,7 +416,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
         T F[5] = { T(0), T(0), T(0), T(0), T(0) };
         T sg = T(0);
         if (S || k >= 1) {
-            bool rie = face_flux<T, true>(TLp, TR, sol[1], sol[2], r0f[0], p0f[0], gam, gfac, nu, F, sg);
+            bool rie = face_flux<T>(TLp, TR, sol[1], sol[2], r0f[0], p0f[0], gam, gfac, nu, F, sg);
             if (rie && (S || (k - 3 >= -1 && k - 3 < n)) && valid) ++c_rie;
         }
         TLp = TL;
