@@ -63,6 +63,8 @@ def lib():
         L.or_set_nstep.argtypes = [ctypes.c_void_p, ctypes.c_long]
         L.or_totals.argtypes = [ctypes.c_void_p, _D]
         L.or_spin_add.argtypes = [ctypes.c_void_p, ctypes.c_double]
+        L.or_set_dissipation.argtypes = [ctypes.c_void_p, ctypes.c_double]
+        L.or_divergence.argtypes = [ctypes.c_void_p, _D]
         L.or_set_spinup.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_long]
         L.or_shell_profile.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _D]
         L.or_counters.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_ulonglong)]
@@ -179,6 +181,14 @@ class Oracle:
     def totals(self):
         out = np.zeros(8)
         lib().or_totals(self.h, out.ctypes.data_as(_D))
+        return out
+
+    def set_dissipation(self, k: float):
+        lib().or_set_dissipation(self.h, k)
+
+    def divergence(self):
+        out = np.empty(self.params.shape)
+        lib().or_divergence(self.h, out.ctypes.data_as(_D))
         return out
 
     def spin_add(self, domega: float):

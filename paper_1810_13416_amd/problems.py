@@ -453,6 +453,20 @@ def sod(n: int = 200) -> Problem:
                    cfl=0.8, nsteps=0, name=f"sod_{n}")
 
 
+def blast(n: int = 24, p_in: float = 10.0, radius: float = 0.2) -> Problem:
+    """Spherical blast in the periodic box [0,1)^3: gas at rest, rho = 1,
+    p = p_in inside r < radius about the centre and 1 outside (cell-centre
+    values), gamma = 1.4; fv marks the hot gas.  A strong outgoing shock."""
+    P = GridParams(n=(n, n, n), dx=1.0 / n, bc=(BC_PERIODIC,) * 3, gamma=1.4)
+    z, y, x = _mesh(P)
+    inside = ((x - 0.5) ** 2 + (y - 0.5) ** 2) + (z - 0.5) ** 2 < radius * radius
+    p = np.where(inside, p_in, 1.0)
+    f = [np.zeros(P.shape) for _ in range(10)]
+    f[0][:] = np.where(inside, 1.0, 0.0)
+    return Problem(P, [np.ones(P.shape), _zeros(P), _zeros(P), _zeros(P), p] + f,
+                   cfl=0.8, nsteps=10, name=f"blast_{n}")
+
+
 # ---------------------------------------------------------------------
 # The advection test of Fig. 3: a slotted disk in a rigid rotation (2-D)
 # ---------------------------------------------------------------------
