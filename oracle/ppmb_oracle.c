@@ -830,7 +830,7 @@ static void pencil_update(pencil *pc, double dt, double dx, double gamma, int de
         /* shock dissipation [reading, after CW84 Sec. 4 with the full 3-D
            divergence, Sec. 1]: where the flow converges, a diffusive flux
            of the conserved hydro perturbations across the face */
-        if (pc->diss_k > 0.0) {
+        if (pc->diss_k > 0.0 && !sa && !sb) {
             double nv = pc->diss_k * fmax(0.0, -0.5 * (pc->div[J] + pc->div[J + 1]));
             pc->FL[J][0] += nv * (pc->rhop[J] - pc->rhop[J + 1]);
             pc->FL[J][1] += nv * (pc->mn[J] - pc->mn[J + 1]);

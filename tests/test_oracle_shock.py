@@ -55,6 +55,22 @@ def test_divergence_at_the_confining_sphere_sees_a_wall():
     O.close()
 
 
+def test_no_dissipative_flux_through_the_sphere_wall():
+    # flow into the confining sphere's wall compresses the cells next to
+    # it; the solid cells take no update, so any flux across the wall would
+    # change the fluid's mass
+    prob = pr.ball(16)
+    st = [a.copy() for a in prob.state]
+    st[1][:] = 0.3
+    O = oracle.Oracle(prob.params, threads=2)
+    O.set_state(st)
+    O.set_dissipation(0.1)
+    m0 = O.totals()[0]
+    O.run(5, 0.8)
+    assert abs(O.totals()[0] / m0 - 1.0) <= 1e-14
+    O.close()
+
+
 def test_uniform_state_is_unchanged_with_dissipation():
     prob = pr.uniform()
     O = oracle.Oracle(prob.params, threads=4)
