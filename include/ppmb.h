@@ -202,6 +202,27 @@ ppmb_status ppmb_set_nstep(ppmb_ctx *ctx, long nstep);
  * included), fv volume, min f0, max f0 }.  Synchronising. */
 ppmb_status ppmb_reduce_totals(ppmb_ctx *ctx, double out[8]);
 
+/* ---- shock dissipation (Sec. 1) ---------------------------------------
+ *
+ * In flows with shocks the paper adds a fully 3-D dissipation inside shocks;
+ * its form is given in a reference that is not available, so this one is a
+ * reading after the artificial dissipation of Colella & Woodward (1984,
+ * Sec. 4): at the start of each step the undivided divergence of the cell
+ * velocity, D = sum over d of (u_d(i + e_d) - u_d(i - e_d)) / 2 (neighbours
+ * through the boundary conditions; a solid neighbour is a wall whose normal
+ * velocity is minus the cell's own), computed in FP64; then in each of the
+ * three passes, at every face between two fluid cells, the flux
+ * k max(0, -(D_i + D_i+1) / 2) (U_i - U_i+1) is added to the five conserved
+ * hydro perturbations U (rho', the three momenta, E').  It vanishes where
+ * the flow does not converge and conserves mass, momentum and energy.
+ * k = 0 (the default) switches it off and the passes run exactly as
+ * without it; k = 0.1 is the customary value.  ppmb_pass takes the
+ * divergence of its own input.  The library allocates one field of the
+ * working precision per brick on the first call with k > 0.  Host-side
+ * setting; drops a captured step graph.  INVALID for k < 0 or not finite;
+ * NOMEM if the field cannot be allocated. */
+ppmb_status ppmb_set_shock_dissipation(ppmb_ctx *ctx, double k);
+
 /* ---- rotation and spherical averages (Sec. 1, Sec. 3) ------------------
  *
  * Spin-up (Sec. 3: a solid-body rotation is added to the flow gradually

@@ -61,6 +61,8 @@ struct ppmb_ctx {
     long spin_nramp = 0;
     double *shell_ws = nullptr;         // shell-sum block partials + result
     size_t shell_ws_bytes = 0;
+    double dissk = 0.0;                 // shock dissipation coefficient (0: off)
+    void *divbuf = nullptr;             // its divergence field (one field per brick)
     std::string err;
 };
 
@@ -333,11 +335,13 @@ static ppmb_status enqueue_pass(ppmb_ctx *c, int axis, int heat, int b0, int b1,
     if (c->prec == PPMB_FP64)
         e = launch_sweep<double>(axis, c->shape, c->db, c->pmap[axis] + f0, f1 - f0, arena<double>(c, from),
                                  arena<double>(c, 1 - from), c->base64, c->dt, c->cnt, heat, c->base64,
-                                 c->work, c->cband, cfl, c->stream);
+                                 c->work, c->cband, static_cast<const double *>(c->divbuf), c->dissk, cfl,
+                                 c->stream);
     else
         e = launch_sweep<float>(axis, c->shape, c->db, c->pmap[axis] + f0, f1 - f0, arena<float>(c, from),
                                 arena<float>(c, 1 - from), static_cast<const float *>(c->baseT), c->dt,
-                                c->cnt, heat, c->base64, c->work, c->cband, cfl, c->stream);
+                                c->cnt, heat, c->base64, c->work, c->cband, static_cast<const float *>(c->divbuf),
+                                c->dissk, cfl, c->stream);
     if (e != hipSuccess) return hipfail(c, e, "sweep launch");
     if (c->profiling) {
         HIPCHK(c, hipEventRecord(tm.b, c->stream));
@@ -353,10 +357,27 @@ static bool any_heat(ppmb_ctx *c)
     return false;
 }
 
+// The divergence field of arena `from` for bricks [b0, b1) (shock
+// dissipation on).
+static ppmb_status enqueue_divergence(ppmb_ctx *c, int b0, int b1, int from)
+{
+    const int f0 = c->cfirst[b0], f1 = c->cfirst[b1];
+    if (c->prec == PPMB_FP64)
+        HIPCHK(c, launch_divergence<double>(c->db, c->cmap + f0, f1 - f0, arena<double>(c, from), c->base64,
+                                            static_cast<double *>(c->divbuf), c->stream));
+    else
+        HIPCHK(c, launch_divergence<float>(c->db, c->cmap + f0, f1 - f0, arena<float>(c, from), c->base64,
+                                           static_cast<float *>(c->divbuf), c->stream));
+    return PPMB_OK;
+}
+
 // Three passes (x,y,z on even steps, z,y,x on odd) for bricks [b0, b1);
-// the last one also reduces the CFL maxima of the new state.
+// the last one also reduces the CFL maxima of the new state.  With shock
+// dissipation on, the divergence of the state at the start of the step
+// drives it in all three.
 static ppmb_status enqueue_passes(ppmb_ctx *c, int b0, int b1, int from)
 {
+    if (c->dissk > 0.0) TRY(enqueue_divergence(c, b0, b1, from));
     const int heat = any_heat(c) ? 1 : 0;
     const int order[2][3] = { { 0, 1, 2 }, { 2, 1, 0 } };
     const int *o = order[c->nstep & 1];
@@ -487,6 +508,7 @@ ppmb_status ppmb_destroy(ppmb_ctx *c)
     hipFree(c->partials);
     hipFree(c->out8);
     hipFree(c->shell_ws);
+    hipFree(c->divbuf);
     delete c;
     return PPMB_OK;
 }
@@ -843,6 +865,7 @@ ppmb_status ppmb_pass(ppmb_ctx *c, int axis, double dt, int heat)
     if (!c || axis < 0 || axis > 2 || !(dt > 0)) return PPMB_ERR_INVALID;
     TRY(need_state(c));
     for (int b = 0; b < c->nb; ++b) HIPCHK(c, launch_set_scalar(c->dt + b, dt, c->stream));
+    if (c->dissk > 0.0) TRY(enqueue_divergence(c, 0, c->nb, c->cur));
     TRY(enqueue_pass(c, axis, heat ? (any_heat(c) ? 1 : 0) : 0, 0, c->nb, c->cur));
     c->cur = 1 - c->cur;
     c->cfl_ready = false;
@@ -880,6 +903,21 @@ ppmb_status ppmb_brick_totals(ppmb_ctx *c, int brick, double out[8])
 }
 
 ppmb_status ppmb_reduce_totals(ppmb_ctx *c, double out[8]) { return ppmb_brick_totals(c, 0, out); }
+
+ppmb_status ppmb_set_shock_dissipation(ppmb_ctx *c, double k)
+{
+    if (!c || !std::isfinite(k) || k < 0.0) return PPMB_ERR_INVALID;
+    if (k > 0.0 && !c->divbuf) {
+        const size_t bytes = (size_t)(c->total_base / 2) * c->esz;
+        if (hipMalloc(&c->divbuf, bytes) != hipSuccess) {
+            c->divbuf = nullptr;
+            return fail(c, PPMB_ERR_NOMEM, "divergence field");
+        }
+    }
+    c->dissk = k;
+    free_graph(c);                       // captured steps hold the previous setting
+    return PPMB_OK;
+}
 
 ppmb_status ppmb_set_spinup(ppmb_ctx *c, double omega, long nramp)
 {

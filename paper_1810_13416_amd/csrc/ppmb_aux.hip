@@ -474,6 +474,69 @@ hipError_t launch_totals(const Geom &g, const T *state, const double *rho0, cons
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------
+// Shock dissipation (Sec. 1: a fully 3-D dissipation inside shocks): the
+// undivided divergence of the cell-centred velocity, sum over d of
+// (u_d(i + e_d) - u_d(i - e_d)) / 2, neighbours through the boundary
+// conditions (a reflecting image's normal velocity flips), a solid
+// neighbour as a wall whose normal velocity is minus the cell's own.
+// ---------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ double vel_at(const Geom &g, const T *S, const double *rho0, long e, int d)
+{
+    return (double)S[(MX + d) * g.fs + e] / (rho0[e] + (double)S[RHO * g.fs + e]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void divergence_kernel(const Brick *bricks, const BlockMap *map,
+                                                         const T *arena, const double *base64, T *div)
+{
+    const BlockMap m = map[blockIdx.x];
+    const Brick &B = bricks[m.brick];
+    const Geom g = B.g;
+    const long nc = B.ncell;
+    const T *S = arena + B.off;
+    const double *rho0 = base64 + B.boff;
+    T *D = div + B.boff / 2;
+    const long c0 = (long)m.local * kCflBlockCells;
+    const long c1 = c0 + kCflBlockCells < nc ? c0 + kCflBlockCells : nc;
+    for (long c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+        const unsigned nx = (unsigned)g.n[0], ny = (unsigned)g.n[1];
+        const unsigned row = (unsigned)c / nx, i = (unsigned)c - row * nx;
+        const unsigned k = row / ny, j = row - k * ny;
+        const int ijk[3] = { (int)i, (int)j, (int)k };
+        const long e = (long)i + (long)j * g.px + (long)k * g.plane;
+        if (g.sphere && solid_at(g, centre(g, 0, i), centre(g, 1, j), centre(g, 2, k))) {
+            D[e] = T(0);
+            continue;
+        }
+        double sum = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            double un[2];
+            for (int side = 0; side < 2; ++side) {
+                int nb[3] = { ijk[0], ijk[1], ijk[2] };
+                int fl;
+                nb[d] = bc_source(ijk[d] + (side ? 1 : -1), g.n[d], g.bc[d], fl);
+                const bool sol = g.sphere && solid_at(g, centre(g, 0, nb[0]), centre(g, 1, nb[1]), centre(g, 2, nb[2]));
+                const long en = (long)nb[0] + (long)nb[1] * g.px + (long)nb[2] * g.plane;
+                un[side] = sol ? -vel_at(g, S, rho0, e, d) : (double)fl * vel_at(g, S, rho0, en, d);
+            }
+            sum += 0.5 * (un[1] - un[0]);
+        }
+        D[e] = T(sum);
+    }
+}
+
+template <typename T>
+hipError_t launch_divergence(const Brick *bricks, const BlockMap *map, int nblocks, const T *state,
+                             const double *base64, T *div, hipStream_t st)
+{
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((divergence_kernel<T>), dim3(nblocks), dim3(256), 0, st, bricks, map, state, base64, div);
+    return hipGetLastError();
+}
+
 __global__ void set_scalar_kernel(double *dst, double v)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = v;
@@ -513,7 +576,9 @@ hipError_t launch_zero_u64(unsigned long long *dst, int count, hipStream_t st)
                                          double *, double *, hipStream_t);                          \
     template hipError_t launch_cfl_finish<T>(const Brick *, int, int, const BlockMap *, int, const T *, \
                                              const double *, unsigned long long *, unsigned long long *, \
-                                             double, double *, hipStream_t);
+                                             double, double *, hipStream_t);                              \
+    template hipError_t launch_divergence<T>(const Brick *, const BlockMap *, int, const T *,          \
+                                             const double *, T *, hipStream_t);
 PPMB_INST(float)
 PPMB_INST(double)
 

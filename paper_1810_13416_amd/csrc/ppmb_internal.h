@@ -46,11 +46,22 @@ int pass_blocks(const Geom &g, int axis, const PassShape &sh);
 // whose working-precision bound reaches the band edge cband[2 brick] (FP64
 // bits, set by launch_cfl_arm), so the slot holds the exact maximum
 // whenever that maximum reaches the edge; base64 is the FP64 base arena.
+// With dissk > 0 the shock dissipation is added at every face between fluid
+// cells from `div` (launch_divergence of the pass input or of the state at
+// the start of the step).
 template <typename T>
 hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, const BlockMap *map,
                         int nblocks, const T *in, T *out, const T *base, const double *dt,
                         unsigned long long *counters, int heat, const double *base64,
-                        unsigned long long *work, const unsigned long long *cband, int cfl, hipStream_t st);
+                        unsigned long long *work, const unsigned long long *cband, const T *div, double dissk,
+                        int cfl, hipStream_t st);
+
+// Undivided velocity divergence of every cell of the bricks the CFL block
+// map covers (FP64 arithmetic, stored in the working precision): field of
+// brick B at div + B.boff / 2, pitched like the state; 0 in solid cells.
+template <typename T>
+hipError_t launch_divergence(const Brick *bricks, const BlockMap *map, int nblocks, const T *state,
+                             const double *base64, T *div, hipStream_t st);
 
 // hydrostatic base state: FP64 RK4 node table (one thread), then cell values
 hipError_t launch_base_state(const Geom &g, int kind, const double *params, double *table,

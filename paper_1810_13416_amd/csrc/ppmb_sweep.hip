@@ -30,6 +30,8 @@ struct SweepArgs {
     int heat;             // 1: add the heating source after the update
     int cfl;              // 1: fold the written cells' signal speeds into the CFL slots
     T cthr;               // cells whose speed bound is below this need no FP64 speed
+    const T *div;         // undivided velocity divergence (shock dissipation), same layout
+    T dissk;              // shock dissipation coefficient
 };
 
 // Arguments of one pass launch over a batch of bricks.
@@ -45,6 +47,8 @@ struct BatchArgs {
     const double *base64;
     unsigned long long *work;     // CFL slots, two per brick
     const unsigned long long *cband;   // per brick: FP64 bits of the band's lower edge, redo flag
+    const T *div;                 // divergence field, one field per brick at boff / 2
+    double dissk;                 // shock dissipation coefficient (kernels with DISS only)
     int heat;
     int cfl;
 };
@@ -59,7 +63,7 @@ __device__ __forceinline__ SweepArgs<T> brick_args(const BatchArgs<T> &b, const 
     const T thr = b.cfl ? band_edge(__longlong_as_double((long long)b.cband[2 * brick]), T(0)) : T(0);
     return SweepArgs<T>{b.in + B.off, b.out + B.off, b.base + B.boff, b.base + B.boff + B.g.fs,
                         b.dt + B.dti, b.counters, b.base64 + B.boff, b.base64 + B.boff + B.g.fs,
-                        B.g.fs, b.heat, b.cfl, thr};
+                        B.g.fs, b.heat, b.cfl, thr, b.div ? b.div + B.boff / 2 : nullptr, T(b.dissk)};
 }
 
 // Global (x, y, z) order of a pass's (normal, t1, t2) components.
@@ -213,7 +217,7 @@ struct AxisInfo {
 
 // March one pencil; la / lb index it across the lane and block axes;
 // gmem is the brick's grid in the brick table.
-template <typename T, int AX>
+template <typename T, int AX, bool DISS>
 __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, int la0, int lane, int lb,
                       unsigned &c_lim, unsigned &c_uns, unsigned &c_rie, double &cmax, bool &cbad)
 {
@@ -275,6 +279,8 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
     T pqr1 = T(0), pqr2 = T(0);   // cell k-4's slope and curvature before limiting
     T Lp = T(1);          // Lagrangian length of cell k-4
     T Gp[10];             // slab at face (k-5)+1/2
+    T dvw[4], cw[4][5];   // shock dissipation: divergence and conserved fields of cells k-3..k
+    for (int c = 0; c < 4; ++c) { dvw[c] = T(0); for (int v = 0; v < 5; ++v) cw[c][v] = T(0); }
     for (int v = 0; v < 5; ++v) Fp[v] = T(0);
     for (int v = 0; v < 10; ++v) { pq[v] = T(0); pqp[v] = T(0); Gp[v] = T(0); }
     TLp = St<T>{T(0), T(0), T(0), T(0), T(0)};
@@ -283,7 +289,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
 
     // Inputs of the next cell, loaded one step ahead so that their latency
     // hides behind the current step's arithmetic.
-    T nx_rp, nx_mn, nx_m1, nx_m2, nx_ep, nx_r0, nx_pb;
+    T nx_rp, nx_mn, nx_m1, nx_m2, nx_ep, nx_r0, nx_pb, nx_dv = T(0);
     int nx_s, nx_fl;
     auto load_next = [&](int k) {
         int fl = 1;
@@ -296,6 +302,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
         nx_ep = bld<T>(rin(EN, s), lix);
         nx_r0 = bld<T>(rsrc(a.rho0 + ubase + s * sAX, rcnt), lix);
         nx_pb = bld<T>(rsrc(a.p0 + ubase + s * sAX, rcnt), lix);
+        if constexpr (DISS) nx_dv = bld<T>(rsrc(a.div + ubase + s * sAX, rcnt), lix);
         nx_s = s;
         nx_fl = fl;
     };
@@ -353,6 +360,16 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
 #pragma unroll
             for (int r = 0; r < 4; ++r) sol[r] = sol[r + 1];
             b0[3] = r0; b1[3] = pb; gr[3] = gv; sol[4] = so;
+            if constexpr (DISS) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    dvw[r] = dvw[r + 1];
+#pragma unroll
+                    for (int vv = 0; vv < 5; ++vv) cw[r][vv] = cw[r + 1][vv];
+                }
+                dvw[3] = fresh(nx_dv);
+                cw[3][0] = rp; cw[3][1] = mn; cw[3][2] = m1; cw[3][3] = m2; cw[3][4] = ep;
+            }
         }
         // the inputs of cell k are consumed: their registers take the loads
         // of cell k+1 (past the end this reads a valid ghost source, unused).
@@ -418,6 +435,12 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
         if (S || k >= 1) {
             bool rie = face_flux<T>(TLp, TR, sol[1], sol[2], r0f[0], p0f[0], gam, gfac, nu, F, sg);
             if (rie && (S || (k - 3 >= -1 && k - 3 < n)) && valid) ++c_rie;
+            if constexpr (DISS) {
+                // shock dissipation across a face between fluid cells
+                const T nv = (sol[1] || sol[2]) ? T(0) : a.dissk * tmax(T(0), T(-0.5) * (dvw[0] + dvw[1]));
+#pragma unroll
+                for (int vv = 0; vv < 5; ++vv) F[vv] = F[vv] + nv * (cw[0][vv] - cw[1][vv]);
+            }
         }
         TLp = TL;
         // ---- (6) conservative update of cell k-3 and heating; written now
@@ -523,7 +546,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
 // and z passes, across y for the x pass); a block holds blockDim/64 waves
 // on consecutive rows of the other transverse axis.
 // FP32: at most 256 VGPRs, two waves per SIMD; FP64 needs the full file.
-template <typename T, int AX>
+template <typename T, int AX, bool DISS>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1)
 void sweep_kernel(BatchArgs<T> b)
 {
@@ -541,7 +564,8 @@ void sweep_kernel(BatchArgs<T> b)
     unsigned c_lim = 0, c_uns = 0, c_rie = 0;          // per lane; widened below
     double cmax = 0.0;
     bool cbad = false;
-    if (lb < g.n[cb]) march<T, AX>(g, &B.g, a, la0, (int)(threadIdx.x & 63), lb, c_lim, c_uns, c_rie, cmax, cbad);
+    if (lb < g.n[cb])
+        march<T, AX, DISS>(g, &B.g, a, la0, (int)(threadIdx.x & 63), lb, c_lim, c_uns, c_rie, cmax, cbad);
     if (b.cfl) cfl_commit(b.work, m.brick, cmax, cbad);
     // event counters: one atomic per wave and counter
     unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
@@ -621,11 +645,12 @@ struct XIn {
     T cu[5];
     T pq[10];
     T r0, pb;
+    T dv;             // divergence (shock dissipation only)
     int s, fl;
 };
 
-template <typename T>
-__device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, long nc, long row,
+template <typename T, bool DISS>
+__device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, const T *div, long nc, long row,
                                        int nx, int bc, int i, XIn<T> &o)
 {
     using AI = AxisInfo<0>;
@@ -645,6 +670,7 @@ __device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, 
     for (int v = 0; v < 10; ++v) o.pq[v] = bld<T>(fld(AI::ppb(v)), s);
     o.r0 = bld<T>(rsrc(rho0 + row, nx), s);
     o.pb = bld<T>(rsrc(p0 + row, nx), s);
+    if constexpr (DISS) o.dv = bld<T>(rsrc(div + row, nx), s);
 }
 
 // One wave walks whole x-rows, 56-cell segment by segment, at least
@@ -652,7 +678,7 @@ __device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, 
 // so that each wave has enough work; the loads of the next segment (of the
 // same or the next row) are issued before the current one is computed, so
 // their latency hides behind the arithmetic.
-template <typename T>
+template <typename T, bool DISS>
 __global__ __launch_bounds__(256)
 void sweep_x_kernel(BatchArgs<T> b)
 {
@@ -687,7 +713,7 @@ void sweep_x_kernel(BatchArgs<T> b)
     auto item_i0 = [&](int it) { return (it % nseg) * kXOut - NG; };
 
     XIn<T> cur;
-    x_load(a.in, a.rho0, a.p0, nc, item_row(it0), nx, bc, item_i0(it0) + lane, cur);
+    x_load<T, DISS>(a.in, a.rho0, a.p0, a.div, nc, item_row(it0), nx, bc, item_i0(it0) + lane, cur);
     // settle the first loads, so that the loop's waits count only the
     // memory operations of the loop itself
     __builtin_amdgcn_s_waitcnt(0);
@@ -715,10 +741,12 @@ void sweep_x_kernel(BatchArgs<T> b)
 #pragma unroll
         for (int v = 0; v < 10; ++v) pq[v] = AI::odd(v) ? fl * cur.pq[v] : fresh(cur.pq[v]);
         const T r0 = fresh(cur.r0), pb = fresh(cur.pb);
+        T dv = T(0);
+        if constexpr (DISS) dv = fresh(cur.dv);
         __builtin_amdgcn_sched_barrier(0);
         {
             const int nit = it + 1 < it1 ? it + 1 : it;       // past the run: reload, unused
-            x_load(a.in, a.rho0, a.p0, nc, item_row(nit), nx, bc, item_i0(nit) + lane, cur);
+            x_load<T, DISS>(a.in, a.rho0, a.p0, a.div, nc, item_row(nit), nx, bc, item_i0(nit) + lane, cur);
         }
         const T xd = ox + (T(s) + T(0.5)) * dxT;
         const T gv = fl * gravity_now<T>(&B.g, 0, xd, rtt + xd * xd);
@@ -781,6 +809,16 @@ void sweep_x_kernel(BatchArgs<T> b)
             bool cnt = face_flux(TL, Rs, so, sb, r0f, p0f, gam, gfac, nu, F, sg);
             bool own_face = (own && i >= 0) || (seg == 0 && lane == NG - 1);
             if (cnt && own_face) ++c_rie;
+            if constexpr (DISS) {
+                // shock dissipation across a face between fluid cells; the
+                // neighbour's divergence is read on every lane (a DPP read
+                // from a lane masked off by a branch returns the reader's own
+                // value), then the wall faces are zeroed
+                const T dvr = from_right(dv);
+                const T nv = (so || sb) ? T(0) : a.dissk * tmax(T(0), T(-0.5) * (dv + dvr));
+#pragma unroll
+                for (int vv = 0; vv < 5; ++vv) F[vv] = F[vv] + nv * (cu[vv] - from_right(cu[vv]));
+            }
         }
         T Fl[5];
 #pragma unroll
@@ -898,19 +936,31 @@ template <typename T>
 hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, const BlockMap *map,
                         int nblocks, const T *in, T *out, const T *base, const double *dt,
                         unsigned long long *counters, int heat, const double *base64,
-                        unsigned long long *work, const unsigned long long *cband, int cfl, hipStream_t st)
+                        unsigned long long *work, const unsigned long long *cband, const T *div, double dissk,
+                        int cfl, hipStream_t st)
 {
     if (nblocks <= 0) return hipErrorInvalidValue;
-    BatchArgs<T> a{bricks, map, in, out, base, dt, counters, base64, work, cband, heat, cfl};
+    const bool diss = dissk > 0.0 && div;
+    BatchArgs<T> a{bricks, map, in, out, base, dt, counters, base64, work, cband, diss ? div : nullptr,
+                   dissk, heat, cfl};
     if (axis == 0 && x_lanes_enabled()) {
-        hipLaunchKernelGGL((sweep_x_kernel<T>), dim3(nblocks), dim3(64 * sh.x_waves), 0, st, a);
+        if (diss) hipLaunchKernelGGL((sweep_x_kernel<T, true>), dim3(nblocks), dim3(64 * sh.x_waves), 0, st, a);
+        else hipLaunchKernelGGL((sweep_x_kernel<T, false>), dim3(nblocks), dim3(64 * sh.x_waves), 0, st, a);
         return hipGetLastError();
     }
     dim3 grid(nblocks), block(64 * sh.march_waves);
-    switch (axis) {
-    case 0: hipLaunchKernelGGL((sweep_kernel<T, 0>), grid, block, 0, st, a); break;
-    case 1: hipLaunchKernelGGL((sweep_kernel<T, 1>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((sweep_kernel<T, 2>), grid, block, 0, st, a); break;
+    if (diss) {
+        switch (axis) {
+        case 0: hipLaunchKernelGGL((sweep_kernel<T, 0, true>), grid, block, 0, st, a); break;
+        case 1: hipLaunchKernelGGL((sweep_kernel<T, 1, true>), grid, block, 0, st, a); break;
+        default: hipLaunchKernelGGL((sweep_kernel<T, 2, true>), grid, block, 0, st, a); break;
+        }
+    } else {
+        switch (axis) {
+        case 0: hipLaunchKernelGGL((sweep_kernel<T, 0, false>), grid, block, 0, st, a); break;
+        case 1: hipLaunchKernelGGL((sweep_kernel<T, 1, false>), grid, block, 0, st, a); break;
+        default: hipLaunchKernelGGL((sweep_kernel<T, 2, false>), grid, block, 0, st, a); break;
+        }
     }
     return hipGetLastError();
 }
@@ -918,10 +968,10 @@ hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, cons
 template hipError_t launch_sweep<float>(int, const PassShape &, const Brick *, const BlockMap *, int,
                                         const float *, float *, const float *, const double *,
                                         unsigned long long *, int, const double *, unsigned long long *,
-                                        const unsigned long long *, int, hipStream_t);
+                                        const unsigned long long *, const float *, double, int, hipStream_t);
 template hipError_t launch_sweep<double>(int, const PassShape &, const Brick *, const BlockMap *, int,
                                          const double *, double *, const double *, const double *,
                                          unsigned long long *, int, const double *, unsigned long long *,
-                                         const unsigned long long *, int, hipStream_t);
+                                         const unsigned long long *, const double *, double, int, hipStream_t);
 
 }  // namespace ppmb

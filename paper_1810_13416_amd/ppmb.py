@@ -31,7 +31,8 @@ EXPORTS = ("ppmb_create", "ppmb_destroy", "ppmb_state_bytes", "ppmb_state_layout
            "ppmb_brick_totals", "ppmb_brick_last_dt", "ppmb_batch_step", "ppmb_set_pass_shape",
            "ppmb_get_pass_shape", "ppmb_autotune", "ppmb_ppb2d_create", "ppmb_ppb2d_destroy",
            "ppmb_ppb2d_set", "ppmb_ppb2d_get", "ppmb_ppb2d_steps", "ppmb_ppb2d_get_nstep",
-           "ppmb_ppb2d_set_nstep", "ppmb_set_spinup", "ppmb_spin_add", "ppmb_shell_profile")
+           "ppmb_ppb2d_set_nstep", "ppmb_set_spinup", "ppmb_spin_add", "ppmb_shell_profile",
+           "ppmb_set_shock_dissipation")
 
 
 class PPMBError(RuntimeError):
@@ -115,6 +116,7 @@ def load():
         "ppmb_set_spinup": [p, d, ctypes.c_long],
         "ppmb_spin_add": [p, d],
         "ppmb_shell_profile": [p, i, i, d, _D],
+        "ppmb_set_shock_dissipation": [p, d],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -283,6 +285,10 @@ class Sim:
         self._check(self.L.ppmb_counters(self.h, out))
         return [int(v) for v in out]
 
+    def set_shock_dissipation(self, k: float):
+        """Dissipation coefficient of the 3-D shock dissipation (0: off)."""
+        self._check(self.L.ppmb_set_shock_dissipation(self.h, float(k)))
+
     def set_spinup(self, omega: float, nramp: int):
         """Steps 0 .. nramp-1 each end with a solid-body rotation increment
         omega / nramp about the z axis."""
@@ -409,6 +415,10 @@ class Batch:
         out = (ctypes.c_ulonglong * 4)()
         self._check(self.L.ppmb_counters(self.h, out))
         return [int(v) for v in out]
+
+    def set_shock_dissipation(self, k: float):
+        """Dissipation coefficient of the 3-D shock dissipation (0: off)."""
+        self._check(self.L.ppmb_set_shock_dissipation(self.h, float(k)))
 
     def set_spinup(self, omega: float, nramp: int):
         """Steps 0 .. nramp-1 each end with a solid-body rotation increment
