@@ -191,6 +191,19 @@ __device__ __forceinline__ double fresh(double v)
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// A value that is the same on every lane, kept in scalar registers.
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // pass-local order of the 10 fv coefficients and which flip at a wall
 __host__ __device__ constexpr int mixed_of(int a, int b) { return FXY + (4 - a - b) % 3; }
 
@@ -217,6 +230,18 @@ struct AxisInfo {
 
 // March one pencil; la / lb index it across the lane and block axes;
 // gmem is the brick's grid in the brick table.
+// Conserved perturbations (rho', m along the pass, the two transverse m,
+// E') of a cell from its primitives q = (rho', u, v, w, p') and density rho.
+template <typename T>
+__device__ __forceinline__ void cons_of(const T *q, T rho, T rgm1, T *u)
+{
+    u[0] = q[0];
+    u[1] = rho * q[1];
+    u[2] = rho * q[2];
+    u[3] = rho * q[3];
+    u[4] = q[4] * rgm1 + T(0.5) * (u[1] * q[1] + u[2] * q[2] + u[3] * q[3]);
+}
+
 template <typename T, int AX, bool DISS>
 __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, int la0, int lane, int lb,
                       unsigned &c_lim, unsigned &c_uns, unsigned &c_rie, double &cmax, bool &cbad)
@@ -246,6 +271,9 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
     // transverse part of |x|^2 and the fluid interval of this pencil
     const T xt1 = T(xt[AI::t1]), xt2 = T(xt[AI::t2]);
     const T rtt = xt1 * xt1 + xt2 * xt2;
+    // z of the pencil for the heating when z is transverse: it is then the
+    // coordinate of the wave's row (lb), the same on every lane
+    const T zt = AX == 2 ? T(0) : wave_uniform(T(xt[2]));
     int flo, fhi;
     fluid_interval(g, AX, xt, flo, fhi);
     const T ox = T(g.origin[AX]), dxT = T(g.dx);
@@ -253,6 +281,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
     const double dt64 = *a.dtp;
     const T dt = T(dt64), nu = T(dt64 / g.dx), hdt = T(0.5 * dt64), rdx = T(1.0 / g.dx);
     const T gam = T(g.gamma), gm1 = T(g.gamma - 1.0), gfac = T(g.gamma / (g.gamma - 1.0));
+    const T rgm1 = T(1.0 / (g.gamma - 1.0));
     const int bc = g.bc[AX];
     const T *in = a.in;
     const long nc = a.fs;
@@ -279,8 +308,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
     T pqr1 = T(0), pqr2 = T(0);   // cell k-4's slope and curvature before limiting
     T Lp = T(1);          // Lagrangian length of cell k-4
     T Gp[10];             // slab at face (k-5)+1/2
-    T dvw[4], cw[4][5];   // shock dissipation: divergence and conserved fields of cells k-3..k
-    for (int c = 0; c < 4; ++c) { dvw[c] = T(0); for (int v = 0; v < 5; ++v) cw[c][v] = T(0); }
+    T dvp = T(0), dvc = T(0);     // shock dissipation: divergence of cells k-3, k-2
     for (int v = 0; v < 5; ++v) Fp[v] = T(0);
     for (int v = 0; v < 10; ++v) { pq[v] = T(0); pqp[v] = T(0); Gp[v] = T(0); }
     TLp = St<T>{T(0), T(0), T(0), T(0), T(0)};
@@ -289,7 +317,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
 
     // Inputs of the next cell, loaded one step ahead so that their latency
     // hides behind the current step's arithmetic.
-    T nx_rp, nx_mn, nx_m1, nx_m2, nx_ep, nx_r0, nx_pb, nx_dv = T(0);
+    T nx_rp, nx_mn, nx_m1, nx_m2, nx_ep, nx_r0, nx_pb;
     int nx_s, nx_fl;
     auto load_next = [&](int k) {
         int fl = 1;
@@ -302,7 +330,6 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
         nx_ep = bld<T>(rin(EN, s), lix);
         nx_r0 = bld<T>(rsrc(a.rho0 + ubase + s * sAX, rcnt), lix);
         nx_pb = bld<T>(rsrc(a.p0 + ubase + s * sAX, rcnt), lix);
-        if constexpr (DISS) nx_dv = bld<T>(rsrc(a.div + ubase + s * sAX, rcnt), lix);
         nx_s = s;
         nx_fl = fl;
     };
@@ -339,6 +366,19 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
         cu3[2] = bld<T>(rin(MX + AI::t1, c3), ld3);
         cu3[3] = bld<T>(rin(MX + AI::t2, c3), ld3);
         cu3[4] = bld<T>(rin(EN, c3), ld3);
+        if constexpr (DISS) {
+            // divergence of cell k-2 for the face (k-3)+1/2 (used from k = 1
+            // on); that of cell k-3 is carried from the previous step
+            int s2 = k - 2;
+            unsigned l2 = lix;
+            if (!S) {
+                int f2;
+                if (k < 0) { s2 = 0; l2 = kNoIdx; }
+                else if (s2 < 0 || s2 >= n) s2 = bc_source(s2, n, bc, f2);
+            }
+            dvp = dvc;
+            dvc = bld<T>(rsrc(a.div + ubase + s2 * sAX, rcnt), l2);
+        }
         {
             T xd = ox + (T(s) + T(0.5)) * dxT;
             T gv = flT * gravity_now<T>(gmem, AX, xd, rtt + xd * xd);
@@ -360,16 +400,6 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
 #pragma unroll
             for (int r = 0; r < 4; ++r) sol[r] = sol[r + 1];
             b0[3] = r0; b1[3] = pb; gr[3] = gv; sol[4] = so;
-            if constexpr (DISS) {
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    dvw[r] = dvw[r + 1];
-#pragma unroll
-                    for (int vv = 0; vv < 5; ++vv) cw[r][vv] = cw[r + 1][vv];
-                }
-                dvw[3] = fresh(nx_dv);
-                cw[3][0] = rp; cw[3][1] = mn; cw[3][2] = m1; cw[3][3] = m2; cw[3][4] = ep;
-            }
         }
         // the inputs of cell k are consumed: their registers take the loads
         // of cell k+1 (past the end this reads a valid ghost source, unused).
@@ -436,10 +466,21 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
             bool rie = face_flux<T>(TLp, TR, sol[1], sol[2], r0f[0], p0f[0], gam, gfac, nu, F, sg);
             if (rie && (S || (k - 3 >= -1 && k - 3 < n)) && valid) ++c_rie;
             if constexpr (DISS) {
-                // shock dissipation across a face between fluid cells
-                const T nv = (sol[1] || sol[2]) ? T(0) : a.dissk * tmax(T(0), T(-0.5) * (dvw[0] + dvw[1]));
+                // shock dissipation across a face between fluid cells: the
+                // conserved fields of cell k-3 as loaded for its update (in
+                // the steady steps, where it lies inside the pencil), else,
+                // and for cell k-2, rebuilt from the primitives
+                const T nv = (sol[1] || sol[2]) ? T(0) : a.dissk * tmax(T(0), T(-0.5) * (dvp + dvc));
+                T ua[5], ub[5];
+                if constexpr (S) {
 #pragma unroll
-                for (int vv = 0; vv < 5; ++vv) F[vv] = F[vv] + nv * (cw[0][vv] - cw[1][vv]);
+                    for (int vv = 0; vv < 5; ++vv) ua[vv] = cu3[vv];
+                } else {
+                    cons_of(q[1], b0[0] + q[1][0], rgm1, ua);
+                }
+                cons_of(q[2], rr[0], rgm1, ub);
+#pragma unroll
+                for (int vv = 0; vv < 5; ++vv) F[vv] = F[vv] + nv * (ua[vv] - ub[vv]);
             }
         }
         TLp = TL;
@@ -449,7 +490,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
             hydro_update(cu3, Fp, F, nu, dt, gr[0], hn);
             if (a.heat) {
                 T xd = ox + (T(cu_) + T(0.5)) * dxT;
-                T zc = AX == 2 ? xd : T(xt[2]);
+                T zc = AX == 2 ? xd : zt;
                 hn[4] = hn[4] + heating_now<T>(gmem, zc, rtt + xd * xd) * dt;
             }
 #pragma unroll
