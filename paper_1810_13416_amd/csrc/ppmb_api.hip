@@ -43,6 +43,8 @@ struct ppmb_ctx {
     std::vector<int> pfirst[3];         // first block of each brick (+ total at the end)
     BlockMap *cmap = nullptr;           // CFL reduction
     std::vector<int> cfirst;
+    BlockMap *dmap = nullptr;           // divergence (shock dissipation)
+    std::vector<int> dfirst;
     long nstep = 0;
     unsigned long long steps = 0;
     // work[] holds the CFL maxima of the current state: the last pass of a
@@ -107,6 +109,8 @@ static void free_maps(ppmb_ctx *c)
     for (int d = 0; d < 3; ++d) { hipFree(c->pmap[d]); c->pmap[d] = nullptr; }
     hipFree(c->cmap);
     c->cmap = nullptr;
+    hipFree(c->dmap);
+    c->dmap = nullptr;
 }
 
 static ppmb_status upload_map(ppmb_ctx *c, const std::vector<BlockMap> &m, BlockMap **dst)
@@ -143,7 +147,17 @@ static ppmb_status build_maps(ppmb_ctx *c)
         for (int l = 0; l < n; ++l) m.push_back(BlockMap{ b, l });
     }
     c->cfirst[c->nb] = (int)m.size();
-    return upload_map(c, m, &c->cmap);
+    TRY(upload_map(c, m, &c->cmap));
+    m.clear();
+    c->dfirst.assign(c->nb + 1, 0);
+    for (int b = 0; b < c->nb; ++b) {
+        c->dfirst[b] = (int)m.size();
+        int n = div_blocks(c->hb[b].g);
+        for (int l = 0; l < n; ++l) m.push_back(BlockMap{ b, l });
+    }
+    c->dfirst[c->nb] = (int)m.size();
+    if (m.size() > 0x7fffffff) return fail(c, PPMB_ERR_INVALID, "too many blocks");
+    return upload_map(c, m, &c->dmap);
 }
 
 static ppmb_status check_grid(const ppmb_grid *grid)
@@ -361,12 +375,12 @@ static bool any_heat(ppmb_ctx *c)
 // dissipation on).
 static ppmb_status enqueue_divergence(ppmb_ctx *c, int b0, int b1, int from)
 {
-    const int f0 = c->cfirst[b0], f1 = c->cfirst[b1];
+    const int f0 = c->dfirst[b0], f1 = c->dfirst[b1];
     if (c->prec == PPMB_FP64)
-        HIPCHK(c, launch_divergence<double>(c->db, c->cmap + f0, f1 - f0, arena<double>(c, from), c->base64,
+        HIPCHK(c, launch_divergence<double>(c->db, c->dmap + f0, f1 - f0, arena<double>(c, from), c->base64,
                                             static_cast<double *>(c->divbuf), c->stream));
     else
-        HIPCHK(c, launch_divergence<float>(c->db, c->cmap + f0, f1 - f0, arena<float>(c, from), c->base64,
+        HIPCHK(c, launch_divergence<float>(c->db, c->dmap + f0, f1 - f0, arena<float>(c, from), c->base64,
                                            static_cast<float *>(c->divbuf), c->stream));
     return PPMB_OK;
 }

@@ -482,49 +482,185 @@ hipError_t launch_totals(const Geom &g, const T *state, const double *rho0, cons
 // neighbour as a wall whose normal velocity is minus the cell's own.
 // ---------------------------------------------------------------------
 
-template <typename T>
-__device__ __forceinline__ double vel_at(const Geom &g, const T *S, const double *rho0, long e, int d)
+// One block: a tile of kDivTx x kDivTy cells across x and y, marched along
+// z through kDivTz planes.  Each thread turns its own cell's conserved
+// fields into a velocity once per plane (one FP64 reciprocal); its x and y
+// neighbours read theirs from the plane's LDS copy (double-buffered, one
+// barrier per plane), the z neighbours come from the thread's own column in
+// registers.  The tile's edge cells outside it (x - 1, x + kDivTx, y - 1,
+// y + kDivTy) are computed by waves 0, 1 and 3, each thread for at most one
+// of them.  The loads of the next plane are issued before the current one
+// is finished.
+constexpr int kDivTx = 64, kDivTy = 4, kDivTz = 32;
+
+int div_blocks(const Geom &g)
 {
-    return (double)S[(MX + d) * g.fs + e] / (rho0[e] + (double)S[RHO * g.fs + e]);
+    const long t = (long)((g.n[0] + kDivTx - 1) / kDivTx) * ((g.n[1] + kDivTy - 1) / kDivTy) *
+                   ((g.n[2] + kDivTz - 1) / kDivTz);
+    return (int)t;
+}
+
+// The raw inputs of one cell: rho', the momentum components asked for, and
+// rho0; `ok` false loads nothing (the slot is not used).
+template <typename T>
+struct DivRaw {
+    T rp, m[3];
+    double r0;
+};
+
+template <typename T, int NM>
+__device__ __forceinline__ void div_load(const T *S, long fs, const double *rho0, long e, bool ok, const int *comp,
+                                         DivRaw<T> &r)
+{
+    if (!ok) e = 0;
+    r.rp = S[RHO * fs + e];
+#pragma unroll
+    for (int c = 0; c < NM; ++c) r.m[c] = S[(MX + comp[c]) * fs + e];
+    r.r0 = rho0[e];
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void divergence_kernel(const Brick *bricks, const BlockMap *map,
                                                          const T *arena, const double *base64, T *div)
 {
+    __shared__ double su[2][kDivTy][kDivTx + 2];            // u at (x0 - 1 + i, y0 + j)
+    __shared__ double sv[2][kDivTy + 2][kDivTx];            // v at (x0 + i, y0 - 1 + j)
+    __shared__ unsigned char fu[2][kDivTy][kDivTx + 2];     // solid flags of the same slots
+    __shared__ unsigned char fv[2][kDivTy + 2][kDivTx];
     const BlockMap m = map[blockIdx.x];
     const Brick &B = bricks[m.brick];
     const Geom g = B.g;
-    const long nc = B.ncell;
     const T *S = arena + B.off;
+    const long fs = g.fs;
     const double *rho0 = base64 + B.boff;
     T *D = div + B.boff / 2;
-    const long c0 = (long)m.local * kCflBlockCells;
-    const long c1 = c0 + kCflBlockCells < nc ? c0 + kCflBlockCells : nc;
-    for (long c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
-        const unsigned nx = (unsigned)g.n[0], ny = (unsigned)g.n[1];
-        const unsigned row = (unsigned)c / nx, i = (unsigned)c - row * nx;
-        const unsigned k = row / ny, j = row - k * ny;
-        const int ijk[3] = { (int)i, (int)j, (int)k };
-        const long e = (long)i + (long)j * g.px + (long)k * g.plane;
-        if (g.sphere && solid_at(g, centre(g, 0, i), centre(g, 1, j), centre(g, 2, k))) {
-            D[e] = T(0);
-            continue;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int tx = (nx + kDivTx - 1) / kDivTx, ty = (ny + kDivTy - 1) / kDivTy;
+    const int x0 = (m.local % tx) * kDivTx;
+    const int y0 = ((m.local / tx) % ty) * kDivTy;
+    const int z0 = (m.local / (tx * ty)) * kDivTz;
+    const int z1 = min(z0 + kDivTz, nz);
+    const int lane = threadIdx.x & 63;
+    const int wy = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    auto elem = [&](int i, int j, int k) { return (long)i + (long)j * g.px + (long)k * g.plane; };
+
+    // own slot (x, y): a cell of the tile, or the image cell just past the
+    // brick's high x or y edge (a neighbour of the last cell); its source
+    // through the boundary conditions and the flips of u and v
+    const int x = x0 + lane, y = y0 + wy;
+    const bool own_slot = x <= nx && y <= ny;
+    const bool out = x < nx && y < ny;                     // writes a divergence
+    int flx = 1, fly = 1;
+    const int sx = x < nx ? x : bc_source(x, nx, g.bc[0], flx);
+    const int sy = y < ny ? y : bc_source(y, ny, g.bc[1], fly);
+    const double cx = centre(g, 0, sx), cy = centre(g, 1, sy);
+
+    // edge slot of this thread: wave 0 the row y0 - 1 (v), wave 3 the row
+    // y0 + kDivTy (v), wave 1 lanes 0..3 the column x0 - 1 and lanes 4..7
+    // the column x0 + kDivTx (u)
+    int hx = 0, hy = 0, hc = 0;                            // position, component (0: none)
+    if (wy == 0) { hx = x; hy = y0 - 1; hc = (x < nx) ? 2 : 0; }
+    else if (wy == kDivTy - 1) { hx = x; hy = y0 + kDivTy; hc = (x < nx && hy <= ny) ? 2 : 0; }
+    else if (wy == 1 && lane < 2 * kDivTy) {
+        hy = y0 + (lane & (kDivTy - 1));
+        hx = lane < kDivTy ? x0 - 1 : x0 + kDivTx;
+        hc = (hy < ny && hx <= nx) ? 1 : 0;
+    }
+    int hf = 1;
+    int hsx = hx, hsy = hy;
+    if (hc == 1 && (hx < 0 || hx >= nx)) hsx = bc_source(hx, nx, g.bc[0], hf);
+    if (hc == 2 && (hy < 0 || hy >= ny)) hsy = bc_source(hy, ny, g.bc[1], hf);
+    const double hcx = centre(g, 0, hsx), hcy = centre(g, 1, hsy);
+
+    const int cuvw[3] = { 0, 1, 2 };
+    const int chc[1] = { hc == 2 ? 1 : 0 };
+    DivRaw<T> ro, rh;                                      // loads of the next plane
+    auto load_plane = [&](int k) {
+        int fz;
+        const int sz = (k >= 0 && k < nz) ? k : bc_source(k, nz, g.bc[2], fz);
+        div_load<T, 3>(S, fs, rho0, elem(sx, sy, sz), own_slot, cuvw, ro);
+        div_load<T, 1>(S, fs, rho0, elem(hsx, hsy, sz), hc != 0, chc, rh);
+    };
+    auto solid_plane = [&](int k, double px, double py) {
+        int fz;
+        const int sz = (k >= 0 && k < nz) ? k : bc_source(k, nz, g.bc[2], fz);
+        return g.sphere && solid_at(g, px, py, centre(g, 2, sz));
+    };
+    auto zflip = [&](int k) {
+        int fz = 1;
+        if (k < 0 || k >= nz) bc_source(k, nz, g.bc[2], fz);
+        return (double)fz;
+    };
+
+    // the cell's velocity and solid flag at plane k from the loads `ro`
+    double u = 0.0, v = 0.0, w = 0.0;
+    bool so = false;
+    auto take_own = [&](int k) {
+        const double ir = 1.0 / (ro.r0 + (double)ro.rp);
+        u = (double)flx * ((double)ro.m[0] * ir);
+        v = (double)fly * ((double)ro.m[1] * ir);
+        w = zflip(k) * ((double)ro.m[2] * ir);
+        so = solid_plane(k, cx, cy);
+    };
+    // edge slot at plane k into LDS buffer b
+    auto put = [&](int k, int b) {
+        if (own_slot) {
+            su[b][wy][lane + 1] = u;
+            fu[b][wy][lane + 1] = so;
+            sv[b][wy + 1][lane] = v;
+            fv[b][wy + 1][lane] = so;
         }
-        double sum = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            double un[2];
-            for (int side = 0; side < 2; ++side) {
-                int nb[3] = { ijk[0], ijk[1], ijk[2] };
-                int fl;
-                nb[d] = bc_source(ijk[d] + (side ? 1 : -1), g.n[d], g.bc[d], fl);
-                const bool sol = g.sphere && solid_at(g, centre(g, 0, nb[0]), centre(g, 1, nb[1]), centre(g, 2, nb[2]));
-                const long en = (long)nb[0] + (long)nb[1] * g.px + (long)nb[2] * g.plane;
-                un[side] = sol ? -vel_at(g, S, rho0, e, d) : (double)fl * vel_at(g, S, rho0, en, d);
+        if (hc != 0) {
+            const double hv = (double)hf * ((double)rh.m[0] / (rh.r0 + (double)rh.rp));
+            const bool hs = solid_plane(k, hcx, hcy);
+            if (hc == 2) {
+                const int r = wy == 0 ? 0 : kDivTy + 1;
+                sv[b][r][lane] = hv;
+                fv[b][r][lane] = hs;
+            } else {
+                const int i = lane < kDivTy ? 0 : kDivTx + 1;
+                su[b][hy - y0][i] = hv;
+                fu[b][hy - y0][i] = hs;
             }
-            sum += 0.5 * (un[1] - un[0]);
         }
-        D[e] = T(sum);
+    };
+
+    // plane z0 - 1 (own column, for w), then plane z0
+    load_plane(z0 - 1);
+    take_own(z0 - 1);
+    double wm = w;
+    bool sm = so;
+    load_plane(z0);
+    take_own(z0);
+    put(z0, z0 & 1);
+    double uc = u, vc = v, wc = w;
+    bool sc = so;
+    load_plane(z0 + 1);
+    for (int k = z0; k < z1; ++k) {
+        take_own(k + 1);                                   // plane k + 1 (own column)
+        __syncthreads();
+        if (k + 1 < z1) {
+            put(k + 1, (k + 1) & 1);
+            load_plane(k + 2);
+        }
+        if (out) {
+            const int b = k & 1;
+            double sum = 0.0;
+            if (!sc) {
+                const double ul = fu[b][wy][lane] ? -uc : su[b][wy][lane];
+                const double ur = fu[b][wy][lane + 2] ? -uc : su[b][wy][lane + 2];
+                sum += 0.5 * (ur - ul);
+                const double vl = fv[b][wy][lane] ? -vc : sv[b][wy][lane];
+                const double vr = fv[b][wy + 2][lane] ? -vc : sv[b][wy + 2][lane];
+                sum += 0.5 * (vr - vl);
+                const double wl = sm ? -wc : wm;
+                const double wr = so ? -wc : w;
+                sum += 0.5 * (wr - wl);
+            }
+            D[elem(x, y, k)] = T(sum);
+        }
+        wm = wc; sm = sc;
+        uc = u; vc = v; wc = w; sc = so;
     }
 }
 
@@ -533,7 +669,8 @@ hipError_t launch_divergence(const Brick *bricks, const BlockMap *map, int nbloc
                              const double *base64, T *div, hipStream_t st)
 {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((divergence_kernel<T>), dim3(nblocks), dim3(256), 0, st, bricks, map, state, base64, div);
+    hipLaunchKernelGGL((divergence_kernel<T>), dim3(nblocks), dim3(kDivTx * kDivTy), 0, st, bricks, map, state,
+                       base64, div);
     return hipGetLastError();
 }
 

@@ -56,9 +56,11 @@ hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, cons
                         unsigned long long *work, const unsigned long long *cband, const T *div, double dissk,
                         int cfl, hipStream_t st);
 
-// Undivided velocity divergence of every cell of the bricks the CFL block
-// map covers (FP64 arithmetic, stored in the working precision): field of
-// brick B at div + B.boff / 2, pitched like the state; 0 in solid cells.
+// Undivided velocity divergence of every cell of the bricks whose blocks
+// are map[0 .. nblocks) (div_blocks(g) blocks per brick; FP64 arithmetic,
+// stored in the working precision): field of brick B at div + B.boff / 2,
+// pitched like the state; 0 in solid cells.
+int div_blocks(const Geom &g);
 template <typename T>
 hipError_t launch_divergence(const Brick *bricks, const BlockMap *map, int nblocks, const T *state,
                              const double *base64, T *div, hipStream_t st);

@@ -453,18 +453,20 @@ def sod(n: int = 200) -> Problem:
                    cfl=0.8, nsteps=0, name=f"sod_{n}")
 
 
-def blast(n: int = 24, p_in: float = 10.0, radius: float = 0.2) -> Problem:
-    """Spherical blast in the periodic box [0,1)^3: gas at rest, rho = 1,
-    p = p_in inside r < radius about the centre and 1 outside (cell-centre
-    values), gamma = 1.4; fv marks the hot gas.  A strong outgoing shock."""
-    P = GridParams(n=(n, n, n), dx=1.0 / n, bc=(BC_PERIODIC,) * 3, gamma=1.4)
+def blast(n=24, p_in: float = 10.0, radius: float = 0.2, bc=None, centre=(0.5, 0.5, 0.5)) -> Problem:
+    """Spherical blast: gas at rest, rho = 1, p = p_in inside r < radius
+    about `centre` and 1 outside (cell-centre values), gamma = 1.4; fv marks
+    the hot gas.  A strong outgoing shock.  n: cells per axis, or (nx, ny,
+    nz) with dx = 1 / nx; bc: per-axis boundary kinds (default periodic)."""
+    nn = (n, n, n) if np.isscalar(n) else tuple(int(v) for v in n)
+    P = GridParams(n=nn, dx=1.0 / nn[0], bc=tuple(bc) if bc else (BC_PERIODIC,) * 3, gamma=1.4)
     z, y, x = _mesh(P)
-    inside = ((x - 0.5) ** 2 + (y - 0.5) ** 2) + (z - 0.5) ** 2 < radius * radius
+    inside = ((x - centre[0]) ** 2 + (y - centre[1]) ** 2) + (z - centre[2]) ** 2 < radius * radius
     p = np.where(inside, p_in, 1.0)
     f = [np.zeros(P.shape) for _ in range(10)]
     f[0][:] = np.where(inside, 1.0, 0.0)
     return Problem(P, [np.ones(P.shape), _zeros(P), _zeros(P), _zeros(P), p] + f,
-                   cfl=0.8, nsteps=10, name=f"blast_{n}")
+                   cfl=0.8, nsteps=10, name=f"blast_{'x'.join(str(v) for v in nn)}")
 
 
 # ---------------------------------------------------------------------

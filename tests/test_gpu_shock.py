@@ -104,6 +104,25 @@ def test_single_dissipative_pass_matches_oracle_fp64(axis, case):
     compare(S.get_conserved(), O.get_conserved())
 
 
+@pytest.mark.parametrize("bc", [(0, 1, 1), (1, 0, 1)])
+def test_dissipation_on_a_ragged_box_matches_oracle_fp64(bc):
+    # a box that takes several x tiles, a partial y tile and two z chunks
+    # of the divergence kernel, with a blast against the reflecting walls
+    prob = pr.blast((70, 9, 33), bc=bc, centre=(0.1, 0.05, 0.3), radius=0.12)
+    S, O = run_pair(prob, 3)
+    compare(S.get_conserved(), O.get_conserved())
+    st = O.get_conserved()
+    dt = O.dt(0.8)
+    for axis in range(3):
+        S.set_conserved(st)
+        Q = oracle.Oracle(prob.params, threads=8)
+        Q.set_conserved(st)
+        Q.set_dissipation(K)
+        Q.pass_(axis, dt)
+        S.pass_(axis, dt)
+        compare(S.get_conserved(), Q.get_conserved())
+
+
 def test_fp32_dissipation_conserves_and_is_deterministic():
     prob = pr.blast(24)
     runs = []
