@@ -45,7 +45,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_traffic_shell512_fp32.txt")
 SQ_SUMMARY = os.path.join(ROOT, "profiles", "sweep_sq_counters_shell512_fp32.md")
-# VALU issue peak without packed FP32 (disabled in this build): 256 CUs x 4
+# VALU issue peak without packed FP32 (disabled in every HIP unit here): 256 CUs x 4
 # SIMDs x 16 lanes per cycle x 2.4 GHz, in 10^12 lane-instructions per second
 VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 # the kernels behind each pass of the FP32 step

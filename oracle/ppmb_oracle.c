@@ -28,8 +28,9 @@
  * shock dissipation is pinned in its divergence (exact on linear fields and
  * at walls) and its effects (idle on uniform states and in rarefactions,
  * conservative, symmetric, smoothing behind a shock that stays in place);
- * the weights of its flux, field by field, are a design of this build with
- * no independent value to pin: parity unpinned for those.
+ * the weights of its flux, field by field, are a design choice (the paper
+ * gives no form for them) with no independent value to pin: parity unpinned
+ * for those.
  */
 #include <math.h>
 #include <stdlib.h>
