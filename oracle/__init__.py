@@ -65,6 +65,8 @@ def lib():
         L.or_spin_add.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.or_set_dissipation.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.or_divergence.argtypes = [ctypes.c_void_p, _D]
+        L.or_set_flattening.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.or_flattening.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
         L.or_set_spinup.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_long]
         L.or_shell_profile.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _D]
         L.or_counters.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_ulonglong)]
@@ -189,6 +191,15 @@ class Oracle:
     def divergence(self):
         out = np.empty(self.params.shape)
         lib().or_divergence(self.h, out.ctypes.data_as(_D))
+        return out
+
+    def set_flattening(self, on: bool):
+        lib().or_set_flattening(self.h, 1 if on else 0)
+
+    def flattening(self, axis: int):
+        """Flattening coefficients of the current state for a pass along axis."""
+        out = np.empty(self.params.shape)
+        lib().or_flattening(self.h, int(axis), out.ctypes.data_as(_D))
         return out
 
     def spin_add(self, domega: float):

@@ -30,7 +30,11 @@
  * conservative, symmetric, smoothing behind a shock that stays in place);
  * the weights of its flux, field by field, are a design choice (the paper
  * gives no form for them) with no independent value to pin: parity unpinned
- * for those.
+ * for those.  The optional flattening near strong shocks is pinned in its
+ * coefficient (zero on smooth and expanding profiles and on weak jumps, one
+ * at a compressive pressure step, mirror symmetric) and its effects (idle
+ * where the coefficient is zero, conservative, symmetric, the Sod shock in
+ * place with less post-shock noise).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -86,6 +90,8 @@ typedef struct {
     long      spin_nramp;  /* ... reached over the steps 0 .. spin_nramp-1 */
     double    diss_k;      /* shock dissipation coefficient (0: off) */
     double   *divu;        /* undivided velocity divergence at the step start */
+    int       flat_on;     /* flattening near strong shocks (CW84 Sec. 4) */
+    double   *flat;        /* its coefficient for the pass in progress */
 } or_sim;
 
 static long cidx(const or_sim *S, int i, int j, int k)
@@ -645,6 +651,8 @@ typedef struct {
     double *rhop, *mn, *mt1, *mt2, *ep, *r0, *p0, *g;   /* gathered, n+2NG */
     double *div;                                        /* divergence (shock dissipation) */
     double diss_k;
+    double *flat;                                       /* flattening coefficient */
+    int flat_on;
     int *solid;
     double *f[10];                                      /* pass-local PPB order */
     /* outputs */
@@ -661,7 +669,7 @@ static void pencil_alloc(pencil *pc, int n)
     int m = n + 2 * NG;
     pc->n = n;
     double **arr[] = { &pc->rhop, &pc->mn, &pc->mt1, &pc->mt2, &pc->ep, &pc->r0, &pc->p0, &pc->g,
-                       &pc->o_rhop, &pc->o_mn, &pc->o_mt1, &pc->o_mt2, &pc->o_ep, &pc->div };
+                       &pc->o_rhop, &pc->o_mn, &pc->o_mt1, &pc->o_mt2, &pc->o_ep, &pc->div, &pc->flat };
     for (unsigned a = 0; a < sizeof(arr) / sizeof(arr[0]); ++a)
         *arr[a] = (double *)calloc(m, sizeof(double));
     for (int q = 0; q < 10; ++q) {
@@ -678,7 +686,7 @@ static void pencil_alloc(pencil *pc, int n)
 static void pencil_free(pencil *pc)
 {
     double *arr[] = { pc->rhop, pc->mn, pc->mt1, pc->mt2, pc->ep, pc->r0, pc->p0, pc->g,
-                      pc->o_rhop, pc->o_mn, pc->o_mt1, pc->o_mt2, pc->o_ep, pc->div };
+                      pc->o_rhop, pc->o_mn, pc->o_mt1, pc->o_mt2, pc->o_ep, pc->div, pc->flat };
     for (unsigned a = 0; a < sizeof(arr) / sizeof(arr[0]); ++a) free(arr[a]);
     for (int q = 0; q < 10; ++q) { free(pc->f[q]); free(pc->o_f[q]); }
     for (int q = 0; q < 40; ++q) free(pc->w[q]);
@@ -735,6 +743,13 @@ static void pencil_update(pencil *pc, double dt, double dx, double gamma, int de
                 if (ws > 0.0) { lc = lc + ws * (l - lc); rc = rc + ws * (r - rc); }
                 l = lc; r = rc;
                 if (J >= NG && J < NG + n) pc->unsmooth++;
+            }
+            if (pc->flat_on) {
+                /* flattening (CW84 Sec. 4) of the final edge values toward
+                   the cell average */
+                const double f = pc->flat[J];
+                l = f * Q[q][J] + (1.0 - f) * l;
+                r = f * Q[q][J] + (1.0 - f) * r;
             }
             qL[q][J] = l; qR[q][J] = r;
         }
@@ -888,10 +903,13 @@ static int bc_map(int j, int n, int bc, double *flip)
     return p - 1 - k;
 }
 
+static void compute_flattening(or_sim *S, int d);
+
 static void do_pass(or_sim *S, int d, double dt)
 {
     const or_params *P = &S->P;
     const int n = P->n[d];
+    if (S->flat_on) compute_flattening(S, d);   /* of this pass's input */
     const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;    /* transverse axes */
     const int na1 = P->n[a1], na2 = P->n[a2];
     int pidx[10];
@@ -908,6 +926,7 @@ static void do_pass(or_sim *S, int d, double dt)
             int t1 = (int)(pe % na1), t2 = (int)(pe / na1);
             pc.unsmooth = pc.nonconv = pc.hits = 0;
             pc.diss_k = S->diss_k;
+            pc.flat_on = S->flat_on;
             for (int j = -NG; j < n + NG; ++j) {
                 int J = j + NG;
                 double fl;
@@ -928,6 +947,7 @@ static void do_pass(or_sim *S, int d, double dt)
                 pc.g[J] = fl * gv[d];
                 pc.solid[J] = solid_at(P, x);
                 pc.div[J] = S->diss_k > 0.0 ? S->divu[ci] : 0.0;
+                pc.flat[J] = S->flat_on ? S->flat[ci] : 0.0;
                 for (int q = 0; q < 10; ++q)
                     pc.f[q][J] = (odd_ppb[q] ? fl : 1.0) * S->U[pidx[q]][ci];
             }
@@ -978,7 +998,7 @@ void or_destroy(void *h)
     or_sim *S = (or_sim *)h;
     if (!S) return;
     for (int q = 0; q < NF; ++q) { free(S->U[q]); free(S->W[q]); }
-    free(S->rho0); free(S->p0); free(S->divu); free(S);
+    free(S->rho0); free(S->p0); free(S->divu); free(S->flat); free(S);
 }
 
 void or_set_threads(void *h, int nthreads) { ((or_sim *)h)->nthreads = nthreads > 0 ? nthreads : 1; }
@@ -1205,6 +1225,72 @@ static void compute_divergence(or_sim *S)
 }
 
 void or_set_dissipation(void *h, double k) { ((or_sim *)h)->diss_k = k > 0.0 ? k : 0.0; }
+
+/* Flattening near strong shocks, after Colella & Woodward (1984, Sec. 4)
+   [reading: the paper names only the 3-D shock dissipation; flattening is
+   CW84's companion device, with their constants].  For the pass along d,
+   with p the full pressure and u the velocity along d (neighbours through
+   the boundary conditions, a reflecting image's u flipped):
+     a cell is a shock candidate when |p(+1) - p(-1)| > eps min(p(+1), p(-1))
+     and u(-1) - u(+1) > 0 (compression);
+     its raw coefficient is min(1, max(0, w2 (z - w1))) with
+     z = (p(+1) - p(-1)) / (p(+2) - p(-2)) (0 where the wide difference is
+     0), and 0 for a cell that is no candidate;
+     its coefficient is the larger of its own raw value and that of its
+     neighbour on the low-pressure side (-1 when p(+1) - p(-1) >= 0). */
+#define FLAT_EPS 0.33
+#define FLAT_W1 0.75
+#define FLAT_W2 10.0
+
+static double cell_pressure(const or_sim *S, long c)
+{
+    double rho = S->rho0[c] + S->U[RHO][c];
+    double mx = S->U[MX][c], my = S->U[MY][c], mz = S->U[MZ][c];
+    double pp = (S->P.gamma - 1.0) * (S->U[EN][c] - 0.5 * (mx * (mx / rho) + my * (my / rho) + mz * (mz / rho)));
+    return S->p0[c] + pp;
+}
+
+static double flat_raw(const double *p, const double *u, int o)
+{
+    /* p, u indexed by offset + 3 */
+    double dp1 = p[o + 4] - p[o + 2], dp2 = p[o + 5] - p[o + 1];
+    int cand = fabs(dp1) > FLAT_EPS * fmin(p[o + 4], p[o + 2]) && u[o + 2] - u[o + 4] > 0.0;
+    if (!cand) return 0.0;
+    double z = dp2 != 0.0 ? dp1 / dp2 : 0.0;
+    return fmin(1.0, fmax(0.0, FLAT_W2 * (z - FLAT_W1)));
+}
+
+static void compute_flattening(or_sim *S, int d)
+{
+    const or_params *P = &S->P;
+    if (!S->flat) S->flat = (double *)calloc(S->ncell, sizeof(double));
+    #pragma omp parallel for num_threads(S->nthreads) schedule(static)
+    for (long c = 0; c < S->ncell; ++c) {
+        int ijk[3] = { (int)(c % P->n[0]), (int)((c / P->n[0]) % P->n[1]), (int)(c / ((long)P->n[0] * P->n[1])) };
+        double p[7], u[7];
+        for (int o = -3; o <= 3; ++o) {
+            int nb[3] = { ijk[0], ijk[1], ijk[2] };
+            double fl;
+            nb[d] = bc_map(ijk[d] + o, P->n[d], P->bc[d], &fl);
+            long e = cidx(S, nb[0], nb[1], nb[2]);
+            p[o + 3] = cell_pressure(S, e);
+            u[o + 3] = fl * cell_velocity(S, e, d);
+        }
+        double f0 = flat_raw(p, u, 0);
+        int side = (p[4] - p[2]) < 0.0 ? 1 : -1;
+        S->flat[c] = fmax(f0, flat_raw(p, u, side));
+    }
+}
+
+void or_set_flattening(void *h, int on) { ((or_sim *)h)->flat_on = on ? 1 : 0; }
+
+/* the flattening coefficients of the current state for a pass along d */
+void or_flattening(void *h, int d, double *out)
+{
+    or_sim *S = (or_sim *)h;
+    compute_flattening(S, d);
+    memcpy(out, S->flat, sizeof(double) * S->ncell);
+}
 
 /* the divergence field of the current state (cells x fastest) */
 void or_divergence(void *h, double *out)
