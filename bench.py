@@ -94,13 +94,15 @@ def run_rotation(sim, n, reps=5):
                               "fluid_volume_over_4pi_3": vol / (4.0 * math.pi / 3.0)}}
 
 
-def run_gpu(prob, precision, steps, warmup, dev_prims, rotation=False, dissk=0.0):
+def run_gpu(prob, precision, steps, warmup, dev_prims, rotation=False, dissk=0.0, flat=False):
     import torch
     from paper_1810_13416_amd import ppmb
     sim = ppmb.Sim(prob.params, precision, device="cuda:0")
     sim.set_state_device(dev_prims)
     if dissk > 0.0:
         sim.set_shock_dissipation(dissk)
+    if flat:
+        sim.set_flattening(True)
     torch.cuda.synchronize()
     sim.step_auto(prob.cfl, warmup)
     torch.cuda.synchronize()
@@ -343,7 +345,7 @@ def main():
     ap.add_argument("--no-rotation", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0)
     ap.add_argument("--dissipation", type=float, default=0.1,
-                    help="coefficient of the extra FP32 run with shock dissipation (0: skip it)")
+                    help="coefficient of the extra FP32 runs with shock handling (0: skip them)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -368,11 +370,15 @@ def main():
     log("FP32 run")
     r32 = run_gpu(prob, ppmb.FP32, args.steps, args.warmup, dev, rotation=not args.no_rotation)
     log(f"FP32: {r32['ms_per_step']:.3f} ms/step, passes {r32['pass_ms']}")
-    rdiss = None
+    rdiss = rflat = None
     if args.dissipation > 0.0:
         log(f"FP32 run with shock dissipation K = {args.dissipation}")
         rdiss = run_gpu(prob, ppmb.FP32, max(5, args.steps // 2), args.warmup, dev, dissk=args.dissipation)
         log(f"FP32 dissipative: {rdiss['ms_per_step']:.3f} ms/step, passes {rdiss['pass_ms']}")
+        log("FP32 run with shock dissipation and flattening")
+        rflat = run_gpu(prob, ppmb.FP32, max(5, args.steps // 2), args.warmup, dev, dissk=args.dissipation,
+                        flat=True)
+        log(f"FP32 dissipation + flattening: {rflat['ms_per_step']:.3f} ms/step, passes {rflat['pass_ms']}")
     r64 = None
     if not args.no_fp64:
         log("FP64 run")
@@ -443,6 +449,11 @@ def main():
                                     "unit": "cell-updates/s", "ms_per_step": rdiss["ms_per_step"],
                                     "pass_ms": rdiss["pass_ms"],
                                     "slowdown_vs_plain": rdiss["ms_per_step"] / r32["ms_per_step"]}
+    if rflat:
+        out["shock_dissipation_and_flattening"] = {
+            "k": args.dissipation, "value": cells / (rflat["ms_per_step"] * 1e-3), "unit": "cell-updates/s",
+            "ms_per_step": rflat["ms_per_step"], "pass_ms": rflat["pass_ms"],
+            "slowdown_vs_plain": rflat["ms_per_step"] / r32["ms_per_step"]}
     if r64:
         out["fp64"] = {"value": cells / (r64["ms_per_step"] * 1e-3), "unit": "cell-updates/s",
                        "ms_per_step": r64["ms_per_step"], "pass_ms": r64["pass_ms"],

@@ -223,6 +223,29 @@ ppmb_status ppmb_reduce_totals(ppmb_ctx *ctx, double out[8]);
  * NOMEM if the field cannot be allocated. */
 ppmb_status ppmb_set_shock_dissipation(ppmb_ctx *ctx, double k);
 
+/* Flattening near strong shocks (Colella & Woodward 1984, Sec. 4), the
+ * customary companion of the shock dissipation; the paper does not name it,
+ * so this is a reading with CW84's constants.  Before each pass, for every
+ * cell and the pass axis d, from the full pressure p (base plus
+ * perturbation) and the velocity u along d of the pass's input (neighbours
+ * through the boundary conditions, a reflecting image's u flipped), FP64:
+ * a cell is a shock candidate when |p(i+1) - p(i-1)| > 0.33 min(p(i+1),
+ * p(i-1)) and u(i-1) - u(i+1) > 1e-10 (|u(i-1)| + |u(i+1)|); its raw
+ * coefficient is then min(1, max(0, 10 (z - 0.75))) with z = (p(i+1) -
+ * p(i-1)) / (p(i+2) - p(i-2)) (0 when that difference is 0), else 0; its
+ * coefficient f is the larger of its own raw value and that of its
+ * neighbour on the low-pressure side (i+1 when p(i+1) < p(i-1), i-1 when
+ * p(i+1) > p(i-1), both when |p(i+1) - p(i-1)| <= 1e-10 (p(i+1) + p(i-1))).
+ * The 1e-10 margins keep the decisions off values equal but for rounding;
+ * CW84's tests are strict.  Each parabola's final edge values (after the
+ * constraints) become f q + (1 - f) edge, q the cell average, for all five
+ * interpolated variables.  on = 0 (the default) switches it off and the
+ * passes run exactly as without it.  The library allocates one field of the
+ * working precision per brick on the first call with on != 0.  Host-side
+ * setting; drops a captured step graph.  INVALID for a null context; NOMEM
+ * if the field cannot be allocated. */
+ppmb_status ppmb_set_flattening(ppmb_ctx *ctx, int on);
+
 /* ---- rotation and spherical averages (Sec. 1, Sec. 3) ------------------
  *
  * Spin-up (Sec. 3: a solid-body rotation is added to the flow gradually

@@ -1232,15 +1232,23 @@ void or_set_dissipation(void *h, double k) { ((or_sim *)h)->diss_k = k > 0.0 ? k
    with p the full pressure and u the velocity along d (neighbours through
    the boundary conditions, a reflecting image's u flipped):
      a cell is a shock candidate when |p(+1) - p(-1)| > eps min(p(+1), p(-1))
-     and u(-1) - u(+1) > 0 (compression);
+     and the flow converges, u(-1) - u(+1) > tie (|u(-1)| + |u(+1)|);
      its raw coefficient is min(1, max(0, w2 (z - w1))) with
      z = (p(+1) - p(-1)) / (p(+2) - p(-2)) (0 where the wide difference is
      0), and 0 for a cell that is no candidate;
      its coefficient is the larger of its own raw value and that of its
-     neighbour on the low-pressure side (-1 when p(+1) - p(-1) >= 0). */
+     neighbour on the low-pressure side (+1 when p(+1) < p(-1), else -1),
+     or of both neighbours when |p(+1) - p(-1)| <= tie (p(+1) + p(-1)).
+   The two tie margins [reading: CW84's tests are strict] keep decisions
+   off values that are equal but for rounding (a uniform transverse flow
+   after a pass gives neighbours the same velocity to the last bit or two),
+   where a strict test would switch the flattening on or off at random; a
+   real shock lies orders of magnitude above them.  The symmetric tie rule
+   also keeps the coefficient mirror symmetric. */
 #define FLAT_EPS 0.33
 #define FLAT_W1 0.75
 #define FLAT_W2 10.0
+#define FLAT_TIE 1e-10
 
 static double cell_pressure(const or_sim *S, long c)
 {
@@ -1254,7 +1262,8 @@ static double flat_raw(const double *p, const double *u, int o)
 {
     /* p, u indexed by offset + 3 */
     double dp1 = p[o + 4] - p[o + 2], dp2 = p[o + 5] - p[o + 1];
-    int cand = fabs(dp1) > FLAT_EPS * fmin(p[o + 4], p[o + 2]) && u[o + 2] - u[o + 4] > 0.0;
+    int cand = fabs(dp1) > FLAT_EPS * fmin(p[o + 4], p[o + 2]) &&
+               u[o + 2] - u[o + 4] > FLAT_TIE * (fabs(u[o + 2]) + fabs(u[o + 4]));
     if (!cand) return 0.0;
     double z = dp2 != 0.0 ? dp1 / dp2 : 0.0;
     return fmin(1.0, fmax(0.0, FLAT_W2 * (z - FLAT_W1)));
@@ -1276,9 +1285,12 @@ static void compute_flattening(or_sim *S, int d)
             p[o + 3] = cell_pressure(S, e);
             u[o + 3] = fl * cell_velocity(S, e, d);
         }
-        double f0 = flat_raw(p, u, 0);
-        int side = (p[4] - p[2]) < 0.0 ? 1 : -1;
-        S->flat[c] = fmax(f0, flat_raw(p, u, side));
+        double f0 = flat_raw(p, u, 0), fm = flat_raw(p, u, -1), fp = flat_raw(p, u, 1);
+        double dp = p[4] - p[2];
+        double nb;
+        if (fabs(dp) <= FLAT_TIE * (p[4] + p[2])) nb = fmax(fm, fp);
+        else nb = dp < 0.0 ? fp : fm;
+        S->flat[c] = fmax(f0, nb);
     }
 }
 

@@ -45,6 +45,8 @@ struct ppmb_ctx {
     std::vector<int> cfirst;
     BlockMap *dmap = nullptr;           // divergence (shock dissipation)
     std::vector<int> dfirst;
+    BlockMap *fmap[3] = { nullptr, nullptr, nullptr };   // flattening, per pass axis
+    std::vector<int> ffirst[3];
     long nstep = 0;
     unsigned long long steps = 0;
     // work[] holds the CFL maxima of the current state: the last pass of a
@@ -65,6 +67,8 @@ struct ppmb_ctx {
     size_t shell_ws_bytes = 0;
     double dissk = 0.0;                 // shock dissipation coefficient (0: off)
     void *divbuf = nullptr;             // its divergence field (one field per brick)
+    bool flat_on = false;               // flattening near strong shocks
+    void *flatbuf = nullptr;            // its coefficients for the pass in progress
     std::string err;
 };
 
@@ -111,6 +115,7 @@ static void free_maps(ppmb_ctx *c)
     c->cmap = nullptr;
     hipFree(c->dmap);
     c->dmap = nullptr;
+    for (int d = 0; d < 3; ++d) { hipFree(c->fmap[d]); c->fmap[d] = nullptr; }
 }
 
 static ppmb_status upload_map(ppmb_ctx *c, const std::vector<BlockMap> &m, BlockMap **dst)
@@ -157,7 +162,20 @@ static ppmb_status build_maps(ppmb_ctx *c)
     }
     c->dfirst[c->nb] = (int)m.size();
     if (m.size() > 0x7fffffff) return fail(c, PPMB_ERR_INVALID, "too many blocks");
-    return upload_map(c, m, &c->dmap);
+    TRY(upload_map(c, m, &c->dmap));
+    for (int d = 0; d < 3; ++d) {
+        m.clear();
+        c->ffirst[d].assign(c->nb + 1, 0);
+        for (int b = 0; b < c->nb; ++b) {
+            c->ffirst[d][b] = (int)m.size();
+            int n = flat_blocks(c->hb[b].g, d);
+            for (int l = 0; l < n; ++l) m.push_back(BlockMap{ b, l });
+        }
+        c->ffirst[d][c->nb] = (int)m.size();
+        if (m.size() > 0x7fffffff) return fail(c, PPMB_ERR_INVALID, "too many blocks");
+        TRY(upload_map(c, m, &c->fmap[d]));
+    }
+    return PPMB_OK;
 }
 
 static ppmb_status check_grid(const ppmb_grid *grid)
@@ -338,6 +356,16 @@ static ppmb_status enqueue_cfl(ppmb_ctx *c, double cfl, int b0, int b1)
 // `cfl` it also reduces the signal speeds of its output into work[].
 static ppmb_status enqueue_pass(ppmb_ctx *c, int axis, int heat, int b0, int b1, int from, int cfl = 0)
 {
+    if (c->flat_on) {
+        // flattening coefficients of this pass's input along its axis
+        const int g0 = c->ffirst[axis][b0], g1 = c->ffirst[axis][b1];
+        if (c->prec == PPMB_FP64)
+            HIPCHK(c, launch_flattening<double>(axis, c->db, c->fmap[axis] + g0, g1 - g0, arena<double>(c, from),
+                                                c->base64, static_cast<double *>(c->flatbuf), c->stream));
+        else
+            HIPCHK(c, launch_flattening<float>(axis, c->db, c->fmap[axis] + g0, g1 - g0, arena<float>(c, from),
+                                               c->base64, static_cast<float *>(c->flatbuf), c->stream));
+    }
     const int f0 = c->pfirst[axis][b0], f1 = c->pfirst[axis][b1];
     ppmb_ctx::Timed tm{ nullptr, nullptr, axis };
     if (c->profiling) {
@@ -349,13 +377,14 @@ static ppmb_status enqueue_pass(ppmb_ctx *c, int axis, int heat, int b0, int b1,
     if (c->prec == PPMB_FP64)
         e = launch_sweep<double>(axis, c->shape, c->db, c->pmap[axis] + f0, f1 - f0, arena<double>(c, from),
                                  arena<double>(c, 1 - from), c->base64, c->dt, c->cnt, heat, c->base64,
-                                 c->work, c->cband, static_cast<const double *>(c->divbuf), c->dissk, cfl,
-                                 c->stream);
+                                 c->work, c->cband, static_cast<const double *>(c->divbuf), c->dissk,
+                                 c->flat_on ? static_cast<const double *>(c->flatbuf) : nullptr, cfl, c->stream);
     else
         e = launch_sweep<float>(axis, c->shape, c->db, c->pmap[axis] + f0, f1 - f0, arena<float>(c, from),
                                 arena<float>(c, 1 - from), static_cast<const float *>(c->baseT), c->dt,
                                 c->cnt, heat, c->base64, c->work, c->cband, static_cast<const float *>(c->divbuf),
-                                c->dissk, cfl, c->stream);
+                                c->dissk, c->flat_on ? static_cast<const float *>(c->flatbuf) : nullptr, cfl,
+                                c->stream);
     if (e != hipSuccess) return hipfail(c, e, "sweep launch");
     if (c->profiling) {
         HIPCHK(c, hipEventRecord(tm.b, c->stream));
@@ -523,6 +552,7 @@ ppmb_status ppmb_destroy(ppmb_ctx *c)
     hipFree(c->out8);
     hipFree(c->shell_ws);
     hipFree(c->divbuf);
+    hipFree(c->flatbuf);
     delete c;
     return PPMB_OK;
 }
@@ -929,6 +959,21 @@ ppmb_status ppmb_set_shock_dissipation(ppmb_ctx *c, double k)
         }
     }
     c->dissk = k;
+    free_graph(c);                       // captured steps hold the previous setting
+    return PPMB_OK;
+}
+
+ppmb_status ppmb_set_flattening(ppmb_ctx *c, int on)
+{
+    if (!c) return PPMB_ERR_INVALID;
+    if (on && !c->flatbuf) {
+        const size_t bytes = (size_t)(c->total_base / 2) * c->esz;
+        if (hipMalloc(&c->flatbuf, bytes) != hipSuccess) {
+            c->flatbuf = nullptr;
+            return fail(c, PPMB_ERR_NOMEM, "flattening field");
+        }
+    }
+    c->flat_on = on != 0;
     free_graph(c);                       // captured steps hold the previous setting
     return PPMB_OK;
 }

@@ -674,6 +674,177 @@ hipError_t launch_divergence(const Brick *bricks, const BlockMap *map, int nbloc
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------
+// Flattening near strong shocks (Colella & Woodward 1984, Sec. 4), the
+// companion of the shock dissipation: per cell and pass axis d, from the
+// full pressure p over three cells each side and the velocity u along d
+// over two, neighbours through the boundary conditions (a reflecting
+// image's u flipped):
+//   raw(i) = 0 unless |p(i+1) - p(i-1)| > eps min(p(i+1), p(i-1)) and
+//            u(i-1) - u(i+1) > tie (|u(i-1)| + |u(i+1)|); else
+//            min(1, max(0, w2 (z - w1))),
+//            z = (p(i+1) - p(i-1)) / (p(i+2) - p(i-2)) (0 if that is 0);
+//   f(i)   = max(raw(i), raw(i + 1)) if p(i+1) < p(i-1), max(raw(i),
+//            raw(i - 1)) if p(i+1) > p(i-1), max of all three when
+//            |p(i+1) - p(i-1)| <= tie (p(i+1) + p(i-1)).
+// The tie margins keep the decisions off values that are equal but for
+// rounding.  FP64 arithmetic, stored in the working precision.
+// ---------------------------------------------------------------------
+
+constexpr double kFlatEps = 0.33, kFlatW1 = 0.75, kFlatW2 = 10.0, kFlatTie = 1e-10;
+constexpr int kFlatChunk = 64;     // cells along the pass per thread (march form)
+constexpr int kFlatXOut = 58;      // outputs per 64-lane row segment (x form)
+
+// the coefficient from the raw values of the cell and its two neighbours
+__device__ __forceinline__ double flat_pick(double pm1, double pp1, double rm, double r0, double rp)
+{
+    const double dp = pp1 - pm1;
+    double nb;
+    if (fabs(dp) <= kFlatTie * (pp1 + pm1)) nb = fmax(rm, rp);
+    else nb = dp < 0.0 ? rp : rm;
+    return fmax(r0, nb);
+}
+
+__device__ __forceinline__ double flat_raw(double pm2, double pm1, double pp1, double pp2, double um1, double up1)
+{
+    const double dp1 = pp1 - pm1, dp2 = pp2 - pm2;
+    const bool cand = fabs(dp1) > kFlatEps * fmin(pp1, pm1) && um1 - up1 > kFlatTie * (fabs(um1) + fabs(up1));
+    if (!cand) return 0.0;
+    const double z = dp2 != 0.0 ? dp1 / dp2 : 0.0;
+    return fmin(1.0, fmax(0.0, kFlatW2 * (z - kFlatW1)));
+}
+
+// Full pressure and the velocity along d of element e (flip fl on u), each
+// velocity a correctly rounded quotient m / rho: the compression test
+// compares two velocities that are often equal but for rounding (a uniform
+// transverse flow after a pass), so FP64 runs take exactly the decisions of
+// any other evaluation of these formulas in the same order.
+template <typename T>
+__device__ __forceinline__ void flat_cell(const Geom &g, const T *S, long fs, const double *r64, const double *p64,
+                                          long e, int d, double fl, double &p, double &u)
+{
+    const double rho = r64[e] + (double)S[RHO * fs + e];
+    const double mx = (double)S[MX * fs + e], my = (double)S[MY * fs + e], mz = (double)S[MZ * fs + e];
+    const double vx = mx / rho, vy = my / rho, vz = mz / rho;
+    p = p64[e] + (g.gamma - 1.0) * ((double)S[EN * fs + e] - 0.5 * (mx * vx + my * vy + mz * vz));
+    u = fl * (d == 0 ? vx : (d == 1 ? vy : vz));
+}
+
+int flat_blocks(const Geom &g, int axis)
+{
+    if (axis == 0) {
+        const long items = (long)g.n[1] * g.n[2] * ((g.n[0] + kFlatXOut - 1) / kFlatXOut);
+        return (int)((items + 3) / 4);
+    }
+    const int cb = 3 - axis;                     // the transverse axis other than x
+    return ((g.n[0] + 63) / 64) * ((g.n[cb] + 3) / 4) * ((g.n[axis] + kFlatChunk - 1) / kFlatChunk);
+}
+
+// y and z passes: each thread marches a chunk of one pencil (lanes across
+// x), windows of p (5 cells), u (4) and the raw coefficient (3).
+template <typename T, int D>
+__global__ __launch_bounds__(256) void flat_march_kernel(const Brick *bricks, const BlockMap *map, const T *arena,
+                                                         const double *base64, T *flat)
+{
+    constexpr int CB = 3 - D;
+    const BlockMap m = map[blockIdx.x];
+    const Brick &B = bricks[m.brick];
+    const Geom g = B.g;
+    const T *S = arena + B.off;
+    const long fs = g.fs;
+    const double *r64 = base64 + B.boff, *p64 = base64 + B.boff + fs;
+    T *F = flat + B.boff / 2;
+    const int n = g.n[D], nx = g.n[0], ncb = g.n[CB];
+    const int tx = (nx + 63) / 64, tb = (ncb + 3) / 4;
+    const int x = (m.local % tx) * 64 + (int)(threadIdx.x & 63);
+    const int b = ((m.local / tx) % tb) * 4 + (int)(threadIdx.x >> 6);
+    const int c0 = (m.local / (tx * tb)) * kFlatChunk;
+    if (x >= nx || b >= ncb) return;
+    const int c1 = min(c0 + kFlatChunk, n);
+    const long sd = D == 1 ? g.px : g.plane, sb = CB == 1 ? g.px : g.plane;
+    const long base = (long)x + (long)b * sb;
+    double P[5] = { 0.0, 0.0, 0.0, 0.0, 0.0 }, U[4] = { 0.0, 0.0, 0.0, 0.0 }, R[3] = { 0.0, 0.0, 0.0 };
+    for (int t = c0 - 3; t <= c1 + 2; ++t) {
+        int fl = 1;
+        const int s = (t >= 0 && t < n) ? t : bc_source(t, n, g.bc[D], fl);
+        double pt, ut;
+        flat_cell<T>(g, S, fs, r64, p64, base + (long)s * sd, D, (double)fl, pt, ut);
+        P[0] = P[1]; P[1] = P[2]; P[2] = P[3]; P[3] = P[4]; P[4] = pt;
+        U[0] = U[1]; U[1] = U[2]; U[2] = U[3]; U[3] = ut;
+        if (t >= c0 + 1) {                       // raw coefficient of cell t - 2
+            R[0] = R[1]; R[1] = R[2];
+            R[2] = flat_raw(P[0], P[1], P[3], P[4], U[0], U[2]);
+        }
+        if (t >= c0 + 3)                         // coefficient of cell t - 3
+            F[base + (long)(t - 3) * sd] = T(flat_pick(P[0], P[2], R[0], R[1], R[2]));
+    }
+}
+
+template <int CTRL>
+__device__ __forceinline__ double aux_dpp(double v)
+{
+    const unsigned long long bits = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)bits, (int)(unsigned)bits, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(bits >> 32), (int)(unsigned)(bits >> 32), CTRL, 0xf,
+                                               0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double left_of(double v) { return aux_dpp<0x138>(v); }    // lane - 1
+__device__ __forceinline__ double right_of(double v) { return aux_dpp<0x130>(v); }   // lane + 1
+
+// x pass: one wave per 64-cell row segment (3 cells of halo each side),
+// neighbours by DPP shifts taken on every lane.
+template <typename T>
+__global__ __launch_bounds__(256) void flat_x_kernel(const Brick *bricks, const BlockMap *map, const T *arena,
+                                                     const double *base64, T *flat)
+{
+    const BlockMap m = map[blockIdx.x];
+    const Brick &B = bricks[m.brick];
+    const Geom g = B.g;
+    const T *S = arena + B.off;
+    const long fs = g.fs;
+    const double *r64 = base64 + B.boff, *p64 = base64 + B.boff + fs;
+    T *F = flat + B.boff / 2;
+    const int nx = g.n[0];
+    const int nseg = (nx + kFlatXOut - 1) / kFlatXOut;
+    const long items = (long)g.n[1] * g.n[2] * nseg;
+    const long item = (long)m.local * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (item >= items) return;                   // whole waves only
+    const int lane = threadIdx.x & 63;
+    const long rowi = item / nseg;
+    const int seg = (int)(item - rowi * nseg);
+    const int y = (int)(rowi % g.n[1]), z = (int)(rowi / g.n[1]);
+    const long row = (long)y * g.px + (long)z * g.plane;
+    const int i = seg * kFlatXOut - 3 + lane;
+    int fl = 1;
+    const int s = (i >= 0 && i < nx) ? i : bc_source(i, nx, g.bc[0], fl);
+    double p, u;
+    flat_cell<T>(g, S, fs, r64, p64, row + s, 0, (double)fl, p, u);
+    const double pm1 = left_of(p), pp1 = right_of(p);
+    const double pm2 = left_of(pm1), pp2 = right_of(pp1);
+    const double um1 = left_of(u), up1 = right_of(u);
+    const double r = flat_raw(pm2, pm1, pp1, pp2, um1, up1);
+    const double rl = left_of(r), rr = right_of(r);
+    const double f = flat_pick(pm1, pp1, rl, r, rr);
+    if (lane >= 3 && lane < 3 + kFlatXOut && i < nx) F[row + i] = T(f);
+}
+
+template <typename T>
+hipError_t launch_flattening(int axis, const Brick *bricks, const BlockMap *map, int nblocks, const T *state,
+                             const double *base64, T *flat, hipStream_t st)
+{
+    if (nblocks <= 0) return hipSuccess;
+    if (axis == 0)
+        hipLaunchKernelGGL((flat_x_kernel<T>), dim3(nblocks), dim3(256), 0, st, bricks, map, state, base64, flat);
+    else if (axis == 1)
+        hipLaunchKernelGGL((flat_march_kernel<T, 1>), dim3(nblocks), dim3(256), 0, st, bricks, map, state, base64,
+                           flat);
+    else
+        hipLaunchKernelGGL((flat_march_kernel<T, 2>), dim3(nblocks), dim3(256), 0, st, bricks, map, state, base64,
+                           flat);
+    return hipGetLastError();
+}
+
 __global__ void set_scalar_kernel(double *dst, double v)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = v;
@@ -715,6 +886,8 @@ hipError_t launch_zero_u64(unsigned long long *dst, int count, hipStream_t st)
                                              const double *, unsigned long long *, unsigned long long *, \
                                              double, double *, hipStream_t);                              \
     template hipError_t launch_divergence<T>(const Brick *, const BlockMap *, int, const T *,          \
+                                             const double *, T *, hipStream_t);                      \
+    template hipError_t launch_flattening<T>(int, const Brick *, const BlockMap *, int, const T *,     \
                                              const double *, T *, hipStream_t);
 PPMB_INST(float)
 PPMB_INST(double)

@@ -48,13 +48,14 @@ int pass_blocks(const Geom &g, int axis, const PassShape &sh);
 // whenever that maximum reaches the edge; base64 is the FP64 base arena.
 // With dissk > 0 the shock dissipation is added at every face between fluid
 // cells from `div` (launch_divergence of the pass input or of the state at
-// the start of the step).
+// the start of the step).  With `flat` (launch_flattening of the pass input
+// along `axis`) every parabola is flattened by its cell's coefficient.
 template <typename T>
 hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, const BlockMap *map,
                         int nblocks, const T *in, T *out, const T *base, const double *dt,
                         unsigned long long *counters, int heat, const double *base64,
                         unsigned long long *work, const unsigned long long *cband, const T *div, double dissk,
-                        int cfl, hipStream_t st);
+                        const T *flat, int cfl, hipStream_t st);
 
 // Undivided velocity divergence of every cell of the bricks whose blocks
 // are map[0 .. nblocks) (div_blocks(g) blocks per brick; FP64 arithmetic,
@@ -64,6 +65,15 @@ int div_blocks(const Geom &g);
 template <typename T>
 hipError_t launch_divergence(const Brick *bricks, const BlockMap *map, int nblocks, const T *state,
                              const double *base64, T *div, hipStream_t st);
+
+// Flattening coefficients (Colella & Woodward 1984, Sec. 4) of every cell
+// of the bricks whose blocks are map[0 .. nblocks) (flat_blocks(g, axis)
+// per brick) for a pass along `axis`, from `state` (FP64 arithmetic, stored
+// in the working precision): field of brick B at flat + B.boff / 2.
+int flat_blocks(const Geom &g, int axis);
+template <typename T>
+hipError_t launch_flattening(int axis, const Brick *bricks, const BlockMap *map, int nblocks, const T *state,
+                             const double *base64, T *flat, hipStream_t st);
 
 // hydrostatic base state: FP64 RK4 node table (one thread), then cell values
 hipError_t launch_base_state(const Geom &g, int kind, const double *params, double *table,

@@ -32,6 +32,7 @@ struct SweepArgs {
     T cthr;               // cells whose speed bound is below this need no FP64 speed
     const T *div;         // undivided velocity divergence (shock dissipation), same layout
     T dissk;              // shock dissipation coefficient
+    const T *flat;        // flattening coefficients of this pass's input, same layout
 };
 
 // Arguments of one pass launch over a batch of bricks.
@@ -49,6 +50,7 @@ struct BatchArgs {
     const unsigned long long *cband;   // per brick: FP64 bits of the band's lower edge, redo flag
     const T *div;                 // divergence field, one field per brick at boff / 2
     double dissk;                 // shock dissipation coefficient (kernels with DISS only)
+    const T *flat;                // flattening field, one per brick at boff / 2 (FLAT only)
     int heat;
     int cfl;
 };
@@ -63,7 +65,8 @@ __device__ __forceinline__ SweepArgs<T> brick_args(const BatchArgs<T> &b, const 
     const T thr = b.cfl ? band_edge(__longlong_as_double((long long)b.cband[2 * brick]), T(0)) : T(0);
     return SweepArgs<T>{b.in + B.off, b.out + B.off, b.base + B.boff, b.base + B.boff + B.g.fs,
                         b.dt + B.dti, b.counters, b.base64 + B.boff, b.base64 + B.boff + B.g.fs,
-                        B.g.fs, b.heat, b.cfl, thr, b.div ? b.div + B.boff / 2 : nullptr, T(b.dissk)};
+                        B.g.fs, b.heat, b.cfl, thr, b.div ? b.div + B.boff / 2 : nullptr, T(b.dissk),
+                        b.flat ? b.flat + B.boff / 2 : nullptr};
 }
 
 // Global (x, y, z) order of a pass's (normal, t1, t2) components.
@@ -242,7 +245,7 @@ __device__ __forceinline__ void cons_of(const T *q, T rho, T rgm1, T *u)
     u[4] = q[4] * rgm1 + T(0.5) * (u[1] * q[1] + u[2] * q[2] + u[3] * q[3]);
 }
 
-template <typename T, int AX, bool DISS>
+template <typename T, int AX, bool DISS, bool FLAT>
 __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, int la0, int lane, int lb,
                       unsigned &c_lim, unsigned &c_uns, unsigned &c_rie, double &cmax, bool &cbad)
 {
@@ -309,6 +312,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
     T Lp = T(1);          // Lagrangian length of cell k-4
     T Gp[10];             // slab at face (k-5)+1/2
     T dvp = T(0), dvc = T(0);     // shock dissipation: divergence of cells k-3, k-2
+    T fk = T(0);                  // flattening coefficient of cell k-2
     for (int v = 0; v < 5; ++v) Fp[v] = T(0);
     for (int v = 0; v < 10; ++v) { pq[v] = T(0); pqp[v] = T(0); Gp[v] = T(0); }
     TLp = St<T>{T(0), T(0), T(0), T(0), T(0)};
@@ -366,9 +370,10 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
         cu3[2] = bld<T>(rin(MX + AI::t1, c3), ld3);
         cu3[3] = bld<T>(rin(MX + AI::t2, c3), ld3);
         cu3[4] = bld<T>(rin(EN, c3), ld3);
-        if constexpr (DISS) {
+        if constexpr (DISS || FLAT) {
             // divergence of cell k-2 for the face (k-3)+1/2 (used from k = 1
-            // on); that of cell k-3 is carried from the previous step
+            // on; that of cell k-3 is carried from the previous step) and
+            // the flattening coefficient of cell k-2 for its parabola
             int s2 = k - 2;
             unsigned l2 = lix;
             if (!S) {
@@ -376,8 +381,11 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
                 if (k < 0) { s2 = 0; l2 = kNoIdx; }
                 else if (s2 < 0 || s2 >= n) s2 = bc_source(s2, n, bc, f2);
             }
-            dvp = dvc;
-            dvc = bld<T>(rsrc(a.div + ubase + s2 * sAX, rcnt), l2);
+            if constexpr (DISS) {
+                dvp = dvc;
+                dvc = bld<T>(rsrc(a.div + ubase + s2 * sAX, rcnt), l2);
+            }
+            if constexpr (FLAT) fk = bld<T>(rsrc(a.flat + ubase + s2 * sAX, rcnt), l2);
         }
         {
             T xd = ox + (T(s) + T(0.5)) * dxT;
@@ -452,6 +460,11 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
                 bool con = parabola(g.smooth_detect, q[2][vv], qf[0][vv], qf[1][vv], flm[0][vv], flm[1][vv],
                                     d2[0][vv], d2[1][vv], d2[2][vv], l, r);
                 if (con && interior && valid) ++c_uns;
+                if constexpr (FLAT) {
+                    // flattening toward the cell average near strong shocks
+                    l = fk * q[2][vv] + (T(1) - fk) * l;
+                    r = fk * q[2][vv] + (T(1) - fk) * r;
+                }
                 qL[vv] = l; qR[vv] = r;
                 dq[vv] = r - l;
                 q6[vv] = T(6) * (q[2][vv] - T(0.5) * (l + r));
@@ -587,7 +600,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
 // and z passes, across y for the x pass); a block holds blockDim/64 waves
 // on consecutive rows of the other transverse axis.
 // FP32: at most 256 VGPRs, two waves per SIMD; FP64 needs the full file.
-template <typename T, int AX, bool DISS>
+template <typename T, int AX, bool DISS, bool FLAT>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1)
 void sweep_kernel(BatchArgs<T> b)
 {
@@ -606,7 +619,7 @@ void sweep_kernel(BatchArgs<T> b)
     double cmax = 0.0;
     bool cbad = false;
     if (lb < g.n[cb])
-        march<T, AX, DISS>(g, &B.g, a, la0, (int)(threadIdx.x & 63), lb, c_lim, c_uns, c_rie, cmax, cbad);
+        march<T, AX, DISS, FLAT>(g, &B.g, a, la0, (int)(threadIdx.x & 63), lb, c_lim, c_uns, c_rie, cmax, cbad);
     if (b.cfl) cfl_commit(b.work, m.brick, cmax, cbad);
     // event counters: one atomic per wave and counter
     unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
@@ -687,11 +700,13 @@ struct XIn {
     T pq[10];
     T r0, pb;
     T dv;             // divergence (shock dissipation only)
+    T fv;             // flattening coefficient (flattening only)
     int s, fl;
 };
 
-template <typename T, bool DISS>
-__device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, const T *div, long nc, long row,
+template <typename T, bool DISS, bool FLAT>
+__device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, const T *div, const T *flat,
+                                       long nc, long row,
                                        int nx, int bc, int i, XIn<T> &o)
 {
     using AI = AxisInfo<0>;
@@ -712,6 +727,7 @@ __device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, 
     o.r0 = bld<T>(rsrc(rho0 + row, nx), s);
     o.pb = bld<T>(rsrc(p0 + row, nx), s);
     if constexpr (DISS) o.dv = bld<T>(rsrc(div + row, nx), s);
+    if constexpr (FLAT) o.fv = bld<T>(rsrc(flat + row, nx), s);
 }
 
 // One wave walks whole x-rows, 56-cell segment by segment, at least
@@ -719,7 +735,7 @@ __device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, 
 // so that each wave has enough work; the loads of the next segment (of the
 // same or the next row) are issued before the current one is computed, so
 // their latency hides behind the arithmetic.
-template <typename T, bool DISS>
+template <typename T, bool DISS, bool FLAT>
 __global__ __launch_bounds__(256)
 void sweep_x_kernel(BatchArgs<T> b)
 {
@@ -754,7 +770,7 @@ void sweep_x_kernel(BatchArgs<T> b)
     auto item_i0 = [&](int it) { return (it % nseg) * kXOut - NG; };
 
     XIn<T> cur;
-    x_load<T, DISS>(a.in, a.rho0, a.p0, a.div, nc, item_row(it0), nx, bc, item_i0(it0) + lane, cur);
+    x_load<T, DISS, FLAT>(a.in, a.rho0, a.p0, a.div, a.flat, nc, item_row(it0), nx, bc, item_i0(it0) + lane, cur);
     // settle the first loads, so that the loop's waits count only the
     // memory operations of the loop itself
     __builtin_amdgcn_s_waitcnt(0);
@@ -784,10 +800,13 @@ void sweep_x_kernel(BatchArgs<T> b)
         const T r0 = fresh(cur.r0), pb = fresh(cur.pb);
         T dv = T(0);
         if constexpr (DISS) dv = fresh(cur.dv);
+        T fk = T(0);
+        if constexpr (FLAT) fk = fresh(cur.fv);
         __builtin_amdgcn_sched_barrier(0);
         {
             const int nit = it + 1 < it1 ? it + 1 : it;       // past the run: reload, unused
-            x_load<T, DISS>(a.in, a.rho0, a.p0, a.div, nc, item_row(nit), nx, bc, item_i0(nit) + lane, cur);
+            x_load<T, DISS, FLAT>(a.in, a.rho0, a.p0, a.div, a.flat, nc, item_row(nit), nx, bc, item_i0(nit) + lane,
+                                  cur);
         }
         const T xd = ox + (T(s) + T(0.5)) * dxT;
         const T gv = fl * gravity_now<T>(&B.g, 0, xd, rtt + xd * xd);
@@ -834,6 +853,10 @@ void sweep_x_kernel(BatchArgs<T> b)
                                 from_left(flm[vv]), flm[vv], from_left(d2[vv]), d2[vv],
                                 from_right(d2[vv]), l, r);
             if (con && own) ++c_uns;
+            if constexpr (FLAT) {
+                l = fk * q[vv] + (T(1) - fk) * l;
+                r = fk * q[vv] + (T(1) - fk) * r;
+            }
             qL[vv] = l; qR[vv] = r;
             dqv[vv] = r - l;
             q6[vv] = T(6) * (q[vv] - T(0.5) * (l + r));
@@ -973,46 +996,50 @@ int pass_blocks(const Geom &g, int axis, const PassShape &sh)
     return ((g.n[ca] + 63) / 64) * ((g.n[cb] + sh.march_waves - 1) / sh.march_waves);
 }
 
+template <typename T, bool D, bool F>
+static void launch_pass_kernel(int axis, bool xl, int nblocks, const PassShape &sh, hipStream_t st,
+                               const BatchArgs<T> &a)
+{
+    if (xl) {
+        hipLaunchKernelGGL((sweep_x_kernel<T, D, F>), dim3(nblocks), dim3(64 * sh.x_waves), 0, st, a);
+        return;
+    }
+    dim3 grid(nblocks), block(64 * sh.march_waves);
+    switch (axis) {
+    case 0: hipLaunchKernelGGL((sweep_kernel<T, 0, D, F>), grid, block, 0, st, a); break;
+    case 1: hipLaunchKernelGGL((sweep_kernel<T, 1, D, F>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((sweep_kernel<T, 2, D, F>), grid, block, 0, st, a); break;
+    }
+}
+
 template <typename T>
 hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, const BlockMap *map,
                         int nblocks, const T *in, T *out, const T *base, const double *dt,
                         unsigned long long *counters, int heat, const double *base64,
                         unsigned long long *work, const unsigned long long *cband, const T *div, double dissk,
-                        int cfl, hipStream_t st)
+                        const T *flat, int cfl, hipStream_t st)
 {
     if (nblocks <= 0) return hipErrorInvalidValue;
     const bool diss = dissk > 0.0 && div;
     BatchArgs<T> a{bricks, map, in, out, base, dt, counters, base64, work, cband, diss ? div : nullptr,
-                   dissk, heat, cfl};
-    if (axis == 0 && x_lanes_enabled()) {
-        if (diss) hipLaunchKernelGGL((sweep_x_kernel<T, true>), dim3(nblocks), dim3(64 * sh.x_waves), 0, st, a);
-        else hipLaunchKernelGGL((sweep_x_kernel<T, false>), dim3(nblocks), dim3(64 * sh.x_waves), 0, st, a);
-        return hipGetLastError();
-    }
-    dim3 grid(nblocks), block(64 * sh.march_waves);
-    if (diss) {
-        switch (axis) {
-        case 0: hipLaunchKernelGGL((sweep_kernel<T, 0, true>), grid, block, 0, st, a); break;
-        case 1: hipLaunchKernelGGL((sweep_kernel<T, 1, true>), grid, block, 0, st, a); break;
-        default: hipLaunchKernelGGL((sweep_kernel<T, 2, true>), grid, block, 0, st, a); break;
-        }
-    } else {
-        switch (axis) {
-        case 0: hipLaunchKernelGGL((sweep_kernel<T, 0, false>), grid, block, 0, st, a); break;
-        case 1: hipLaunchKernelGGL((sweep_kernel<T, 1, false>), grid, block, 0, st, a); break;
-        default: hipLaunchKernelGGL((sweep_kernel<T, 2, false>), grid, block, 0, st, a); break;
-        }
-    }
+                   dissk, flat, heat, cfl};
+    const bool xl = axis == 0 && x_lanes_enabled();
+    if (diss && flat) launch_pass_kernel<T, true, true>(axis, xl, nblocks, sh, st, a);
+    else if (diss) launch_pass_kernel<T, true, false>(axis, xl, nblocks, sh, st, a);
+    else if (flat) launch_pass_kernel<T, false, true>(axis, xl, nblocks, sh, st, a);
+    else launch_pass_kernel<T, false, false>(axis, xl, nblocks, sh, st, a);
     return hipGetLastError();
 }
 
 template hipError_t launch_sweep<float>(int, const PassShape &, const Brick *, const BlockMap *, int,
                                         const float *, float *, const float *, const double *,
                                         unsigned long long *, int, const double *, unsigned long long *,
-                                        const unsigned long long *, const float *, double, int, hipStream_t);
+                                        const unsigned long long *, const float *, double, const float *, int,
+                                        hipStream_t);
 template hipError_t launch_sweep<double>(int, const PassShape &, const Brick *, const BlockMap *, int,
                                          const double *, double *, const double *, const double *,
                                          unsigned long long *, int, const double *, unsigned long long *,
-                                         const unsigned long long *, const double *, double, int, hipStream_t);
+                                         const unsigned long long *, const double *, double, const double *, int,
+                                         hipStream_t);
 
 }  // namespace ppmb

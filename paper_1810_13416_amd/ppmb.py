@@ -32,7 +32,7 @@ EXPORTS = ("ppmb_create", "ppmb_destroy", "ppmb_state_bytes", "ppmb_state_layout
            "ppmb_get_pass_shape", "ppmb_autotune", "ppmb_ppb2d_create", "ppmb_ppb2d_destroy",
            "ppmb_ppb2d_set", "ppmb_ppb2d_get", "ppmb_ppb2d_steps", "ppmb_ppb2d_get_nstep",
            "ppmb_ppb2d_set_nstep", "ppmb_set_spinup", "ppmb_spin_add", "ppmb_shell_profile",
-           "ppmb_set_shock_dissipation")
+           "ppmb_set_shock_dissipation", "ppmb_set_flattening")
 
 
 class PPMBError(RuntimeError):
@@ -117,6 +117,7 @@ def load():
         "ppmb_spin_add": [p, d],
         "ppmb_shell_profile": [p, i, i, d, _D],
         "ppmb_set_shock_dissipation": [p, d],
+        "ppmb_set_flattening": [p, ctypes.c_int],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -289,6 +290,10 @@ class Sim:
         """Dissipation coefficient of the 3-D shock dissipation (0: off)."""
         self._check(self.L.ppmb_set_shock_dissipation(self.h, float(k)))
 
+    def set_flattening(self, on: bool):
+        """Flattening of the parabolas near strong shocks (CW84 Sec. 4)."""
+        self._check(self.L.ppmb_set_flattening(self.h, 1 if on else 0))
+
     def set_spinup(self, omega: float, nramp: int):
         """Steps 0 .. nramp-1 each end with a solid-body rotation increment
         omega / nramp about the z axis."""
@@ -419,6 +424,10 @@ class Batch:
     def set_shock_dissipation(self, k: float):
         """Dissipation coefficient of the 3-D shock dissipation (0: off)."""
         self._check(self.L.ppmb_set_shock_dissipation(self.h, float(k)))
+
+    def set_flattening(self, on: bool):
+        """Flattening of the parabolas near strong shocks (CW84 Sec. 4)."""
+        self._check(self.L.ppmb_set_flattening(self.h, 1 if on else 0))
 
     def set_spinup(self, omega: float, nramp: int):
         """Steps 0 .. nramp-1 each end with a solid-body rotation increment

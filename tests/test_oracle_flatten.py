@@ -88,6 +88,23 @@ def test_weak_jump_is_not_flattened():
     assert np.all(row(p, u) == 0.0)
 
 
+def test_pressure_tie_keeps_the_coefficient_mirror_equivariant():
+    # a 3-cell pressure plateau with compression only on its right edge:
+    # the middle cell has equal pressures on both sides, so no side is the
+    # low-pressure one; the coefficient of the mirrored profile must be the
+    # mirror of the coefficient (a one-sided tie rule would break this)
+    n = 16
+    p = np.ones(n)
+    p[7:10] = 10.0
+    u = np.zeros(n)
+    u[8:] = 0.3
+    u[10:] = -0.4                                    # converges across cell 9 only
+    f = row(p, u)
+    g = row(p[::-1], -u[::-1])
+    assert np.array_equal(f, g[::-1])
+    assert f[9] == 1.0 and f[8] == 1.0
+
+
 def test_coefficient_is_mirror_symmetric():
     prob = pr.blast(16)
     O = oracle.Oracle(prob.params, threads=4)
