@@ -49,8 +49,8 @@ SQ_SUMMARY = os.path.join(ROOT, "profiles", "sweep_sq_counters_shell512_fp32.md"
 # SIMDs x 16 lanes per cycle x 2.4 GHz, in 10^12 lane-instructions per second
 VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 # the kernels behind each pass of the FP32 step
-PASS_KERNELS = {"x": "sweep_x_kernel<float, false>", "y": "sweep_kernel<float, 1, false>",
-                "z": "sweep_kernel<float, 2, false>"}
+PASS_KERNELS = {"x": "sweep_x_kernel<float, false, false>", "y": "sweep_kernel<float, 1, false, false>",
+                "z": "sweep_kernel<float, 2, false, false>"}
 N_FIELDS = 15
 METRIC = "cell-updates/s per PPM+PPB 3-D step, FP32-perturb vs FP64, % HBM roofline"
 

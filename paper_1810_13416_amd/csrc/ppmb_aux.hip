@@ -720,14 +720,33 @@ __device__ __forceinline__ double flat_raw(double pm2, double pm1, double pp1, d
 // transverse flow after a pass), so FP64 runs take exactly the decisions of
 // any other evaluation of these formulas in the same order.
 template <typename T>
-__device__ __forceinline__ void flat_cell(const Geom &g, const T *S, long fs, const double *r64, const double *p64,
-                                          long e, int d, double fl, double &p, double &u)
+struct FlatRaw {
+    T rp, mx, my, mz, ep;
+    double r0, p0, fl;
+};
+
+template <typename T>
+__device__ __forceinline__ void flat_load(const T *S, long fs, const double *r64, const double *p64, long e,
+                                          double fl, FlatRaw<T> &r)
 {
-    const double rho = r64[e] + (double)S[RHO * fs + e];
-    const double mx = (double)S[MX * fs + e], my = (double)S[MY * fs + e], mz = (double)S[MZ * fs + e];
+    r.rp = S[RHO * fs + e];
+    r.mx = S[MX * fs + e];
+    r.my = S[MY * fs + e];
+    r.mz = S[MZ * fs + e];
+    r.ep = S[EN * fs + e];
+    r.r0 = r64[e];
+    r.p0 = p64[e];
+    r.fl = fl;
+}
+
+template <typename T>
+__device__ __forceinline__ void flat_eval(const Geom &g, const FlatRaw<T> &r, int d, double &p, double &u)
+{
+    const double rho = r.r0 + (double)r.rp;
+    const double mx = (double)r.mx, my = (double)r.my, mz = (double)r.mz;
     const double vx = mx / rho, vy = my / rho, vz = mz / rho;
-    p = p64[e] + (g.gamma - 1.0) * ((double)S[EN * fs + e] - 0.5 * (mx * vx + my * vy + mz * vz));
-    u = fl * (d == 0 ? vx : (d == 1 ? vy : vz));
+    p = r.p0 + (g.gamma - 1.0) * ((double)r.ep - 0.5 * (mx * vx + my * vy + mz * vz));
+    u = r.fl * (d == 0 ? vx : (d == 1 ? vy : vz));
 }
 
 int flat_blocks(const Geom &g, int axis)
@@ -764,11 +783,19 @@ __global__ __launch_bounds__(256) void flat_march_kernel(const Brick *bricks, co
     const long sd = D == 1 ? g.px : g.plane, sb = CB == 1 ? g.px : g.plane;
     const long base = (long)x + (long)b * sb;
     double P[5] = { 0.0, 0.0, 0.0, 0.0, 0.0 }, U[4] = { 0.0, 0.0, 0.0, 0.0 }, R[3] = { 0.0, 0.0, 0.0 };
-    for (int t = c0 - 3; t <= c1 + 2; ++t) {
+    // inputs of cell t, loaded one step ahead
+    auto load = [&](int t, FlatRaw<T> &r) {
         int fl = 1;
         const int s = (t >= 0 && t < n) ? t : bc_source(t, n, g.bc[D], fl);
+        flat_load<T>(S, fs, r64, p64, base + (long)s * sd, (double)fl, r);
+    };
+    FlatRaw<T> ahead;
+    load(c0 - 3, ahead);
+    for (int t = c0 - 3; t <= c1 + 2; ++t) {
+        const FlatRaw<T> cur = ahead;
+        if (t < c1 + 2) load(t + 1, ahead);
         double pt, ut;
-        flat_cell<T>(g, S, fs, r64, p64, base + (long)s * sd, D, (double)fl, pt, ut);
+        flat_eval<T>(g, cur, D, pt, ut);
         P[0] = P[1]; P[1] = P[2]; P[2] = P[3]; P[3] = P[4]; P[4] = pt;
         U[0] = U[1]; U[1] = U[2]; U[2] = U[3]; U[3] = ut;
         if (t >= c0 + 1) {                       // raw coefficient of cell t - 2
@@ -819,7 +846,9 @@ __global__ __launch_bounds__(256) void flat_x_kernel(const Brick *bricks, const 
     int fl = 1;
     const int s = (i >= 0 && i < nx) ? i : bc_source(i, nx, g.bc[0], fl);
     double p, u;
-    flat_cell<T>(g, S, fs, r64, p64, row + s, 0, (double)fl, p, u);
+    FlatRaw<T> r0;
+    flat_load<T>(S, fs, r64, p64, row + s, (double)fl, r0);
+    flat_eval<T>(g, r0, 0, p, u);
     const double pm1 = left_of(p), pp1 = right_of(p);
     const double pm2 = left_of(pm1), pp2 = right_of(pp1);
     const double um1 = left_of(u), up1 = right_of(u);
