@@ -246,36 +246,45 @@ __device__ __forceinline__ void cons_of(const T *q, T rho, T rgm1, T *u)
 }
 
 template <typename T, int AX, bool DISS, bool FLAT>
-__device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, int la0, int lane, int lb,
-                      unsigned &c_lim, unsigned &c_uns, unsigned &c_rie, double &cmax, bool &cbad)
+__device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, int la0, int lane, int lb, int pk,
+                      int nb, unsigned &c_lim, unsigned &c_uns, unsigned &c_rie, double &cmax, bool &cbad)
 {
     using AI = AxisInfo<AX>;
     const int n = g.n[AX];
     const int ca = (AX == 0) ? 1 : 0;
     const int cb = 3 - AX - ca;
-    // lanes past the edge of the brick march a copy of its last pencil and
-    // store nothing
-    const int cnt = min(64, g.n[ca] - la0);
-    const bool valid = lane < cnt;
-    const int lld = valid ? lane : cnt - 1;
+    // The wave's pencils: pk rows of pencils (rows lb .. lb + nb - 1 along
+    // cb) of the brick's g.n[ca] pencils each, packed lane after lane when a
+    // row is at most half a wave (pk > 1, la0 = 0), else the 64 pencils from
+    // la0 of row lb.  Lanes past the last pencil march a copy of one and
+    // store nothing.
+    const int na = g.n[ca];
+    const int cnt = min(64, na - la0);
+    const int pr = pk > 1 ? lane / na : 0;
+    const bool valid = pk > 1 ? pr < nb : lane < cnt;
+    const int lld = pk > 1 ? lane - pr * na : (valid ? lane : cnt - 1);
+    const int lrow = pk > 1 ? (valid ? pr : nb - 1) : 0;
     const int la = la0 + lld;
     int ijk0[3];
-    ijk0[ca] = la; ijk0[cb] = lb; ijk0[AX] = 0;
+    ijk0[ca] = la; ijk0[cb] = lb + lrow; ijk0[AX] = 0;
     const long stride[3] = { 1, (long)g.px, g.plane };
     const long sAX = stride[AX];
-    // element index of this lane in the row of 64 pencils (stride 1 for the
-    // y and z passes, nx for the x pass), and the row's element count
-    const unsigned lix = (unsigned)(lld * stride[ca]);
+    // element index of this lane from the wave's first pencil (stride 1 for
+    // the y and z passes, nx for the x pass, rows stride[cb] apart), and the
+    // element count the wave's rows span
+    const unsigned lix = (unsigned)(lld * stride[ca] + lrow * stride[cb]);
     const unsigned lst = valid ? lix : kNoIdx;
-    const int rcnt = (int)((cnt - 1) * stride[ca] + 1);
+    const int rcnt = pk > 1 ? (int)((nb - 1) * stride[cb] + (na - 1) * stride[ca] + 1)
+                            : (int)((cnt - 1) * stride[ca] + 1);
     // wave-uniform offset of the 64-lane row at pencil index 0
     const long ubase = (long)la0 * stride[ca] + (long)lb * stride[cb];
     const double xt[3] = { centre(g, 0, ijk0[0]), centre(g, 1, ijk0[1]), centre(g, 2, ijk0[2]) };
     // transverse part of |x|^2 and the fluid interval of this pencil
     const T xt1 = T(xt[AI::t1]), xt2 = T(xt[AI::t2]);
     const T rtt = xt1 * xt1 + xt2 * xt2;
-    // z of the pencil for the heating when z is transverse: it is then the
-    // coordinate of the wave's row (lb), the same on every lane
+    // z of the pencil for the heating when z is transverse: the coordinate of
+    // the wave's row (lb), the same on every lane unless rows are packed
+    // (then rebuilt from the lane where it is used)
     const T zt = AX == 2 ? T(0) : wave_uniform(T(xt[2]));
     int flo, fhi;
     fluid_interval(g, AX, xt, flo, fhi);
@@ -504,6 +513,12 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
             if (a.heat) {
                 T xd = ox + (T(cu_) + T(0.5)) * dxT;
                 T zc = AX == 2 ? xd : zt;
+                if (AX != 2 && pk > 1) {
+                    // the lane id from the exec mask, so that no register
+                    // holds it through the march
+                    const int ln = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+                    zc = T(centre(g, 2, lb + min(ln / na, nb - 1)));
+                }
                 hn[4] = hn[4] + heating_now<T>(gmem, zc, rtt + xd * xd) * dt;
             }
 #pragma unroll
@@ -600,6 +615,13 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
 // and z passes, across y for the x pass); a block holds blockDim/64 waves
 // on consecutive rows of the other transverse axis.
 // FP32: at most 256 VGPRs, two waves per SIMD; FP64 needs the full file.
+// Rows of pencils one wave of the marching kernel packs: the y and z passes
+// of a brick at most 32 cells wide in x hold 64 / nx rows per wave.
+__host__ __device__ inline int march_pack(const Geom &g, int axis)
+{
+    return (axis != 0 && g.n[0] <= 32) ? 64 / g.n[0] : 1;
+}
+
 template <typename T, int AX, bool DISS, bool FLAT>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1)
 void sweep_kernel(BatchArgs<T> b)
@@ -613,13 +635,15 @@ void sweep_kernel(BatchArgs<T> b)
     const int waves = blockDim.x >> 6;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int nblk_a = (g.n[ca] + 63) / 64;
+    const int pk = march_pack(g, AX);
     const int la0 = (m.local % nblk_a) * 64;
-    const int lb = (m.local / nblk_a) * waves + wv;
+    const int lb = ((m.local / nblk_a) * waves + wv) * pk;
     unsigned c_lim = 0, c_uns = 0, c_rie = 0;          // per lane; widened below
     double cmax = 0.0;
     bool cbad = false;
     if (lb < g.n[cb])
-        march<T, AX, DISS, FLAT>(g, &B.g, a, la0, (int)(threadIdx.x & 63), lb, c_lim, c_uns, c_rie, cmax, cbad);
+        march<T, AX, DISS, FLAT>(g, &B.g, a, la0, (int)(threadIdx.x & 63), lb, pk, min(pk, g.n[cb] - lb), c_lim,
+                                 c_uns, c_rie, cmax, cbad);
     if (b.cfl) cfl_commit(b.work, m.brick, cmax, cbad);
     // event counters: one atomic per wave and counter
     unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
@@ -993,7 +1017,9 @@ int pass_blocks(const Geom &g, int axis, const PassShape &sh)
     }
     const int ca = (axis == 0) ? 1 : 0;
     const int cb = 3 - axis - ca;
-    return ((g.n[ca] + 63) / 64) * ((g.n[cb] + sh.march_waves - 1) / sh.march_waves);
+    const int pk = march_pack(g, axis);
+    const int rows = (g.n[cb] + pk - 1) / pk;          // waves per column of 64 pencils
+    return ((g.n[ca] + 63) / 64) * ((rows + sh.march_waves - 1) / sh.march_waves);
 }
 
 template <typename T, bool D, bool F>
