@@ -5,7 +5,9 @@ FP64 oracle, through the C ABI: FP64 relative L1 <= 1e-12 and Linf <= 1e-9
 the confining sphere's wall, and single passes; FP32 conserves mass and
 energy with its FP64 reductions, is run-to-run deterministic, and with the
 dissipation off is bitwise the same as without the setting; a HIP-graph
-replay of dissipative steps equals direct launches bit for bit."""
+replay of dissipative steps equals direct launches bit for bit; FP32 with
+the dissipation and the flattening on meets the smooth-flow precision bar
+against the FP64 oracle run the same way."""
 import numpy as np
 import pytest
 
@@ -171,3 +173,39 @@ def test_dissipative_graph_replay_equals_direct_launches():
         for b in range(len(probs)):
             for q in range(15):
                 assert np.array_equal(o[b][q], out[0][b][q]), (b, q)
+
+
+def test_fp32_shock_handling_matches_fp64_oracle_on_smooth_flow():
+    # the smooth-flow precision target of the plain step (100 steps,
+    # relative L1 <= 1e-5, Linf <= 1e-4 on rho, u, p and f0), here with the
+    # dissipation and the flattening switched on on both sides
+    prob = pr.config1(base="const")
+    O = oracle.Oracle(prob.params, threads=8)
+    O.set_state(prob.state)
+    O.set_dissipation(K)
+    O.set_flattening(True)
+    S = sim(prob.params, "fp32")
+    S.set_state(prob.state)
+    S.set_shock_dissipation(K)
+    S.set_flattening(True)
+    for _ in range(100):
+        dt = O.dt(prob.cfl)
+        O.step(dt)
+        S.step(dt)
+    a, b = S.get_state(), O.get_state()
+    for q in range(6):
+        # full rho and p (the constant base is 1), velocities against their
+        # mean size
+        x = a[q] + (1.0 if q in (0, 4) else 0.0)
+        y = b[q] + (1.0 if q in (0, 4) else 0.0)
+        grp = [1, 2, 3] if q in (1, 2, 3) else [q]
+        s1 = sum(float(np.mean(np.abs(b[g] + (1.0 if g in (0, 4) else 0.0)))) for g in grp) / len(grp)
+        si = max(float(np.max(np.abs(b[g] + (1.0 if g in (0, 4) else 0.0)))) for g in grp)
+        d = np.abs(x - y)
+        assert float(np.mean(d)) / s1 <= 1e-5 and float(np.max(d)) / si <= 1e-4, (q, float(np.mean(d)) / s1)
+    # the options acted on this flow: the oracle's plain run differs
+    P = oracle.Oracle(prob.params, threads=8)
+    P.set_state(prob.state)
+    for _ in range(100):
+        P.step(P.dt(prob.cfl))
+    assert not np.array_equal(P.get_state()[0], b[0])
