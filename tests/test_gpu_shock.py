@@ -209,3 +209,30 @@ def test_fp32_shock_handling_matches_fp64_oracle_on_smooth_flow():
     for _ in range(100):
         P.step(P.dt(prob.cfl))
     assert not np.array_equal(P.get_state()[0], b[0])
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_shock_handling_bricks_of_a_batch_match_oracle_fp64(mode):
+    # bricks of different shapes and boundaries in one batch: each brick's
+    # divergence and flattening fields live at its own offset, which a
+    # comparison between launch modes alone would not check
+    from paper_1810_13416_amd import ppmb
+    probs = [pr.blast((20, 16, 12), centre=(0.3, 0.4, 0.35), radius=0.15),
+             pr.blast((40, 9, 33), bc=(1, 0, 1), centre=(0.1, 0.05, 0.3), radius=0.12),
+             pr.blast(16, p_in=5.0)]
+    B = ppmb.Batch([p.params for p in probs], ppmb.FP64)
+    for b, p in enumerate(probs):
+        B.set_state(b, p.state)
+    B.set_shock_dissipation(K)
+    B.set_flattening(True)
+    B.step(0.8, 3, mode=mode)
+    B.synchronize()
+    for b, p in enumerate(probs):
+        O = oracle.Oracle(p.params, threads=8)
+        O.set_state(p.state)
+        O.set_dissipation(K)
+        O.set_flattening(True)
+        for _ in range(3):
+            O.step(O.dt(0.8))
+        compare(B.get_conserved(b), O.get_conserved())
+    B.close()
