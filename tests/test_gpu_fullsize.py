@@ -14,7 +14,9 @@ of the field's scale over the sampled pencils; measured 3e-16).  FP32
 against the FP64 oracle from identical FP32-representable inputs, one
 pass: relative L1 and Linf 1e-5, the FP32 figure for smooth flows (measured
 1.5e-7 and 3.7e-7: the FP32 arithmetic and one rounding of each stored
-value, no branch of the constraints resolved differently)."""
+value, no branch of the constraints resolved differently).  The flattening
+depends only on the pencil too, so FP64 passes with it on are checked the
+same way on the shell with a planted shock at its centre."""
 import numpy as np
 import pytest
 
@@ -76,15 +78,20 @@ def _scales(ref):
     return out
 
 
-def _check_pass(S, prob, axis, l1_tol, li_tol):
+def _check_pass(S, prob, axis, l1_tol, li_tol, flat=False):
     dt = S.dt(prob.cfl)
     before = _pencils(S, axis)
     S.pass_(axis, dt)
     after = _pencils(S, axis)
     ref = []
+    flagged = 0
     for (a, b), cons in zip(SAMPLES, before):
         O = oracle.Oracle(_pencil_params(prob.params, axis, a, b), threads=1)
         O.set_conserved([c.reshape(_shape(axis)) for c in cons])
+        if flat:
+            # the coefficients depend on the pencil alone
+            O.set_flattening(True)
+            flagged += int(np.count_nonzero(O.flattening(axis)))
         O.pass_(axis, dt)
         ref.append([c.reshape(-1) for c in O.get_conserved()])
         O.close()
@@ -98,6 +105,8 @@ def _check_pass(S, prob, axis, l1_tol, li_tol):
         ei = max(float(np.max(np.abs(g[q] - o[q]))) for g, o in zip(after, ref)) / sc[q][1]
         assert e1 <= l1_tol and ei <= li_tol, (axis, q, e1, ei)
         worst = (max(worst[0], e1), max(worst[1], ei))
+    if flat:
+        assert flagged > 0                 # the flattening acted on the samples
     print(f"axis {axis}: worst relative L1 {worst[0]:.3e}, Linf {worst[1]:.3e}")
 
 
@@ -114,6 +123,30 @@ def test_fullsize_passes_match_oracle_on_sampled_pencils(shell, prec):
     tol = (1e-5, 1e-5) if prec == "fp32" else (1e-12, 1e-9)
     for axis in (0, 1, 2):
         _check_pass(S, shell, axis, *tol)
+    S.close()
+
+
+def test_fullsize_flattened_passes_match_oracle_on_sampled_pencils_fp64(shell):
+    # the shell with a planted shock: the central pressure doubled inside
+    # r < 0.06 and a converging flow -0.5 x inside r < 0.3, so that the
+    # pencils through the centre have flattened cells
+    from paper_1810_13416_amd import ppmb
+    P = shell.params
+    z, y, x = np.meshgrid(*(pr._centres(P, ax) for ax in (2, 1, 0)), indexing="ij")
+    r2 = (x * x + y * y) + z * z
+    _, p0c = oracle.base_profile(P, np.array([0.0]))
+    st = list(shell.state)
+    st[4] = st[4] + np.where(r2 < 0.06 ** 2, float(p0c[0]), 0.0)
+    inner = r2 < 0.3 ** 2
+    for d, c in ((1, x), (2, y), (3, z)):
+        st[d] = st[d] + np.where(inner, -0.5 * c, 0.0)
+    del x, y, z, r2, inner
+    S = ppmb.Sim(P, ppmb.FP64)
+    S.set_state(st)
+    del st
+    S.set_flattening(True)
+    for axis in (0, 1, 2):
+        _check_pass(S, shell, axis, 1e-12, 1e-9, flat=True)
     S.close()
 
 
