@@ -719,6 +719,21 @@ __device__ __forceinline__ double flat_raw(double pm2, double pm1, double pp1, d
 // compares two velocities that are often equal but for rounding (a uniform
 // transverse flow after a pass), so FP64 runs take exactly the decisions of
 // any other evaluation of these formulas in the same order.
+// a copy of v as a new value (an identity DPP move)
+__device__ __forceinline__ float aux_fresh(float v)
+{
+    const int b = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, 0xE4, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double aux_fresh(double v)
+{
+    const unsigned long long bits = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)bits, (int)(unsigned)bits, 0xE4, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(bits >> 32), (int)(unsigned)(bits >> 32), 0xE4, 0xf,
+                                               0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 template <typename T>
 struct FlatRaw {
     T rp, mx, my, mz, ep;
@@ -737,6 +752,13 @@ __device__ __forceinline__ void flat_load(const T *S, long fs, const double *r64
     r.r0 = r64[e];
     r.p0 = p64[e];
     r.fl = fl;
+}
+
+template <typename T>
+__device__ __forceinline__ FlatRaw<T> flat_take(const FlatRaw<T> &r)
+{
+    return FlatRaw<T>{aux_fresh(r.rp), aux_fresh(r.mx), aux_fresh(r.my), aux_fresh(r.mz), aux_fresh(r.ep),
+                      aux_fresh(r.r0), aux_fresh(r.p0), r.fl};
 }
 
 template <typename T>
@@ -783,17 +805,19 @@ __global__ __launch_bounds__(256) void flat_march_kernel(const Brick *bricks, co
     const long sd = D == 1 ? g.px : g.plane, sb = CB == 1 ? g.px : g.plane;
     const long base = (long)x + (long)b * sb;
     double P[5] = { 0.0, 0.0, 0.0, 0.0, 0.0 }, U[4] = { 0.0, 0.0, 0.0, 0.0 }, R[3] = { 0.0, 0.0, 0.0 };
-    // inputs of cell t, loaded one step ahead
     auto load = [&](int t, FlatRaw<T> &r) {
         int fl = 1;
         const int s = (t >= 0 && t < n) ? t : bc_source(t, n, g.bc[D], fl);
         flat_load<T>(S, fs, r64, p64, base + (long)s * sd, (double)fl, r);
     };
-    FlatRaw<T> ahead;
-    load(c0 - 3, ahead);
-    for (int t = c0 - 3; t <= c1 + 2; ++t) {
-        const FlatRaw<T> cur = ahead;
-        if (t < c1 + 2) load(t + 1, ahead);
+    // Inputs loaded two cells ahead into two buffers used in turn (the loop
+    // is unrolled by two): each step takes its buffer's values into new
+    // registers, then loads cell t + 2 into it, so that no register copy at
+    // the loop's end has to wait for a load in flight.
+    auto step = [&](int t, FlatRaw<T> &buf) {
+        const FlatRaw<T> cur = flat_take(buf);
+        __builtin_amdgcn_sched_barrier(0);
+        if (t + 2 <= c1 + 2) load(t + 2, buf);
         double pt, ut;
         flat_eval<T>(g, cur, D, pt, ut);
         P[0] = P[1]; P[1] = P[2]; P[2] = P[3]; P[3] = P[4]; P[4] = pt;
@@ -804,7 +828,16 @@ __global__ __launch_bounds__(256) void flat_march_kernel(const Brick *bricks, co
         }
         if (t >= c0 + 3)                         // coefficient of cell t - 3
             F[base + (long)(t - 3) * sd] = T(flat_pick(P[0], P[2], R[0], R[1], R[2]));
+    };
+    FlatRaw<T> ba, bb;
+    load(c0 - 3, ba);
+    load(c0 - 2, bb);
+    int t = c0 - 3;
+    for (; t + 1 <= c1 + 2; t += 2) {
+        step(t, ba);
+        step(t + 1, bb);
     }
+    if (t <= c1 + 2) step(t, ba);
 }
 
 template <int CTRL>
