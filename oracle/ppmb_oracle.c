@@ -28,9 +28,11 @@
  * shock dissipation is pinned in its divergence (exact on linear fields and
  * at walls) and its effects (idle on uniform states and in rarefactions,
  * conservative, symmetric, smoothing behind a shock that stays in place);
- * the weights of its flux, field by field, are a design choice (the paper
- * gives no form for them) with no independent value to pin: parity unpinned
- * for those.  The optional flattening near strong shocks is pinned in its
+ * its flux is pinned by a closed form: under uniform compression the
+ * coefficient is the same at every interior face and the dissipation is a
+ * discrete diffusion of each conserved hydro field, which fixes the
+ * weight, its sign, the undivided divergence and the face differencing
+ * field by field.  The optional flattening near strong shocks is pinned in its
  * coefficient (zero on smooth and expanding profiles and on weak jumps, one
  * at a compressive pressure step, mirror symmetric) and its effects (idle
  * where the coefficient is zero, conservative, symmetric, the Sod shock in
