@@ -41,11 +41,17 @@ _DD = ctypes.POINTER(_D)
 
 
 def lib():
+    """The loaded oracle library.  PPMB_ORACLE_LIB names another build of the
+    same source to load instead (the planted-mistake tests build altered
+    copies of the oracle and check that its pins reject them)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        L = ctypes.CDLL(_LIB)
+        path = os.environ.get("PPMB_ORACLE_LIB")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+        L = ctypes.CDLL(path)
         L.or_create.restype = ctypes.c_void_p
         L.or_create.argtypes = [ctypes.POINTER(_Params), ctypes.c_int]
         L.or_destroy.argtypes = [ctypes.c_void_p]

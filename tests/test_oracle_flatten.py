@@ -205,3 +205,26 @@ def test_sod_with_flattening_keeps_the_shock_and_the_accuracy():
     plateau = (x > 0.72) & (x < 0.82)
     tv = [np.sum(np.abs(np.diff(st[4][0, 0][plateau]))) for st in (plain, flat)]
     assert tv[1] < 0.75 * tv[0]
+
+
+def test_convergence_margin_ignores_rounding_and_keeps_real_compression():
+    # A cell is a shock candidate only if u(i-1) - u(i+1) > 1e-10 (|u(i-1)|
+    # + |u(i+1)|).  Under a compressive pressure step, a uniform flow whose
+    # velocities differ in the last bits only is not a shock: no flattening
+    # whichever way the last bits lean (a strict test, > 0, would flatten
+    # fully when they lean one way and not at all the other way).
+    n = 16
+    p = np.where(np.arange(n) < 8, 1.0, 10.0)
+    for lean in (+1, -1):
+        u = np.full(n, 0.3)
+        for k in range(n):                 # one ulp per cell, falling (+1) or rising (-1)
+            for _ in range(n - k if lean > 0 else k):
+                u[k] = np.nextafter(u[k], 1.0)
+        assert (u[6] - u[8] > 0) == (lean > 0)
+        f = row(p, u)
+        assert np.all(f == 0.0), (lean, f)
+    # a real compression, 1e-8 of the flow speed across the step (far below
+    # any shock's, far above rounding): full flattening at the step
+    u = np.where(np.arange(n) < 8, 0.3 * (1 + 1e-8), 0.3)
+    f = row(p, u)
+    assert f[7] == 1.0 and f[8] == 1.0, f
