@@ -55,6 +55,7 @@ typedef enum {
     PPMB_ERR_NOMEM = -2,        /* device allocation failed */
     PPMB_ERR_HIP = -3,          /* a HIP runtime call or kernel failed */
     PPMB_ERR_NONPHYSICAL = -4,  /* non-positive density or pressure, or NaN, found */
+    PPMB_ERR_CFL = -5,          /* a step was given a dt above the checked Courant limit */
     PPMB_ERR_UNSUPPORTED = -6   /* a combination the library does not implement */
 } ppmb_status;
 
@@ -149,6 +150,29 @@ ppmb_status ppmb_current_state(const ppmb_ctx *ctx, void **dev_state);
  * Synchronising.  Call before ppmb_set_state. */
 ppmb_status ppmb_set_base_state(ppmb_ctx *ctx, int kind, const double params[6]);
 
+/* Gravity of every brick, after create (Sec. 3: gravity tapered to zero
+ * before the confining sphere).  kind and params as grav_kind and grav of
+ * ppmb_grid: NONE with nparams 0; CONST with nparams 3 (the acceleration
+ * vector); RADIAL with nparams 4 (g0, rc, r1, r2: g = -g0 r_hat times
+ * r/rc inside rc, (rc/r)^2 outside, times a taper from 1 at r1 to 0 at r2).
+ * Acts on the passes enqueued after the call (the half-step sources of the
+ * tracing and the momentum and energy sources of the update).  The base
+ * state is not re-integrated: call ppmb_set_base_state again for a base in
+ * balance with the new gravity.  Synchronises the stream (the brick table
+ * is rewritten) and drops a captured step graph.  INVALID for an unknown
+ * kind, a wrong nparams, a non-finite parameter, rc <= 0 or r2 <= r1. */
+ppmb_status ppmb_set_gravity(ppmb_ctx *ctx, int kind, const double *params, int nparams);
+
+/* Heating of every brick, after create (Sec. 2: the driving luminosity,
+ * boosted in the paper's runs).  kind and params as heat_kind and heat of
+ * ppmb_grid: NONE with nparams 0; LAYER_Z with nparams 3 (Q0, extent, z0:
+ * energy source Q0 h((z - z0) / extent)); BALL with nparams 2 or 3 (Q0,
+ * extent: Q0 h(r / extent); a third value is ignored).  The source is added
+ * after the last pass of each step.  Synchronises the stream and drops a
+ * captured step graph.  INVALID for an unknown kind, a wrong nparams, a
+ * non-finite parameter or extent <= 0. */
+ppmb_status ppmb_set_heating(ppmb_ctx *ctx, int kind, const double *params, int nparams);
+
 /* Copy the FP64 base fields (rho0, p0; ncell each) to host memory.
  * Synchronising. */
 ppmb_status ppmb_get_base(ppmb_ctx *ctx, double *host_rho0, double *host_p0);
@@ -174,12 +198,34 @@ ppmb_status ppmb_set_conserved(ppmb_ctx *ctx, const double *const host_cons[15])
 
 /* CFL time step dt = cfl * dx / max over fluid cells and axes of |u_d| + c,
  * computed in FP64 from the stored state.  Synchronising.  Errors:
- * NONPHYSICAL if a fluid cell has rho <= 0, p <= 0 or a NaN. */
+ * NONPHYSICAL if a fluid cell has rho <= 0, p <= 0 or a NaN.
+ *
+ * Deferred errors.  The passes and the CFL reductions raise device flags
+ * that the synchronising calls ppmb_compute_dt, ppmb_last_dt,
+ * ppmb_brick_last_dt, ppmb_reduce_totals, ppmb_brick_totals,
+ * ppmb_counters and ppmb_synchronize read (after finishing their own work,
+ * so that their outputs are filled) and clear: NONPHYSICAL when a step
+ * produced or started from a fluid cell with rho <= 0, p <= 0 or a NaN
+ * (ppmb_step_auto keeps stepping on such a state until one of these calls),
+ * CFL when the Courant check of ppmb_set_cfl_check failed. */
 ppmb_status ppmb_compute_dt(ppmb_ctx *ctx, double cfl, double *dt_out);
 
 /* One step of size dt: three 1-D passes, x,y,z on even steps and z,y,x on
  * odd steps, then the heating source.  Asynchronous. */
 ppmb_status ppmb_step(ppmb_ctx *ctx, double dt);
+
+/* Courant check of caller-given time steps (a failure detector for
+ * ppmb_step and ppmb_pass; ppmb_step_auto takes its dt from the CFL
+ * condition and is not checked).  With courant_max > 0, each ppmb_step and
+ * ppmb_pass first reduces, on the device and in FP64, the largest signal
+ * speed s = max over fluid cells and axes of |u_d| + c of the state it
+ * starts from, and raises the CFL flag when dt > courant_max * dx / s; the
+ * step is still taken, and the next synchronising call returns
+ * PPMB_ERR_CFL (the caller restores a checkpoint and retries with a
+ * smaller dt).  courant_max = 0 switches the check off.  The default is off,
+ * or 1.0 when the environment variable PPMB_CHECK_CFL is 1 at create.
+ * Asynchronous; INVALID for courant_max < 0 or not finite. */
+ppmb_status ppmb_set_cfl_check(ppmb_ctx *ctx, double courant_max);
 
 /* `nsteps` steps, each taking dt from the CFL condition of the state at its
  * start, computed on the device: no host synchronisation.  The dt of the
@@ -285,6 +331,7 @@ ppmb_status ppmb_spin_add(ppmb_ctx *ctx, double domega);
  * [1, 1024], dr <= 0 or not finite, a bad brick index or unbound state;
  * NOMEM if the workspace cannot be allocated. */
 ppmb_status ppmb_shell_profile(ppmb_ctx *ctx, int brick, int nbins, double dr, double *host_out);
+
 
 /* Event counters since create: { fv limiter activations that changed a
  * profile by more than round-off, unsmooth (cell, variable) pairs

@@ -72,6 +72,8 @@ def lib():
         L.or_set_dissipation.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.or_divergence.argtypes = [ctypes.c_void_p, _D]
         L.or_set_flattening.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.or_set_gravity.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
+        L.or_set_heating.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
         L.or_flattening.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
         L.or_set_spinup.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_long]
         L.or_shell_profile.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _D]
@@ -207,6 +209,16 @@ class Oracle:
         out = np.empty(self.params.shape)
         lib().or_flattening(self.h, int(axis), out.ctypes.data_as(_D))
         return out
+
+    def set_gravity(self, kind: int, params=()):
+        g = np.zeros(4)
+        g[:len(params)] = params
+        lib().or_set_gravity(self.h, int(kind), g.ctypes.data_as(_D))
+
+    def set_heating(self, kind: int, params=()):
+        q = np.zeros(3)
+        q[:len(params)] = params
+        lib().or_set_heating(self.h, int(kind), q.ctypes.data_as(_D))
 
     def spin_add(self, domega: float):
         lib().or_spin_add(self.h, domega)

@@ -1298,6 +1298,22 @@ static void compute_flattening(or_sim *S, int d)
 
 void or_set_flattening(void *h, int on) { ((or_sim *)h)->flat_on = on ? 1 : 0; }
 
+/* Gravity and heating changed during a run (Sec. 3 gravity, Sec. 2 heating):
+   the parameters of the following passes; the base state is kept as it is. */
+void or_set_gravity(void *h, int kind, const double g[4])
+{
+    or_sim *S = (or_sim *)h;
+    S->P.grav_kind = kind;
+    for (int q = 0; q < 4; ++q) S->P.grav[q] = g[q];
+}
+
+void or_set_heating(void *h, int kind, const double q3[3])
+{
+    or_sim *S = (or_sim *)h;
+    S->P.heat_kind = kind;
+    for (int q = 0; q < 3; ++q) S->P.heat[q] = q3[q];
+}
+
 /* the flattening coefficients of the current state for a pass along d */
 void or_flattening(void *h, int d, double *out)
 {

@@ -10,6 +10,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -33,7 +34,7 @@ struct ppmb_ctx {
     double *table = nullptr;            // base-state RK4 nodes (reused brick by brick)
     long table_len = 0;
     double *dt = nullptr;               // per-brick dt
-    unsigned long long *cnt = nullptr;  // [0..2] event counters
+    unsigned long long *cnt = nullptr;  // [0..2] event counters, [3] Courant-check flag
     unsigned long long *work = nullptr; // per brick: smax bits, non-physical flag
     unsigned long long *cband = nullptr; // per brick: band edge of the fused CFL reduction, redo flag
     double *partials = nullptr;         // totals block partials
@@ -67,6 +68,7 @@ struct ppmb_ctx {
     size_t shell_ws_bytes = 0;
     double dissk = 0.0;                 // shock dissipation coefficient (0: off)
     void *divbuf = nullptr;             // its divergence field (one field per brick)
+    double courant_max = 0.0;           // Courant check of caller-given dt (0: off)
     bool flat_on = false;               // flattening near strong shocks
     void *flatbuf = nullptr;            // its coefficients for the pass in progress
     std::string err;
@@ -178,6 +180,26 @@ static ppmb_status build_maps(ppmb_ctx *c)
     return PPMB_OK;
 }
 
+// Gravity and heating parameters: kind known, values finite, the radial
+// core radius and taper interval and the heating extent positive.
+static bool gravity_ok(int kind, const double *p)
+{
+    if (kind < PPMB_GRAV_NONE || kind > PPMB_GRAV_RADIAL) return false;
+    const int np = kind == PPMB_GRAV_CONST ? 3 : (kind == PPMB_GRAV_RADIAL ? 4 : 0);
+    for (int q = 0; q < np; ++q)
+        if (!std::isfinite(p[q])) return false;
+    return kind != PPMB_GRAV_RADIAL || (p[1] > 0.0 && p[3] > p[2]);
+}
+
+static bool heating_ok(int kind, const double *p)
+{
+    if (kind < PPMB_HEAT_NONE || kind > PPMB_HEAT_BALL) return false;
+    const int np = kind == PPMB_HEAT_LAYER_Z ? 3 : (kind == PPMB_HEAT_BALL ? 2 : 0);
+    for (int q = 0; q < np; ++q)
+        if (!std::isfinite(p[q])) return false;
+    return kind == PPMB_HEAT_NONE || p[1] > 0.0;
+}
+
 static ppmb_status check_grid(const ppmb_grid *grid)
 {
     if (!grid) return PPMB_ERR_INVALID;
@@ -186,7 +208,7 @@ static ppmb_status check_grid(const ppmb_grid *grid)
         if (grid->bc[d] != PPMB_BC_PERIODIC && grid->bc[d] != PPMB_BC_REFLECT) return PPMB_ERR_INVALID;
     }
     if (!(grid->dx > 0.0) || !(grid->gamma > 1.0)) return PPMB_ERR_INVALID;
-    if (grid->grav_kind < 0 || grid->grav_kind > 2 || grid->heat_kind < 0 || grid->heat_kind > 2)
+    if (!gravity_ok(grid->grav_kind, grid->grav) || !heating_ok(grid->heat_kind, grid->heat))
         return PPMB_ERR_INVALID;
     if (grid->smooth_detect < 0 || grid->smooth_detect > 2) return PPMB_ERR_INVALID;
     if ((long)grid->n[0] * grid->n[1] * grid->n[2] >= (1L << 31)) return PPMB_ERR_INVALID;
@@ -211,6 +233,8 @@ static double solid_threshold(double R)
     return t;
 }
 
+static void source_constants(Geom &g);
+
 static Geom geom_of(const ppmb_grid *grid)
 {
     Geom g{};
@@ -225,7 +249,20 @@ static Geom geom_of(const ppmb_grid *grid)
     g.heat_kind = grid->heat_kind;
     for (int q = 0; q < 3; ++q) g.heat[q] = grid->heat[q];
     g.smooth_detect = grid->smooth_detect;
-    // the pass kernels' gravity and heating constants, once
+    source_constants(g);
+    // pitched storage: rows padded to 64 elements (256-byte aligned in FP32),
+    // fields padded by 17 x 64 elements more, so that corresponding cells of
+    // the 15 fields do not share cache sets
+    g.px = (grid->n[0] + 63) / 64 * 64;
+    g.plane = (long)g.px * grid->n[1];
+    g.fs = (g.plane * grid->n[2] + 63) / 64 * 64 + 17 * 64;
+    return g;
+}
+
+// The pass kernels' gravity and heating constants in both precisions, from
+// grav_kind / grav and heat_kind / heat, once on the host.
+static void source_constants(Geom &g)
+{
     double gc[6] = { 0, 0, 0, 0, 0, 0 };
     if (g.grav_kind == 1) {
         for (int q = 0; q < 3; ++q) gc[q] = g.grav[q];
@@ -240,13 +277,6 @@ static Geom geom_of(const ppmb_grid *grid)
     for (int q = 0; q < 6; ++q) { g.gcd[q] = gc[q]; g.gcf[q] = (float)gc[q]; }
     const double hc[3] = { g.heat[0], g.heat_kind ? 1.0 / g.heat[1] : 0.0, g.heat[2] };
     for (int q = 0; q < 3; ++q) { g.hcd[q] = hc[q]; g.hcf[q] = (float)hc[q]; }
-    // pitched storage: rows padded to 64 elements (256-byte aligned in FP32),
-    // fields padded by 17 x 64 elements more, so that corresponding cells of
-    // the 15 fields do not share cache sets
-    g.px = (grid->n[0] + 63) / 64 * 64;
-    g.plane = (long)g.px * grid->n[1];
-    g.fs = (g.plane * grid->n[2] + 63) / 64 * 64 + 17 * 64;
-    return g;
 }
 
 static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_precision prec,
@@ -277,6 +307,8 @@ static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_preci
     }
     c->total_state = off;
     c->total_base = boff;
+    if (const char *e = getenv("PPMB_CHECK_CFL"))
+        if (e[0] == '1' && e[1] == 0) c->courant_max = 1.0;
     c->table_len = 64 + 2 * maxspan;
     hipError_t e = hipMalloc(&c->db, sizeof(Brick) * nbricks);
     if (e == hipSuccess) e = hipMalloc(&c->base64, sizeof(double) * boff);
@@ -488,11 +520,16 @@ static ppmb_status enqueue_step(ppmb_ctx *c, bool with_cfl, double cfl, bool per
     return PPMB_OK;
 }
 
+// The deferred error flags (synchronising): the per-brick non-physical
+// flags of the CFL reductions and the Courant-check flag.  A raised flag is
+// cleared and reported once.
 static ppmb_status check_flag(ppmb_ctx *c)
 {
     std::vector<unsigned long long> w(2 * c->nb);
+    unsigned long long cf = 0;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(w.data(), c->work, sizeof(unsigned long long) * w.size(), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(&cf, c->cnt + 3, sizeof(unsigned long long), hipMemcpyDeviceToHost));
     bool bad = false;
     for (int b = 0; b < c->nb; ++b) bad = bad || w[2 * b + 1];
     if (bad) {
@@ -501,6 +538,24 @@ static ppmb_status check_flag(ppmb_ctx *c)
         c->cfl_ready = false;
         return fail(c, PPMB_ERR_NONPHYSICAL, "non-positive density or pressure, or NaN, in a fluid cell");
     }
+    if (cf) {
+        HIPCHK(c, launch_zero_u64(c->cnt + 3, 1, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return fail(c, PPMB_ERR_CFL, "a step's dt exceeded the Courant limit of the CFL check");
+    }
+    return PPMB_OK;
+}
+
+// dt of every brick for ppmb_step / ppmb_pass: the given value, after the
+// Courant check when it is on.
+static ppmb_status enqueue_given_dt(ppmb_ctx *c, double dt)
+{
+    if (c->courant_max > 0.0) {
+        TRY(enqueue_cfl(c, c->courant_max, 0, c->nb));
+        HIPCHK(c, launch_cfl_given(c->db, 0, c->nb, dt, c->dt, c->cnt + 3, c->stream));
+        return PPMB_OK;
+    }
+    for (int b = 0; b < c->nb; ++b) HIPCHK(c, launch_set_scalar(c->dt + b, dt, c->stream));
     return PPMB_OK;
 }
 
@@ -514,6 +569,7 @@ const char *ppmb_status_string(ppmb_status s)
     case PPMB_ERR_NOMEM: return "out of device memory";
     case PPMB_ERR_HIP: return "HIP error";
     case PPMB_ERR_NONPHYSICAL: return "non-physical state";
+    case PPMB_ERR_CFL: return "time step above the Courant limit";
     case PPMB_ERR_UNSUPPORTED: return "unsupported";
     }
     return "unknown status";
@@ -825,8 +881,61 @@ ppmb_status ppmb_step(ppmb_ctx *c, double dt)
 {
     if (!c || !(dt > 0) || !std::isfinite(dt)) return PPMB_ERR_INVALID;
     TRY(need_state(c));
-    for (int b = 0; b < c->nb; ++b) HIPCHK(c, launch_set_scalar(c->dt + b, dt, c->stream));
+    TRY(enqueue_given_dt(c, dt));
     return enqueue_step(c, false, 0.0, false);
+}
+
+ppmb_status ppmb_set_cfl_check(ppmb_ctx *c, double courant_max)
+{
+    if (!c || !std::isfinite(courant_max) || courant_max < 0.0) return PPMB_ERR_INVALID;
+    c->courant_max = courant_max;
+    return PPMB_OK;
+}
+
+// Rewrite the device brick table from the host copy (after a change of the
+// source parameters), with no kernel of the stream reading it.
+static ppmb_status upload_bricks(ppmb_ctx *c)
+{
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->db, c->hb.data(), sizeof(Brick) * c->nb, hipMemcpyHostToDevice));
+    free_graph(c);                       // captured steps hold launch arguments of the old table
+    return PPMB_OK;
+}
+
+ppmb_status ppmb_set_gravity(ppmb_ctx *c, int kind, const double *params, int nparams)
+{
+    if (!c) return PPMB_ERR_INVALID;
+    const int need = kind == PPMB_GRAV_CONST ? 3 : (kind == PPMB_GRAV_RADIAL ? 4 : 0);
+    if (kind < PPMB_GRAV_NONE || kind > PPMB_GRAV_RADIAL || nparams != need || (need && !params))
+        return fail(c, PPMB_ERR_INVALID, "set_gravity: unknown kind or wrong parameter count");
+    double p[4] = { 0, 0, 0, 0 };
+    for (int q = 0; q < need; ++q) p[q] = params[q];
+    if (!gravity_ok(kind, p)) return fail(c, PPMB_ERR_INVALID, "set_gravity: bad parameters");
+    for (auto &B : c->hb) {
+        B.g.grav_kind = kind;
+        for (int q = 0; q < 4; ++q) B.g.grav[q] = p[q];
+        source_constants(B.g);
+    }
+    return upload_bricks(c);
+}
+
+ppmb_status ppmb_set_heating(ppmb_ctx *c, int kind, const double *params, int nparams)
+{
+    if (!c) return PPMB_ERR_INVALID;
+    const bool count_ok = kind == PPMB_HEAT_LAYER_Z ? nparams == 3
+                        : (kind == PPMB_HEAT_BALL ? (nparams == 2 || nparams == 3) : nparams == 0);
+    if (kind < PPMB_HEAT_NONE || kind > PPMB_HEAT_BALL || !count_ok || (nparams && !params))
+        return fail(c, PPMB_ERR_INVALID, "set_heating: unknown kind or wrong parameter count");
+    double p[3] = { 0, 0, 0 };
+    for (int q = 0; q < nparams; ++q) p[q] = params[q];
+    if (kind == PPMB_HEAT_BALL) p[2] = 0.0;
+    if (!heating_ok(kind, p)) return fail(c, PPMB_ERR_INVALID, "set_heating: bad parameters");
+    for (auto &B : c->hb) {
+        B.g.heat_kind = kind;
+        for (int q = 0; q < 3; ++q) B.g.heat[q] = p[q];
+        source_constants(B.g);
+    }
+    return upload_bricks(c);
 }
 
 ppmb_status ppmb_step_auto(ppmb_ctx *c, double cfl, int nsteps)
@@ -899,16 +1008,16 @@ ppmb_status ppmb_brick_last_dt(ppmb_ctx *c, int brick, double *dt_out)
     if (brick < 0 || brick >= c->nb) return fail(c, PPMB_ERR_INVALID, "brick index out of range");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(dt_out, c->dt + brick, sizeof(double), hipMemcpyDeviceToHost));
-    return PPMB_OK;
+    return check_flag(c);
 }
 
 ppmb_status ppmb_last_dt(ppmb_ctx *c, double *dt_out) { return ppmb_brick_last_dt(c, 0, dt_out); }
 
 ppmb_status ppmb_pass(ppmb_ctx *c, int axis, double dt, int heat)
 {
-    if (!c || axis < 0 || axis > 2 || !(dt > 0)) return PPMB_ERR_INVALID;
+    if (!c || axis < 0 || axis > 2 || !(dt > 0) || !std::isfinite(dt)) return PPMB_ERR_INVALID;
     TRY(need_state(c));
-    for (int b = 0; b < c->nb; ++b) HIPCHK(c, launch_set_scalar(c->dt + b, dt, c->stream));
+    TRY(enqueue_given_dt(c, dt));
     if (c->dissk > 0.0) TRY(enqueue_divergence(c, 0, c->nb, c->cur));
     TRY(enqueue_pass(c, axis, heat ? (any_heat(c) ? 1 : 0) : 0, 0, c->nb, c->cur));
     c->cur = 1 - c->cur;
@@ -943,7 +1052,7 @@ ppmb_status ppmb_brick_totals(ppmb_ctx *c, int brick, double out[8])
                                        c->base64 + B.boff + B.g.fs, c->partials, c->out8, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(out, c->out8, sizeof(double) * 8, hipMemcpyDeviceToHost));
-    return PPMB_OK;
+    return check_flag(c);
 }
 
 ppmb_status ppmb_reduce_totals(ppmb_ctx *c, double out[8]) { return ppmb_brick_totals(c, 0, out); }
@@ -1031,7 +1140,7 @@ ppmb_status ppmb_counters(ppmb_ctx *c, unsigned long long out[4])
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(out, c->cnt, sizeof(unsigned long long) * 3, hipMemcpyDeviceToHost));
     out[3] = c->steps;
-    return PPMB_OK;
+    return check_flag(c);
 }
 
 ppmb_status ppmb_set_pass_shape(ppmb_ctx *c, int march_waves, int x_waves)
@@ -1171,7 +1280,7 @@ ppmb_status ppmb_synchronize(ppmb_ctx *c)
 {
     if (!c) return PPMB_ERR_INVALID;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return PPMB_OK;
+    return check_flag(c);
 }
 
 }  // extern "C"

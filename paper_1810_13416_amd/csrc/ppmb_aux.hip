@@ -369,6 +369,26 @@ __global__ void cfl_redo_finish_kernel(const Brick *bricks, int b0, int nb, cons
     }
 }
 
+// Courant check of a caller-given dt: dt[dti] holds courant_max dx / smax
+// of the state the step starts from (launch_cfl); raise the flag where the
+// given dt exceeds it, then store the given dt.
+__global__ void cfl_given_kernel(const Brick *bricks, int b0, int nb, double given, double *dt,
+                                 unsigned long long *flag)
+{
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const Brick &B = bricks[b0 + b];
+        if (!(given <= dt[B.dti])) atomicOr(flag, 1ull);
+        dt[B.dti] = given;
+    }
+}
+
+hipError_t launch_cfl_given(const Brick *bricks, int b0, int nb, double given, double *dt,
+                            unsigned long long *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(cfl_given_kernel, dim3(1), dim3(256), 0, st, bricks, b0, nb, given, dt, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_cfl_arm(unsigned long long *work, unsigned long long *cband, int b0, int nb, hipStream_t st)
 {
     hipLaunchKernelGGL(cfl_arm_kernel, dim3(1), dim3(256), 0, st, work, cband, b0, nb);

@@ -130,6 +130,11 @@ constexpr int kTotalsBlocks = 1024;
 // then their dt.  Every launch is a kernel: no host decision, graph-safe.
 constexpr double kCflBand = 1e-4;
 hipError_t launch_cfl_arm(unsigned long long *work, unsigned long long *cband, int b0, int nb, hipStream_t st);
+// Courant check of a caller-given dt for bricks [b0, b0 + nb): with
+// dt[dti] = courant_max dx / smax from launch_cfl, set *flag where
+// given > dt[dti]; then dt[dti] = given.
+hipError_t launch_cfl_given(const Brick *bricks, int b0, int nb, double given, double *dt,
+                            unsigned long long *flag, hipStream_t st);
 template <typename T>
 hipError_t launch_cfl_finish(const Brick *bricks, int b0, int nb, const BlockMap *map, int nblocks,
                              const T *state, const double *base64, unsigned long long *work,

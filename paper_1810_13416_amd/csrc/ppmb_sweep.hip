@@ -55,7 +55,8 @@ struct BatchArgs {
     int cfl;
 };
 
-template <typename T>
+// The band edge in the working precision, rounded down in FP32 so that no
+// cell whose FP64 speed reaches the FP64 edge is judged below it.
 __device__ __forceinline__ float band_edge(double v, float) { return __double2float_rd(v); }
 __device__ __forceinline__ double band_edge(double v, double) { return v; }
 

@@ -32,7 +32,8 @@ EXPORTS = ("ppmb_create", "ppmb_destroy", "ppmb_state_bytes", "ppmb_state_layout
            "ppmb_get_pass_shape", "ppmb_autotune", "ppmb_ppb2d_create", "ppmb_ppb2d_destroy",
            "ppmb_ppb2d_set", "ppmb_ppb2d_get", "ppmb_ppb2d_steps", "ppmb_ppb2d_get_nstep",
            "ppmb_ppb2d_set_nstep", "ppmb_set_spinup", "ppmb_spin_add", "ppmb_shell_profile",
-           "ppmb_set_shock_dissipation", "ppmb_set_flattening")
+           "ppmb_set_shock_dissipation", "ppmb_set_flattening", "ppmb_set_gravity",
+           "ppmb_set_heating", "ppmb_set_cfl_check")
 
 
 class PPMBError(RuntimeError):
@@ -118,6 +119,9 @@ def load():
         "ppmb_shell_profile": [p, i, i, d, _D],
         "ppmb_set_shock_dissipation": [p, d],
         "ppmb_set_flattening": [p, ctypes.c_int],
+        "ppmb_set_gravity": [p, i, _D, i],
+        "ppmb_set_heating": [p, i, _D, i],
+        "ppmb_set_cfl_check": [p, d],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -294,6 +298,24 @@ class Sim:
         """Flattening of the parabolas near strong shocks (CW84 Sec. 4)."""
         self._check(self.L.ppmb_set_flattening(self.h, 1 if on else 0))
 
+    def set_gravity(self, kind: int, params=()):
+        """Gravity of every brick (kind NONE 0, CONST 1 with 3 values,
+        RADIAL 2 with 4 values); the base state is kept."""
+        arr = np.ascontiguousarray(params, dtype=np.float64).reshape(-1)
+        self._check(self.L.ppmb_set_gravity(self.h, int(kind), arr.ctypes.data_as(_D) if arr.size else None,
+                                            int(arr.size)))
+
+    def set_heating(self, kind: int, params=()):
+        """Heating of every brick (kind NONE 0, LAYER_Z 1 with 3 values,
+        BALL 2 with 2 or 3 values)."""
+        arr = np.ascontiguousarray(params, dtype=np.float64).reshape(-1)
+        self._check(self.L.ppmb_set_heating(self.h, int(kind), arr.ctypes.data_as(_D) if arr.size else None,
+                                            int(arr.size)))
+
+    def set_cfl_check(self, courant_max: float):
+        """Courant check of the dt given to step / pass_ (0: off)."""
+        self._check(self.L.ppmb_set_cfl_check(self.h, float(courant_max)))
+
     def set_spinup(self, omega: float, nramp: int):
         """Steps 0 .. nramp-1 each end with a solid-body rotation increment
         omega / nramp about the z axis."""
@@ -428,6 +450,10 @@ class Batch:
     def set_flattening(self, on: bool):
         """Flattening of the parabolas near strong shocks (CW84 Sec. 4)."""
         self._check(self.L.ppmb_set_flattening(self.h, 1 if on else 0))
+
+    set_gravity = Sim.set_gravity
+    set_heating = Sim.set_heating
+    set_cfl_check = Sim.set_cfl_check
 
     def set_spinup(self, omega: float, nramp: int):
         """Steps 0 .. nramp-1 each end with a solid-body rotation increment

@@ -1,0 +1,141 @@
+"""GPU tests of the C-ABI calls that change physics or report deferred
+errors after create: gravity and heating set mid-run (against the oracle
+given the same change), the Courant check of caller-given dt, and the
+non-physical flag raised inside an asynchronous run and reported by the
+next synchronising call."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1810_13416_amd import problems as pr
+
+pytestmark = pytest.mark.gpu
+
+
+def sim(params, prec="fp64"):
+    from paper_1810_13416_amd import ppmb
+    return ppmb.Sim(params, ppmb.FP64 if prec == "fp64" else ppmb.FP32)
+
+
+def rel_l1(a, b, scale):
+    return float(np.sum(np.abs(a - b))) / max(scale, 1e-300)
+
+
+def compare_all(ga, oa, tol):
+    for q in range(15):
+        grp = [5] if q >= 5 else ([1, 2, 3] if q in (1, 2, 3) else [q])
+        s1 = sum(float(np.sum(np.abs(oa[x]))) for x in grp) / len(grp)
+        e = rel_l1(ga[q], oa[q], s1)
+        assert e <= tol, (q, e)
+
+
+@pytest.mark.parametrize("cfg", ["strat", "sphere"])
+def test_gravity_and_heating_changed_mid_run_match_oracle(cfg):
+    # Sec. 3 gravity, Sec. 2 heating: both changed after three steps, on
+    # the library and on the oracle; FP64 parity afterwards
+    prob = pr.config2(n=16) if cfg == "strat" else pr.config3(n=24)
+    O = oracle.Oracle(prob.params, threads=8)
+    O.set_state(prob.state)
+    S = sim(prob.params)
+    S.set_state(prob.state)
+    for _ in range(3):
+        dt = O.dt(prob.cfl)
+        O.step(dt)
+        S.step(dt)
+    if cfg == "strat":
+        g = (0.05, 0.0, -0.5 * abs(prob.params.grav[2]))
+        heat = (1, (0.3, 0.15, 0.05))
+    else:
+        g0, rc, r1, r2 = prob.params.grav
+        g = (0.5 * g0, 2.0 * rc, r1, r2)
+        heat = (2, (0.2, 0.3))
+    kind = 1 if cfg == "strat" else 2
+    S.set_gravity(kind, g)
+    O.set_gravity(kind, g)
+    S.set_heating(heat[0], heat[1])
+    O.set_heating(heat[0], heat[1])
+    for _ in range(3):
+        dt = O.dt(prob.cfl)
+        O.step(dt)
+        S.step(dt)
+    compare_all(S.get_state(), O.get_state(), 1e-12)
+    # gravity switched off: a free, unheated run from here on
+    S.set_gravity(0, ())
+    O.set_gravity(0, ())
+    S.set_heating(0, ())
+    O.set_heating(0, ())
+    for _ in range(2):
+        dt = O.dt(prob.cfl)
+        O.step(dt)
+        S.step(dt)
+    compare_all(S.get_state(), O.get_state(), 1e-12)
+
+
+def test_gravity_and_heating_argument_errors():
+    from paper_1810_13416_amd import ppmb
+    prob = pr.config2(n=8)
+    S = sim(prob.params)
+    bad_gravity = [(3, ()), (1, (0.0, 0.0)), (1, (0.0, 0.0, float("nan"))), (2, (1.0, 0.0, 0.5, 0.9)),
+                   (2, (1.0, 0.1, 0.9, 0.5)), (0, (1.0,))]
+    for kind, params in bad_gravity:
+        with pytest.raises(ppmb.PPMBError, match="-1"):
+            S.set_gravity(kind, params)
+    bad_heating = [(3, ()), (1, (0.1, 0.1)), (1, (0.1, 0.0, 0.0)), (2, (0.1,)), (2, (float("inf"), 0.2))]
+    for kind, params in bad_heating:
+        with pytest.raises(ppmb.PPMBError, match="-1"):
+            S.set_heating(kind, params)
+    with pytest.raises(ppmb.PPMBError, match="-1"):
+        S.set_cfl_check(-1.0)
+
+
+def test_cfl_check_reports_oversized_dt():
+    from paper_1810_13416_amd import ppmb
+    prob = pr.uniform()
+    S = sim(prob.params)
+    S.set_state(prob.state)
+    dt_c = S.dt(1.0)                 # Courant number 1
+    S.set_cfl_check(1.0)
+    S.step(0.8 * dt_c)
+    S.synchronize()                  # within the limit: no error
+    S.step(1.3 * dt_c)
+    with pytest.raises(ppmb.PPMBError, match="-5"):
+        S.synchronize()
+    S.synchronize()                  # reported once, then cleared
+    S.set_cfl_check(0.0)
+    S.step(1.3 * dt_c)               # check off: no report
+    S.synchronize()
+
+
+def test_cfl_check_leaves_the_step_unchanged():
+    # the check only reads the state: the checked run is bitwise the plain one
+    prob = pr.config2(n=16)
+    A = sim(prob.params, "fp32")
+    A.set_state(prob.state)
+    B = sim(prob.params, "fp32")
+    B.set_state(prob.state)
+    B.set_cfl_check(1.0)
+    for _ in range(4):
+        dt = A.dt(prob.cfl)
+        A.step(dt)
+        B.step(dt)
+    B.synchronize()
+    for a, b in zip(A.get_conserved(), B.get_conserved()):
+        assert np.array_equal(a, b)
+
+
+def test_nonphysical_state_is_reported_after_async_steps():
+    from paper_1810_13416_amd import ppmb
+    prob = pr.uniform()
+    st = [a.copy() for a in prob.state]
+    st[4][3, 2, 1] = -1.0            # negative pressure in one cell
+    S = sim(prob.params)
+    S.set_state(st)
+    S.step_auto(0.8, 2)              # asynchronous: no report yet
+    with pytest.raises(ppmb.PPMBError, match="-4"):
+        S.last_dt()
+    # the same through the totals
+    T = sim(prob.params)
+    T.set_state(st)
+    T.step_auto(0.8, 1)
+    with pytest.raises(ppmb.PPMBError, match="-4"):
+        T.totals()

@@ -53,6 +53,20 @@ def test_status_strings_without_gpu():
     L.ppmb_status_string.argtypes = [ctypes.c_int]
     assert L.ppmb_status_string(0) == b"ok"
     assert L.ppmb_status_string(-4) == b"non-physical state"
+    assert L.ppmb_status_string(-5) == b"time step above the Courant limit"
+
+
+def test_setters_reject_a_null_context_without_gpu():
+    # argument errors are reported at once, before any HIP call
+    L = ctypes.CDLL(_lib_path())
+    D = ctypes.POINTER(ctypes.c_double)
+    L.ppmb_set_gravity.argtypes = [ctypes.c_void_p, ctypes.c_int, D, ctypes.c_int]
+    L.ppmb_set_heating.argtypes = [ctypes.c_void_p, ctypes.c_int, D, ctypes.c_int]
+    L.ppmb_set_cfl_check.argtypes = [ctypes.c_void_p, ctypes.c_double]
+    g = (ctypes.c_double * 4)(0.0, 0.0, -1.0, 0.0)
+    assert L.ppmb_set_gravity(None, 1, g, 3) == -1
+    assert L.ppmb_set_heating(None, 1, g, 3) == -1
+    assert L.ppmb_set_cfl_check(None, 1.0) == -1
 
 
 def test_grid_struct_layout_matches_header():
