@@ -332,6 +332,21 @@ ppmb_status ppmb_spin_add(ppmb_ctx *ctx, double domega);
  * NOMEM if the workspace cannot be allocated. */
 ppmb_status ppmb_shell_profile(ppmb_ctx *ctx, int brick, int nbins, double dr, double *host_out);
 
+/* The same shell sums for callers that cannot allocate device memory (code
+ * under HIP-graph capture, tight serving loops, hosts that forbid
+ * allocation): no hipMalloc, hipFree or allocating library call.  The
+ * block partials live in a static device workspace of 4 Mi doubles
+ * (32 MiB) that every GPU the library runs on holds from its first context
+ * until the process ends.  dev_out: caller-owned device memory of
+ * 8 * nbins doubles, the same layout and bitwise the same values as
+ * ppmb_shell_profile's host_out.  Asynchronous (the result is in dev_out
+ * once the context's stream reaches it).  All calls on one GPU share the
+ * one workspace: calls that overlap on one GPU (two streams, two threads)
+ * race and must be ordered by the caller.  INVALID as for
+ * ppmb_shell_profile, a NULL dev_out, or a grid whose block partials
+ * (8 * nbins * (blocks + groups) doubles; at most 4161 * 8 * nbins for
+ * large grids) exceed the workspace. */
+ppmb_status ppmb_shell_profile_noalloc(ppmb_ctx *ctx, int brick, int nbins, double dr, double *dev_out);
 
 /* Event counters since create: { fv limiter activations that changed a
  * profile by more than round-off, unsmooth (cell, variable) pairs

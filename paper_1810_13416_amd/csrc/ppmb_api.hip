@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -69,6 +70,8 @@ struct ppmb_ctx {
     double dissk = 0.0;                 // shock dissipation coefficient (0: off)
     void *divbuf = nullptr;             // its divergence field (one field per brick)
     double courant_max = 0.0;           // Courant check of caller-given dt (0: off)
+    int device = 0;                     // the device current at create
+    double *noalloc_ws = nullptr;       // that device's copy of the static shell workspace
     bool flat_on = false;               // flattening near strong shocks
     void *flatbuf = nullptr;            // its coefficients for the pass in progress
     std::string err;
@@ -279,6 +282,36 @@ static void source_constants(Geom &g)
     for (int q = 0; q < 3; ++q) { g.hcd[q] = hc[q]; g.hcf[q] = (float)hc[q]; }
 }
 
+// Static workspace of ppmb_shell_profile_noalloc: a file-scope device array,
+// one copy per GPU the library runs on, held until the process ends.  Host
+// code never names it directly (the host-side symbol is not a device
+// address): its device address is looked up once per device, at create,
+// and kept below.
+constexpr long kShellStaticDoubles = 4L << 20;          // 32 MiB
+static __device__ __align__(256) double scratch[kShellStaticDoubles];
+constexpr int kMaxDevices = 64;
+static std::mutex scratch_mu;
+static double *scratch_ptr[kMaxDevices] = {};
+
+// The static workspace's address on the current device (looked up once).
+static hipError_t scratch_of_current_device(int *device, double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *device = dev;
+    *out = scratch_ptr[dev];
+    return hipSuccess;
+}
+
 static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_precision prec,
                                  void *hip_stream, bool own_state, ppmb_ctx **out)
 {
@@ -310,7 +343,12 @@ static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_preci
     if (const char *e = getenv("PPMB_CHECK_CFL"))
         if (e[0] == '1' && e[1] == 0) c->courant_max = 1.0;
     c->table_len = 64 + 2 * maxspan;
-    hipError_t e = hipMalloc(&c->db, sizeof(Brick) * nbricks);
+    hipError_t e = scratch_of_current_device(&c->device, &c->noalloc_ws);
+    if (e != hipSuccess) {
+        delete c;
+        return PPMB_ERR_HIP;
+    }
+    e = hipMalloc(&c->db, sizeof(Brick) * nbricks);
     if (e == hipSuccess) e = hipMalloc(&c->base64, sizeof(double) * boff);
     if (e == hipSuccess) e = hipMemset(c->base64, 0, sizeof(double) * boff);   // padding included
     if (e == hipSuccess && prec == PPMB_FP32) e = hipMalloc(&c->baseT, sizeof(float) * boff);
@@ -1131,6 +1169,29 @@ ppmb_status ppmb_shell_profile(ppmb_ctx *c, int brick, int nbins, double dr, dou
                                       c->shell_ws, res, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(out, res, sizeof(double) * 8 * nbins, hipMemcpyDeviceToHost));
+    return PPMB_OK;
+}
+
+ppmb_status ppmb_shell_profile_noalloc(ppmb_ctx *c, int brick, int nbins, double dr, double *dev_out)
+{
+    if (!c || !dev_out || nbins < 1 || nbins > kShellMaxBins || !(dr > 0) || !std::isfinite(dr))
+        return PPMB_ERR_INVALID;
+    if (!((double)nbins * dr < 1e300)) return PPMB_ERR_INVALID;
+    TRY(check_brick(c, brick));
+    const Brick &B = c->hb[brick];
+    const long nwork = shell_work_doubles(B.g, nbins);
+    if (nwork > kShellStaticDoubles)
+        return fail(c, PPMB_ERR_INVALID, "shell_profile_noalloc: block partials of " + std::to_string(nwork) +
+                                             " doubles exceed the static workspace of " +
+                                             std::to_string(kShellStaticDoubles));
+    // every element of the workspace the kernels read is written first by
+    // the same call: nothing to clear
+    if (c->prec == PPMB_FP64)
+        HIPCHK(c, launch_shell<double>(B.g, arena<double>(c, c->cur) + B.off, c->base64 + B.boff, nbins, dr,
+                                       c->noalloc_ws, dev_out, c->stream));
+    else
+        HIPCHK(c, launch_shell<float>(B.g, arena<float>(c, c->cur) + B.off, c->base64 + B.boff, nbins, dr,
+                                      c->noalloc_ws, dev_out, c->stream));
     return PPMB_OK;
 }
 

@@ -33,7 +33,7 @@ EXPORTS = ("ppmb_create", "ppmb_destroy", "ppmb_state_bytes", "ppmb_state_layout
            "ppmb_ppb2d_set", "ppmb_ppb2d_get", "ppmb_ppb2d_steps", "ppmb_ppb2d_get_nstep",
            "ppmb_ppb2d_set_nstep", "ppmb_set_spinup", "ppmb_spin_add", "ppmb_shell_profile",
            "ppmb_set_shock_dissipation", "ppmb_set_flattening", "ppmb_set_gravity",
-           "ppmb_set_heating", "ppmb_set_cfl_check")
+           "ppmb_set_heating", "ppmb_set_cfl_check", "ppmb_shell_profile_noalloc")
 
 
 class PPMBError(RuntimeError):
@@ -122,6 +122,7 @@ def load():
         "ppmb_set_gravity": [p, i, _D, i],
         "ppmb_set_heating": [p, i, _D, i],
         "ppmb_set_cfl_check": [p, d],
+        "ppmb_shell_profile_noalloc": [p, i, i, d, p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -331,6 +332,12 @@ class Sim:
         self._check(self.L.ppmb_shell_profile(self.h, int(brick), int(nbins), float(dr),
                                               out.ctypes.data_as(_D)))
         return out
+
+    def shell_profile_noalloc(self, out, nbins: int, dr: float, brick: int = 0):
+        """Shell sums into `out`, a device tensor of nbins * 8 float64, with no
+        allocation by the library (static workspace); asynchronous."""
+        self._check(self.L.ppmb_shell_profile_noalloc(self.h, int(brick), int(nbins), float(dr),
+                                                      ctypes.c_void_p(out.data_ptr())))
 
     def profile(self, enable=True):
         self._check(self.L.ppmb_profile_enable(self.h, 1 if enable else 0))
