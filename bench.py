@@ -94,10 +94,15 @@ def run_rotation(sim, n, reps=5):
                               "fluid_volume_over_4pi_3": vol / (4.0 * math.pi / 3.0)}}
 
 
-def run_gpu(prob, precision, steps, warmup, dev_prims, rotation=False, dissk=0.0, flat=False):
+TILING = (0, 1)        # cells per wave along a pencil (0: whole), x rows per wave
+
+
+def run_gpu(prob, precision, steps, warmup, dev_prims, rotation=False, dissk=0.0, flat=False, skip=True):
     import torch
     from paper_1810_13416_amd import ppmb
     sim = ppmb.Sim(prob.params, precision, device="cuda:0")
+    sim.set_solid_skip(skip)
+    sim.set_tiling(*TILING)
     sim.set_state_device(dev_prims)
     if dissk > 0.0:
         sim.set_shock_dissipation(dissk)
@@ -107,20 +112,28 @@ def run_gpu(prob, precision, steps, warmup, dev_prims, rotation=False, dissk=0.0
     sim.step_auto(prob.cfl, warmup)
     torch.cuda.synchronize()
     sim.profile(True)
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # the timed steps in up to 5 blocks of equal length, each bracketed by
+    # events on the library's stream; ms per step is the median block's
+    nblk = max(1, min(5, steps))
+    sizes = [steps // nblk + (1 if b < steps % nblk else 0) for b in range(nblk)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nblk + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record()
-    sim.step_auto(prob.cfl, steps)
-    stop.record()
+    ev[0].record(sim.stream)
+    for b, k in enumerate(sizes):
+        sim.step_auto(prob.cfl, k)
+        ev[b + 1].record(sim.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sim.profile(False)
     counts, ms = sim.profile_read()
-    ms_step = start.elapsed_time(stop) / steps
+    per_block = [ev[b].elapsed_time(ev[b + 1]) / k for b, k in enumerate(sizes)]
+    ms_step = float(sorted(per_block)[len(per_block) // 2]) if nblk % 2 else \
+        0.5 * sum(sorted(per_block)[nblk // 2 - 1: nblk // 2 + 1])
     tot = sim.totals()
     cnt = sim.counters()
-    info = {"ms_per_step": ms_step, "wall_ms_per_step": 1e3 * wall / steps,
+    info = {"ms_per_step": ms_step, "ms_per_step_blocks": per_block,
+            "ms_per_step_mean": ev[0].elapsed_time(ev[-1]) / steps, "wall_ms_per_step": 1e3 * wall / steps,
             "pass_ms": {ax: (ms[i] / counts[i] if counts[i] else None) for i, ax in enumerate("xyz")},
             "totals": [float(v) for v in tot], "counters": cnt, "dt_last": sim.last_dt()}
     if rotation:
@@ -311,12 +324,10 @@ def run_ppb2d():
     return out
 
 
-def cpu_baseline(n=256, steps=8):
-    import numpy as np  # noqa: F401
+def _oracle_rate(n, steps, threads):
     import oracle
     from paper_1810_13416_amd import problems
     prob = problems.config3(n=n)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
     O = oracle.Oracle(prob.params, threads=threads)
     O.set_state(prob.state)
     del prob.state
@@ -324,14 +335,41 @@ def cpu_baseline(n=256, steps=8):
     for _ in range(steps):
         O.step(O.dt(0.8))
     dt = time.perf_counter() - t0
-    cells = n ** 3 * steps
     O.close()
-    return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle, same shell recipe at {n}^3, {steps} step(s), {dt:.1f} s",
-            "seconds": dt}
+    return n ** 3 * steps / dt, dt
+
+
+def cpu_baseline(n=512, steps=2, n1=128, steps1=2):
+    """The FP64 oracle on the host cores: the benchmark's own grid for a
+    few steps with every core, and a smaller grid of the same recipe on
+    one thread."""
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    rate, dt = _oracle_rate(n, steps, threads)
+    log(f"oracle {n}^3 x {steps} on {threads} threads: {dt:.1f} s")
+    rate1, dt1 = _oracle_rate(n1, steps1, 1)
+    log(f"oracle {n1}^3 x {steps1} on 1 thread: {dt1:.1f} s")
+    return {"value": rate, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle, the same shell at {n}^3, {steps} step(s), {dt:.1f} s on {threads} threads",
+            "seconds": dt,
+            "single_thread": {"value": rate1, "unit": "cell-updates/s", "cores": 1,
+                              "sample": f"FP64 oracle, the same recipe at {n1}^3, {steps1} step(s), {dt1:.1f} s"}}
+
+
+def fluid_cell_count(params):
+    """Cells whose centre lies inside the confining sphere, by the library's
+    test: (x^2 + y^2) + z^2 below the square of the radius (radius 1 here,
+    whose square and correctly rounded square root are exact)."""
+    import numpy as np
+    if not params.sphere:
+        return int(np.prod(params.n))
+    assert params.sphere_r == 1.0
+    c = [params.origin[a] + (np.arange(params.n[a]) + 0.5) * params.dx for a in range(3)]
+    xy = (c[0][None, :] * c[0][None, :]) + (c[1][:, None] * c[1][:, None])
+    return int(sum(int(np.count_nonzero(xy + z * z < 1.0)) for z in c[2]))
 
 
 def main():
+    global TILING
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -343,6 +381,10 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-ppb2d", action="store_true")
     ap.add_argument("--no-rotation", action="store_true")
+    ap.add_argument("--tiling", type=str, default=None,
+                    help="march_chunk,x_rows of the pass kernels (default: %s,%s)" % TILING)
+    ap.add_argument("--compare-skip", action="store_true",
+                    help="also time the FP32 step with every pass writing every cell")
     ap.add_argument("--calib-copy-mib", type=int, default=0)
     ap.add_argument("--dissipation", type=float, default=0.1,
                     help="coefficient of the extra FP32 runs with shock handling (0: skip them)")
@@ -356,6 +398,8 @@ def main():
     import torch
     from paper_1810_13416_amd import ppmb, problems
 
+    if args.tiling:
+        TILING = tuple(int(v) for v in args.tiling.split(","))
     if args.calib_copy_mib:
         calib_copy(args.calib_copy_mib)
     log(f"generating the {args.n}^3 shell inputs")
@@ -370,6 +414,11 @@ def main():
     log("FP32 run")
     r32 = run_gpu(prob, ppmb.FP32, args.steps, args.warmup, dev, rotation=not args.no_rotation)
     log(f"FP32: {r32['ms_per_step']:.3f} ms/step, passes {r32['pass_ms']}")
+    rall = None
+    if args.compare_skip:
+        log("FP32 run, every pass writing every cell")
+        rall = run_gpu(prob, ppmb.FP32, args.steps, args.warmup, dev, skip=False)
+        log(f"FP32 all cells: {rall['ms_per_step']:.3f} ms/step, passes {rall['pass_ms']}")
     rdiss = rflat = None
     if args.dissipation > 0.0:
         log(f"FP32 run with shock dissipation K = {args.dissipation}")
@@ -388,7 +437,12 @@ def main():
     torch.cuda.empty_cache()
 
     value = cells / (r32["ms_per_step"] * 1e-3)
-    bytes_per_launch = 2 * N_FIELDS * 4 * cells
+    fluid = fluid_cell_count(prob.params)
+    # algorithmic bytes of a pass: the 15 fields read and written once for
+    # every cell it updates, the fluid cells (solid cells keep their values
+    # and are not moved); ghost reads, base fields and the solid cells near
+    # the fluid that a pass does touch are traffic, not algorithmic bytes
+    bytes_per_launch = 2 * N_FIELDS * 4 * fluid
     kernels = {}
     for ax, ms in r32["pass_ms"].items():
         if ms:
@@ -425,6 +479,12 @@ def main():
                      "traffic_source": os.path.relpath(TRAFFIC_SUMMARY, ROOT) if traffic else None},
         "hbm_roofline_cell_updates_per_s": HBM_PEAK_GBS * 1e9 / (3 * 2 * N_FIELDS * 4),
         "fraction_of_hbm_roofline": value / (HBM_PEAK_GBS * 1e9 / (3 * 2 * N_FIELDS * 4)),
+        "fluid": {"cells": fluid, "cell_updates_per_s": fluid / (r32["ms_per_step"] * 1e-3),
+                  "fraction_of_hbm_roofline": fluid / (r32["ms_per_step"] * 1e-3) /
+                  (HBM_PEAK_GBS * 1e9 / (3 * 2 * N_FIELDS * 4)),
+                  "note": "the cells the method updates; value counts every cell of the grid, "
+                          "solid cells (kept, and skipped by the passes beyond the stencil reach) included"},
+        "ms_per_step_blocks": r32["ms_per_step_blocks"], "ms_per_step_mean": r32["ms_per_step_mean"],
         "counters": r32["counters"],
     }
     valu = measured_valu()
@@ -444,6 +504,9 @@ def main():
         out["rotation"] = r32["rotation"]
         log(f"spin-up increment {r32['rotation']['spin_add']['ms']:.3f} ms, shell sums "
             f"{r32['rotation']['shell_profile']['ms']:.3f} ms")
+    if rall:
+        out["without_solid_skip"] = {"ms_per_step": rall["ms_per_step"], "pass_ms": rall["pass_ms"],
+                                     "speedup_of_skip": rall["ms_per_step"] / r32["ms_per_step"]}
     if rdiss:
         out["shock_dissipation"] = {"k": args.dissipation, "value": cells / (rdiss["ms_per_step"] * 1e-3),
                                     "unit": "cell-updates/s", "ms_per_step": rdiss["ms_per_step"],

@@ -214,6 +214,20 @@ ppmb_status ppmb_compute_dt(ppmb_ctx *ctx, double cfl, double *dt_out);
  * odd steps, then the heating source.  Asynchronous. */
 ppmb_status ppmb_step(ppmb_ctx *ctx, double dt);
 
+/* Solid cells of the confining sphere (Sec. 3) keep their values, so the
+ * passes leave out those farther than the stencil reach (4 cells) from a
+ * fluid cell: a wave of pencils marches over the union of its pencils'
+ * fluid intervals (plus 4 cells either side, read only), the x pass visits
+ * only the 56-cell segments from the row's first fluid cell to its last.
+ * This needs the solid cells to hold the same values in both state
+ * buffers: the first pass after a state change by the library (set_state,
+ * set_conserved, bind_state, set_base_state) writes every cell, and later
+ * passes skip.  A caller that writes a bound buffer directly calls
+ * ppmb_bind_state again.  on = 0 makes every pass write every cell (the
+ * results are bitwise the same either way); on = 1 is the default.
+ * Drops a captured step graph.  INVALID for a null context. */
+ppmb_status ppmb_set_solid_skip(ppmb_ctx *ctx, int on);
+
 /* Courant check of caller-given time steps (a failure detector for
  * ppmb_step and ppmb_pass; ppmb_step_auto takes its dt from the CFL
  * condition and is not checked).  With courant_max > 0, each ppmb_step and
@@ -393,6 +407,16 @@ ppmb_status ppmb_batch_step(ppmb_ctx *ctx, double cfl, int nsteps, int mode);
  * Changes no result bit.  Synchronising. */
 ppmb_status ppmb_set_pass_shape(ppmb_ctx *ctx, int march_waves, int x_waves);
 ppmb_status ppmb_get_pass_shape(const ppmb_ctx *ctx, int *march_waves, int *x_waves);
+
+/* Work per wave of the pass kernels: the marching kernel (y and z passes)
+ * cuts each pencil into chunks of march_chunk cells, one wave per chunk
+ * (0: one wave marches the whole pencil; else at least 16), and the x pass
+ * gives each wave at least x_rows x-rows (1..64).  Shorter chunks and
+ * more rows even out the waves' work when solid cells are skipped; every
+ * wave reads 4 cells beyond its chunk either side.  Changes no result bit.
+ * Synchronising.  The default is chunk 0, 1 row. */
+ppmb_status ppmb_set_pass_tiling(ppmb_ctx *ctx, int march_chunk, int x_rows);
+ppmb_status ppmb_get_pass_tiling(const ppmb_ctx *ctx, int *march_chunk, int *x_rows);
 
 /* Autotuner: times every launch shape (waves per block 1, 2, 4 for each of
  * the two pass kernels) on this context's bricks, `reps` passes per axis

@@ -744,7 +744,9 @@ static void pencil_update(pencil *pc, double dt, double dx, double gamma, int de
                 constrain_parabola(Q[q][J], &lc, &rc);
                 if (ws > 0.0) { lc = lc + ws * (l - lc); rc = rc + ws * (r - rc); }
                 l = lc; r = rc;
-                if (J >= NG && J < NG + n) pc->unsmooth++;
+                /* counted in the fluid cells of the pencil (a solid cell
+                   is not part of the flow, Sec. 3, and keeps its state) */
+                if (J >= NG && J < NG + n && !pc->solid[J]) pc->unsmooth++;
             }
             if (pc->flat_on) {
                 /* flattening (CW84 Sec. 4) of the final edge values toward

@@ -40,7 +40,7 @@ struct ppmb_ctx {
     unsigned long long *cband = nullptr; // per brick: band edge of the fused CFL reduction, redo flag
     double *partials = nullptr;         // totals block partials
     double *out8 = nullptr;             // totals result
-    PassShape shape{ 1, 4 };
+    PassShape shape{ 1, 4, 0, 1 };
     BlockMap *pmap[3] = { nullptr, nullptr, nullptr };   // per pass axis
     std::vector<int> pfirst[3];         // first block of each brick (+ total at the end)
     BlockMap *cmap = nullptr;           // CFL reduction
@@ -72,6 +72,10 @@ struct ppmb_ctx {
     double courant_max = 0.0;           // Courant check of caller-given dt (0: off)
     int device = 0;                     // the device current at create
     double *noalloc_ws = nullptr;       // that device's copy of the static shell workspace
+    // per brick: both arenas hold the same values in the solid cells (true
+    // after a pass that wrote every cell), so passes may skip them
+    std::vector<char> solid_same;
+    bool skip_on = true;                // ppmb_set_solid_skip
     bool flat_on = false;               // flattening near strong shocks
     void *flatbuf = nullptr;            // its coefficients for the pass in progress
     std::string err;
@@ -111,6 +115,22 @@ static void free_graph(ppmb_ctx *c)
     c->gexec = nullptr;
     c->graph = nullptr;
     c->gkey_cur = c->gkey_par = -1;
+}
+
+// The state of bricks [b0, b1) was written by something other than a
+// pass: the next pass writes every cell again (a captured step graph
+// holds passes that skip solid cells, so it goes too).
+static void solid_reset(ppmb_ctx *c, int b0, int b1)
+{
+    for (int b = b0; b < b1; ++b) c->solid_same[b] = 0;
+    free_graph(c);
+}
+
+static bool solid_all_same(const ppmb_ctx *c, int b0, int b1)
+{
+    for (int b = b0; b < b1; ++b)
+        if (!c->solid_same[b]) return false;
+    return true;
 }
 
 static void free_maps(ppmb_ctx *c)
@@ -340,6 +360,7 @@ static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_preci
     }
     c->total_state = off;
     c->total_base = boff;
+    c->solid_same.assign(nbricks, 0);
     if (const char *e = getenv("PPMB_CHECK_CFL"))
         if (e[0] == '1' && e[1] == 0) c->courant_max = 1.0;
     c->table_len = 64 + 2 * maxspan;
@@ -444,18 +465,22 @@ static ppmb_status enqueue_pass(ppmb_ctx *c, int axis, int heat, int b0, int b1,
         HIPCHK(c, hipEventRecord(tm.a, c->stream));
     }
     hipError_t e;
+    const int skip = c->skip_on && solid_all_same(c, b0, b1) ? 1 : 0;
     if (c->prec == PPMB_FP64)
         e = launch_sweep<double>(axis, c->shape, c->db, c->pmap[axis] + f0, f1 - f0, arena<double>(c, from),
                                  arena<double>(c, 1 - from), c->base64, c->dt, c->cnt, heat, c->base64,
                                  c->work, c->cband, static_cast<const double *>(c->divbuf), c->dissk,
-                                 c->flat_on ? static_cast<const double *>(c->flatbuf) : nullptr, cfl, c->stream);
+                                 c->flat_on ? static_cast<const double *>(c->flatbuf) : nullptr, cfl, skip,
+                                 c->stream);
     else
         e = launch_sweep<float>(axis, c->shape, c->db, c->pmap[axis] + f0, f1 - f0, arena<float>(c, from),
                                 arena<float>(c, 1 - from), static_cast<const float *>(c->baseT), c->dt,
                                 c->cnt, heat, c->base64, c->work, c->cband, static_cast<const float *>(c->divbuf),
                                 c->dissk, c->flat_on ? static_cast<const float *>(c->flatbuf) : nullptr, cfl,
-                                c->stream);
+                                skip, c->stream);
     if (e != hipSuccess) return hipfail(c, e, "sweep launch");
+    // a pass that wrote every cell copied the solid ones unchanged
+    for (int b = b0; b < b1; ++b) c->solid_same[b] = 1;
     if (c->profiling) {
         HIPCHK(c, hipEventRecord(tm.b, c->stream));
         c->timed.push_back(tm);
@@ -680,6 +705,7 @@ ppmb_status ppmb_bind_state(ppmb_ctx *c, void *a, void *b)
     c->buf[1] = b;
     c->cur = 0;
     c->cfl_ready = false;
+    solid_reset(c, 0, c->nb);
     return PPMB_OK;
 }
 
@@ -697,6 +723,7 @@ ppmb_status ppmb_brick_set_base_state(ppmb_ctx *c, int brick, int kind, const do
     const Brick &B = c->hb[brick];
     if (kind < 0 || kind > 3) return fail(c, PPMB_ERR_INVALID, "set_base_state: unknown kind");
     c->cfl_ready = false;
+    solid_reset(c, brick, brick + 1);
     if (kind != PPMB_BASE_NONE && !params) return fail(c, PPMB_ERR_INVALID, "set_base_state: params required");
     if (kind == PPMB_BASE_POLY_Z && B.g.grav_kind != PPMB_GRAV_CONST)
         return fail(c, PPMB_ERR_INVALID, "POLY_Z needs constant gravity");
@@ -768,6 +795,7 @@ static ppmb_status set_state_dev(ppmb_ctx *c, int brick, const double *const dev
 {
     TRY(check_brick(c, brick));
     c->cfl_ready = false;
+    solid_reset(c, brick, brick + 1);
     const Brick &B = c->hb[brick];
     for (int q = 0; q < NF; ++q)
         if (!dev_prim[q]) return fail(c, PPMB_ERR_INVALID, "set_state: null field");
@@ -793,6 +821,7 @@ ppmb_status ppmb_brick_set_state(ppmb_ctx *c, int brick, const double *const hos
     if (!c || !host_prim) return PPMB_ERR_INVALID;
     TRY(check_brick(c, brick));
     c->cfl_ready = false;
+    solid_reset(c, brick, brick + 1);
     for (int q = 0; q < NF; ++q)
         if (!host_prim[q]) return fail(c, PPMB_ERR_INVALID, "set_state: null field");
     const Brick &B = c->hb[brick];
@@ -887,6 +916,7 @@ ppmb_status ppmb_set_conserved(ppmb_ctx *c, const double *const host_cons[15])
     if (!c || !host_cons) return PPMB_ERR_INVALID;
     TRY(check_brick(c, 0));
     c->cfl_ready = false;
+    solid_reset(c, 0, 1);
     const Brick &B = c->hb[0];
     const long n = B.ncell;
     Staging st;
@@ -921,6 +951,14 @@ ppmb_status ppmb_step(ppmb_ctx *c, double dt)
     TRY(need_state(c));
     TRY(enqueue_given_dt(c, dt));
     return enqueue_step(c, false, 0.0, false);
+}
+
+ppmb_status ppmb_set_solid_skip(ppmb_ctx *c, int on)
+{
+    if (!c) return PPMB_ERR_INVALID;
+    c->skip_on = on != 0;
+    free_graph(c);                       // captured passes hold the previous setting
+    return PPMB_OK;
 }
 
 ppmb_status ppmb_set_cfl_check(ppmb_ctx *c, double courant_max)
@@ -989,8 +1027,10 @@ ppmb_status ppmb_step_auto(ppmb_ctx *c, double cfl, int nsteps)
 // from the captured ones.  Steps inside a spin-up ramp are never captured.
 static ppmb_status graph_steps(ppmb_ctx *c, double cfl, int nsteps)
 {
-    // steps of a spin-up ramp differ from one another: launched directly
-    for (; nsteps > 0 && c->nstep < c->spin_nramp; --nsteps) TRY(enqueue_step(c, true, cfl, false));
+    // steps of a spin-up ramp differ from one another, and the first step
+    // after a state change writes every cell: launched directly
+    for (; nsteps > 0 && (c->nstep < c->spin_nramp || !solid_all_same(c, 0, c->nb)); --nsteps)
+        TRY(enqueue_step(c, true, cfl, false));
     int pairs = nsteps / 2;
     if (pairs > 0) {
         // the captured steps take dt from the maxima in work[]: make them
@@ -1210,8 +1250,28 @@ ppmb_status ppmb_set_pass_shape(ppmb_ctx *c, int march_waves, int x_waves)
     auto ok = [](int w) { return w == 1 || w == 2 || w == 4; };
     if (!ok(march_waves) || !ok(x_waves)) return fail(c, PPMB_ERR_INVALID, "pass shape: waves per block must be 1, 2 or 4");
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->shape = PassShape{ march_waves, x_waves };
+    c->shape.march_waves = march_waves;
+    c->shape.x_waves = x_waves;
     return build_maps(c);
+}
+
+ppmb_status ppmb_set_pass_tiling(ppmb_ctx *c, int march_chunk, int x_rows)
+{
+    if (!c) return PPMB_ERR_INVALID;
+    if (march_chunk < 0 || (march_chunk > 0 && march_chunk < 16) || x_rows < 1 || x_rows > 64)
+        return fail(c, PPMB_ERR_INVALID, "pass tiling: chunk 0 or >= 16 cells, 1..64 rows per wave");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->shape.march_chunk = march_chunk;
+    c->shape.x_rows = x_rows;
+    return build_maps(c);
+}
+
+ppmb_status ppmb_get_pass_tiling(const ppmb_ctx *c, int *march_chunk, int *x_rows)
+{
+    if (!c || !march_chunk || !x_rows) return PPMB_ERR_INVALID;
+    *march_chunk = c->shape.march_chunk;
+    *x_rows = c->shape.x_rows;
+    return PPMB_OK;
 }
 
 ppmb_status ppmb_get_pass_shape(const ppmb_ctx *c, int *march_waves, int *x_waves)

@@ -98,7 +98,9 @@ __device__ __forceinline__ int bc_source(int j, int n, int bc, int &flip)
 // Cell-centre coordinate (FP64).
 __device__ __forceinline__ double centre(const Geom &g, int axis, int i)
 {
-    return g.origin[axis] + ((double)i + 0.5) * g.dx;
+    // rounded product, then rounded sum, in every unit whatever its
+    // contraction setting: the same number as on the host
+    return __dadd_rn(g.origin[axis], __dmul_rn((double)i + 0.5, g.dx));
 }
 
 // |x|^2 evaluated without contraction so that the solid test agrees

@@ -33,6 +33,8 @@ struct BlockMap {
 struct PassShape {
     int march_waves;
     int x_waves;
+    int march_chunk;      // cells per wave along the pencil (0: the whole pencil)
+    int x_rows;           // x pass: at least this many rows per wave
 };
 
 // Number of blocks the pass along `axis` needs for one brick.
@@ -50,12 +52,17 @@ int pass_blocks(const Geom &g, int axis, const PassShape &sh);
 // cells from `div` (launch_divergence of the pass input or of the state at
 // the start of the step).  With `flat` (launch_flattening of the pass input
 // along `axis`) every parabola is flattened by its cell's coefficient.
+// With `skip` (solid cells hold the same values in `in` and `out`) the
+// pass neither loads nor writes solid cells farther than the stencil reach
+// from a fluid cell: a wave of pencils marches over the union of their
+// fluid intervals, the x pass visits only the 56-cell segments holding
+// fluid cells.
 template <typename T>
 hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, const BlockMap *map,
                         int nblocks, const T *in, T *out, const T *base, const double *dt,
                         unsigned long long *counters, int heat, const double *base64,
                         unsigned long long *work, const unsigned long long *cband, const T *div, double dissk,
-                        const T *flat, int cfl, hipStream_t st);
+                        const T *flat, int cfl, int skip, hipStream_t st);
 
 // Undivided velocity divergence of every cell of the bricks whose blocks
 // are map[0 .. nblocks) (div_blocks(g) blocks per brick; FP64 arithmetic,

@@ -33,6 +33,7 @@ struct SweepArgs {
     const T *div;         // undivided velocity divergence (shock dissipation), same layout
     T dissk;              // shock dissipation coefficient
     const T *flat;        // flattening coefficients of this pass's input, same layout
+    int skip;             // 1: solid cells hold the same values in both arenas; passes skip them
 };
 
 // Arguments of one pass launch over a batch of bricks.
@@ -53,7 +54,23 @@ struct BatchArgs {
     const T *flat;                // flattening field, one per brick at boff / 2 (FLAT only)
     int heat;
     int cfl;
+    int skip;                     // solid cells are the same in both arenas: not written
+    int chunk;                    // marching kernel: cells per wave along the pencil (0: all)
+    int x_rows;                   // x pass: at least this many rows per wave
 };
+
+// A value that is the same on every lane, kept in scalar registers.
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
 
 // The band edge in the working precision, rounded down in FP32 so that no
 // cell whose FP64 speed reaches the FP64 edge is judged below it.
@@ -63,11 +80,12 @@ __device__ __forceinline__ double band_edge(double v, double) { return v; }
 template <typename T>
 __device__ __forceinline__ SweepArgs<T> brick_args(const BatchArgs<T> &b, const Brick &B, int brick)
 {
-    const T thr = b.cfl ? band_edge(__longlong_as_double((long long)b.cband[2 * brick]), T(0)) : T(0);
+    // the same on every lane: kept in a scalar register
+    const T thr = wave_uniform(b.cfl ? band_edge(__longlong_as_double((long long)b.cband[2 * brick]), T(0)) : T(0));
     return SweepArgs<T>{b.in + B.off, b.out + B.off, b.base + B.boff, b.base + B.boff + B.g.fs,
                         b.dt + B.dti, b.counters, b.base64 + B.boff, b.base64 + B.boff + B.g.fs,
                         B.g.fs, b.heat, b.cfl, thr, b.div ? b.div + B.boff / 2 : nullptr, T(b.dissk),
-                        b.flat ? b.flat + B.boff / 2 : nullptr};
+                        b.flat ? b.flat + B.boff / 2 : nullptr, b.skip};
 }
 
 // Global (x, y, z) order of a pass's (normal, t1, t2) components.
@@ -94,11 +112,6 @@ __device__ __forceinline__ void cfl_commit(unsigned long long *work, int brick, 
         if (bb) atomicOr(&work[2 * brick + 1], 1ull);
     }
 }
-
-template <bool B>
-struct Phase {
-    static constexpr bool value = B;
-};
 
 // Range-checked raw buffer access (gfx9 buffer resource, no stride): an
 // element index at or past the resource's count reads zero and writes
@@ -195,19 +208,6 @@ __device__ __forceinline__ double fresh(double v)
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// A value that is the same on every lane, kept in scalar registers.
-__device__ __forceinline__ float wave_uniform(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ double wave_uniform(double v)
-{
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
-    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-
 // pass-local order of the 10 fv coefficients and which flip at a wall
 __host__ __device__ constexpr int mixed_of(int a, int b) { return FXY + (4 - a - b) % 3; }
 
@@ -248,7 +248,8 @@ __device__ __forceinline__ void cons_of(const T *q, T rho, T rgm1, T *u)
 
 template <typename T, int AX, bool DISS, bool FLAT>
 __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, int la0, int lane, int lb, int pk,
-                      int nb, unsigned &c_lim, unsigned &c_uns, unsigned &c_rie, double &cmax, bool &cbad)
+                      int nb, int clo, int chi, unsigned &c_lim, unsigned &c_uns, unsigned &c_rie, double &cmax,
+                      bool &cbad)
 {
     using AI = AxisInfo<AX>;
     const int n = g.n[AX];
@@ -290,6 +291,25 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
     int flo, fhi;
     fluid_interval(g, AX, xt, flo, fhi);
     const T ox = T(g.origin[AX]), dxT = T(g.dx);
+    // The cells the wave updates: [wlo, whi], its chunk [clo, chi] of the
+    // pencils, narrowed when solid cells are skipped (they keep their
+    // values, which both arenas hold alike) to the union of the pencils'
+    // fluid cells in the chunk.  The march reads 4 cells beyond it on
+    // either side (real cells, solid ones included, or ghosts through the
+    // boundary conditions) and writes only inside it.
+    int wlo = clo, whi = chi;
+    if (a.skip) {
+        const int fl = max(flo, clo), fh = min(fhi, chi);
+        int l = fl <= fh ? fl : n, h = fl <= fh ? fh : -1;
+        for (int off = 1; off < 64; off <<= 1) {
+            l = min(l, __shfl_xor(l, off));
+            h = max(h, __shfl_xor(h, off));
+        }
+        wlo = __builtin_amdgcn_readfirstlane(l);
+        whi = __builtin_amdgcn_readfirstlane(h);
+        if (wlo > whi) return;             // every pencil of the wave is solid
+    }
+    const int k0 = wlo - NG;               // first cell loaded
 
     const double dt64 = *a.dtp;
     const T dt = T(dt64), nu = T(dt64 / g.dx), hdt = T(0.5 * dt64), rdx = T(1.0 / g.dx);
@@ -347,19 +367,46 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
         nx_s = s;
         nx_fl = fl;
     };
-    load_next(-NG);
+    load_next(k0);
     // settle the first loads here, so that the loop's own wait for the next
     // cell's inputs only counts memory operations issued after them
     __builtin_amdgcn_s_waitcnt(0);
+    {
+        // The window starts filled with the first cell's state, so that the
+        // first steps, whose results are not stored (an update reads only
+        // cells within 4 of its own), compute on physical values.
+        const T flT = T(nx_fl);
+        const T rho = nx_r0 + nx_rp, ir = trcp(rho);
+        const T mn = flT * nx_mn;
+        const T u = mn * ir, v = nx_m1 * ir, w = nx_m2 * ir;
+        const T pp = gm1 * (nx_ep - T(0.5) * (mn * u + nx_m1 * v + nx_m2 * w));
+        const T c = tsqrt(gam * (nx_pb + pp) * ir);
+        const T pv[5] = { nx_rp, u, v, w, pp };
+#pragma unroll
+        for (int vv = 0; vv < 5; ++vv) {
+#pragma unroll
+            for (int r = 0; r < 5; ++r) q[r][vv] = pv[vv];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) { qf[r][vv] = pv[vv]; flm[r][vv] = pv[vv]; }
+#pragma unroll
+            for (int r = 0; r < 3; ++r) { sm[r][vv] = T(0); d2[r][vv] = T(0); }
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r) { rr[r] = rho; cr[r] = c; }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) { b0[r] = nx_r0; b1[r] = nx_pb; }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) { r0f[r] = nx_r0; p0f[r] = nx_pb; }
+        TLp = St<T>{nx_rp, u, v, w, pp};
+    }
 
-    // One step of the march.  The steady steps (every stage active, every
-    // cell of the step inside the pencil) are a loop of their own with the
-    // range tests compiled out, so that every memory operation is issued on
-    // every step and the compiler's waits count exactly the operations
-    // issued after the one waited for; the few steps at either end of the
-    // pencil run the general form.
-    auto step = [&](const int k, auto phase) {
-        constexpr bool S = decltype(phase)::value;
+    // One step of the march.  Every step runs every stage with the same
+    // arithmetic (so a cell's result does not depend on where its wave's
+    // range begins or ends); only the stores and the event counts are
+    // switched off outside the range, by index, so that every memory
+    // operation is issued on every step and the compiler's waits count
+    // exactly the operations issued after the one waited for.
+    auto step = [&](const int k) {
         // ---- (1) cell k from the prefetched inputs (base added back, Sec. 1);
         //          loads of cell k+1 and of the conserved fields of cell k-3
         //          (cache hits, for its update) are issued first
@@ -368,34 +415,33 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
         const T rp = fresh(nx_rp), mn = flT * nx_mn, m1 = fresh(nx_m1), m2 = fresh(nx_m2), ep = fresh(nx_ep);
         const T r0 = fresh(nx_r0), pb = fresh(nx_pb);
         const int cu_ = k - 3;
-        const bool upd = S || (cu_ >= 0 && cu_ < n);
-        // cell k-3 for its update; outside the pencil the loads and the
-        // stores below are switched off by index (one clamped row address)
-        const int c3 = upd ? cu_ : 0;
-        const unsigned ld3 = upd ? lix : kNoIdx;
+        const bool upd = cu_ >= wlo && cu_ <= whi;
+        // cell k-3 (through the boundary conditions outside the pencil,
+        // where the wall flip of the normal momentum is applied below):
+        // its conserved fields for its update, its fv coefficients (donors
+        // -1..n) for the PPB stage, loaded raw; no arithmetic waits on these
+        // loads before they are used
+        int pq_fl = 1;
+        int s3 = cu_;
+        if (s3 < 0 || s3 >= n) s3 = bc_source(cu_, n, bc, pq_fl);
         const unsigned st3 = upd ? lst : kNoIdx;
         T cu3[5];
-        cu3[0] = bld<T>(rin(RHO, c3), ld3);
-        cu3[1] = bld<T>(rin(MX + AX, c3), ld3);
-        cu3[2] = bld<T>(rin(MX + AI::t1, c3), ld3);
-        cu3[3] = bld<T>(rin(MX + AI::t2, c3), ld3);
-        cu3[4] = bld<T>(rin(EN, c3), ld3);
+        cu3[0] = bld<T>(rin(RHO, s3), lix);
+        cu3[1] = bld<T>(rin(MX + AX, s3), lix);
+        cu3[2] = bld<T>(rin(MX + AI::t1, s3), lix);
+        cu3[3] = bld<T>(rin(MX + AI::t2, s3), lix);
+        cu3[4] = bld<T>(rin(EN, s3), lix);
         if constexpr (DISS || FLAT) {
-            // divergence of cell k-2 for the face (k-3)+1/2 (used from k = 1
-            // on; that of cell k-3 is carried from the previous step) and
-            // the flattening coefficient of cell k-2 for its parabola
-            int s2 = k - 2;
-            unsigned l2 = lix;
-            if (!S) {
-                int f2;
-                if (k < 0) { s2 = 0; l2 = kNoIdx; }
-                else if (s2 < 0 || s2 >= n) s2 = bc_source(s2, n, bc, f2);
-            }
+            // divergence of cell k-2 for the face (k-3)+1/2 (that of cell
+            // k-3 is carried from the previous step) and the flattening
+            // coefficient of cell k-2 for its parabola
+            int s2 = k - 2, f2;
+            if (s2 < 0 || s2 >= n) s2 = bc_source(s2, n, bc, f2);
             if constexpr (DISS) {
                 dvp = dvc;
-                dvc = bld<T>(rsrc(a.div + ubase + s2 * sAX, rcnt), l2);
+                dvc = bld<T>(rsrc(a.div + ubase + s2 * sAX, rcnt), lix);
             }
-            if constexpr (FLAT) fk = bld<T>(rsrc(a.flat + ubase + s2 * sAX, rcnt), l2);
+            if constexpr (FLAT) fk = bld<T>(rsrc(a.flat + ubase + s2 * sAX, rcnt), lix);
         }
         {
             T xd = ox + (T(s) + T(0.5)) * dxT;
@@ -426,18 +472,10 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
         // (and a wait on the loads) at the end of every step.
         __builtin_amdgcn_sched_barrier(0);
         load_next(k + 1);
-        // fv coefficients of cell k-3 (donors -1..n), loaded raw; the wall
-        // flip of the odd ones is applied where they are used, so that no
-        // arithmetic waits on these loads before then
-        int pq_fl = 1;
-        {
-            int s3 = k - 3;
-            if (!S && (s3 < 0 || s3 >= n)) s3 = bc_source(k - 3, n, bc, pq_fl);
 #pragma unroll
-            for (int v = 0; v < 10; ++v) pq[v] = bld<T>(rin(AI::ppb(v), s3), lix);
-        }
+        for (int v = 0; v < 10; ++v) pq[v] = bld<T>(rin(AI::ppb(v), s3), lix);
         // ---- (2) interface values at face (k-2)+1/2 (cells k-3..k)
-        if (S || k >= -1) {
+        {
 #pragma unroll
             for (int vv = 0; vv < 5; ++vv) { qf[0][vv] = qf[1][vv]; qf[1][vv] = face4(q[1][vv], q[2][vv], q[3][vv], q[4][vv]); }
             r0f[0] = r0f[1]; r0f[1] = face4(b0[0], b0[1], b0[2], b0[3]);
@@ -445,7 +483,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
         }
         // ---- (3) limited slope and second difference of cell k-1; the
         //          limited-slope face value at (k-2)+1/2
-        if (S || k >= -2) {
+        {
 #pragma unroll
             for (int vv = 0; vv < 5; ++vv) {
                 sm[0][vv] = sm[1][vv]; sm[1][vv] = sm[2][vv];
@@ -456,13 +494,13 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
                 flm[1][vv] = face_limited(q[2][vv], q[3][vv], sm[1][vv], sm[2][vv]);
             }
         }
-        if (!S && k < 0) return;
         // ---- (4) parabolas of cell k-2, constrained only where the 5-cell
         //          window is not smooth (Sec. 1), blended over the graded
         //          band; tracing (CW84 Sec. 3)
         St<T> TL, TR;
         {
-            const bool interior = S || ((k - 2 >= 0) && (k - 2 < n));
+            // unsmooth pairs are counted in the fluid cells the wave updates
+            const bool interior = (k - 2 >= wlo) && (k - 2 <= whi) && !sol[2];
             T qL[5], qR[5], dq[5], q6[5];
 #pragma unroll
             for (int vv = 0; vv < 5; ++vv) {
@@ -483,32 +521,31 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
                        p0f[1], nu, hdt, rdx, TL, TR);
         }
         // ---- (5) Riemann problem and fluxes at face (k-3)+1/2
-        T F[5] = { T(0), T(0), T(0), T(0), T(0) };
-        T sg = T(0);
-        if (S || k >= 1) {
+        T F[5];
+        T sg;
+        {
             bool rie = face_flux<T>(TLp, TR, sol[1], sol[2], r0f[0], p0f[0], gam, gfac, nu, F, sg);
-            if (rie && (S || (k - 3 >= -1 && k - 3 < n)) && valid) ++c_rie;
+            if (rie && (k - 3 >= wlo - 1) && (k - 3 <= whi) && valid) ++c_rie;
             if constexpr (DISS) {
                 // shock dissipation across a face between fluid cells: the
-                // conserved fields of cell k-3 as loaded for its update (in
-                // the steady steps, where it lies inside the pencil), else,
-                // and for cell k-2, rebuilt from the primitives
+                // conserved fields of cell k-3 as loaded for its update, and
+                // those of cell k-2 rebuilt from its primitives
                 const T nv = (sol[1] || sol[2]) ? T(0) : a.dissk * tmax(T(0), T(-0.5) * (dvp + dvc));
-                T ua[5], ub[5];
-                if constexpr (S) {
-#pragma unroll
-                    for (int vv = 0; vv < 5; ++vv) ua[vv] = cu3[vv];
-                } else {
-                    cons_of(q[1], b0[0] + q[1][0], rgm1, ua);
-                }
+                T ub[5];
                 cons_of(q[2], rr[0], rgm1, ub);
+                if (pq_fl < 0) cu3[1] = -cu3[1];     // seen through a reflecting wall
 #pragma unroll
-                for (int vv = 0; vv < 5; ++vv) F[vv] = F[vv] + nv * (ua[vv] - ub[vv]);
+                for (int vv = 0; vv < 5; ++vv) F[vv] = F[vv] + nv * (cu3[vv] - ub[vv]);
             }
         }
         TLp = TL;
         // ---- (6) conservative update of cell k-3 and heating; written now
         {
+            // (outside the pencil the update is not stored; DISS has flipped
+            // the ghost's normal momentum already)
+            if constexpr (!DISS) {
+                if (pq_fl < 0) cu3[1] = -cu3[1];
+            }
             T hn[5];
             hydro_update(cu3, Fp, F, nu, dt, gr[0], hn);
             if (a.heat) {
@@ -524,11 +561,11 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
             }
 #pragma unroll
             for (int vv = 0; vv < 5; ++vv) hn[vv] = sol[1] ? cu3[vv] : hn[vv];
-            bst(rout(RHO, c3), st3, hn[0]);
-            bst(rout(MX + AX, c3), st3, hn[1]);
-            bst(rout(MX + AI::t1, c3), st3, hn[2]);
-            bst(rout(MX + AI::t2, c3), st3, hn[3]);
-            bst(rout(EN, c3), st3, hn[4]);
+            bst(rout(RHO, s3), st3, hn[0]);
+            bst(rout(MX + AX, s3), st3, hn[1]);
+            bst(rout(MX + AI::t1, s3), st3, hn[2]);
+            bst(rout(MX + AI::t2, s3), st3, hn[3]);
+            bst(rout(EN, s3), st3, hn[4]);
             // the next step's CFL reduction from the values just written:
             // the exact FP64 speed only where the bound reaches the band
             // below the last maximum (in few waves), with its FP64 base
@@ -536,9 +573,9 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
                 const bool need = upd && valid && !sol[1] &&
                                   speed_may_reach(b0[0], b1[0], hn[0], hn[1], hn[2], hn[3], hn[4], gam, gm1, a.cthr);
                 if (__ballot(need)) {
-                    const unsigned ic = need ? ld3 : kNoIdx;
-                    const double br0 = bld<double>(rsrc(a.r064 + ubase + c3 * sAX, rcnt), ic);
-                    const double bp0 = bld<double>(rsrc(a.p064 + ubase + c3 * sAX, rcnt), ic);
+                    const unsigned ic = need ? lix : kNoIdx;
+                    const double br0 = bld<double>(rsrc(a.r064 + ubase + s3 * sAX, rcnt), ic);
+                    const double bp0 = bld<double>(rsrc(a.p064 + ubase + s3 * sAX, rcnt), ic);
                     if (need) {
                         double mx, my, mz;
                         to_global<AX, double>(hn[1], hn[2], hn[3], mx, my, mz);
@@ -551,21 +588,21 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
             }
         }
         // ---- (7) PPB: donor k-3, slab at face (k-4)+1/2, update cell k-4
-        if (S || k >= 2) {
-            if (!S && pq_fl < 0) {
+        {
+            if (pq_fl < 0) {
 #pragma unroll
                 for (int v = 0; v < 10; ++v) pq[v] = AI::odd(v) ? -pq[v] : pq[v];
             }
             T Ld = T(1) + (sg - sg1);
             T l1 = pq[1], l2 = pq[2];
             bool hit = fv_limit(pq[0], l1, l2);
-            if (hit && (S || (k - 3 >= 0 && k - 3 < n)) && !sol[1] && valid) ++c_lim;
+            if (hit && upd && !sol[1] && valid) ++c_lim;
             T pql[10];
 #pragma unroll
             for (int v = 0; v < 10; ++v) pql[v] = pq[v];
             pql[1] = l1; pql[2] = l2;
             T G[10];
-            if (S || k >= 3) {
+            {
                 // donor: cell k-4 when the face velocity is positive, else
                 // cell k-3 seen mirrored (odd-in-s coefficients flipped); a
                 // zero velocity gives a zero slab
@@ -578,8 +615,8 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
                 }
                 slab(dn, sg1, pos ? Lp : Ld, G);
                 const int cw = k - 4;
-                const bool wr = S || (cw >= 0 && cw < n);
-                const int cwc = wr ? cw : 0;
+                const bool wr = cw >= wlo && cw <= whi;
+                const int cwc = wr ? cw : wlo;
                 const unsigned stw = wr ? lst : kNoIdx;
                 T o[10];
                 ppb_update(pqp, sg1 - sg2, T(0.5) * (sg2 + sg1), Gp, G, o);
@@ -602,14 +639,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
 #pragma unroll
         for (int vv = 0; vv < 5; ++vv) Fp[vv] = F[vv];
     };
-    for (int k = -NG; k < n + NG; ++k) {
-        if (k == NG && NG <= n + 1) {
-            __builtin_amdgcn_s_waitcnt(0);
-            for (; k <= n + 1; ++k) step(k, Phase<true>{});
-            __builtin_amdgcn_s_waitcnt(0);
-        }
-        step(k, Phase<false>{});
-    }
+    for (int k = k0; k <= whi + NG; ++k) step(k);
 }
 
 // Marching kernel: each wave covers 64 pencils (lanes across x for the y
@@ -621,6 +651,14 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
 __host__ __device__ inline int march_pack(const Geom &g, int axis)
 {
     return (axis != 0 && g.n[0] <= 32) ? 64 / g.n[0] : 1;
+}
+
+// Waves of the marching kernel along a pencil of n cells: chunks of
+// `chunk` cells (0: one wave for the whole pencil).  Each wave marches its
+// chunk plus 4 cells either side.
+__host__ __device__ inline int march_chunks(int n, int chunk)
+{
+    return chunk > 0 ? (n + chunk - 1) / chunk : 1;
 }
 
 template <typename T, int AX, bool DISS, bool FLAT>
@@ -637,14 +675,19 @@ void sweep_kernel(BatchArgs<T> b)
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int nblk_a = (g.n[ca] + 63) / 64;
     const int pk = march_pack(g, AX);
-    const int la0 = (m.local % nblk_a) * 64;
-    const int lb = ((m.local / nblk_a) * waves + wv) * pk;
+    // block = (chunk along the pencils, column of 64 pencils, rows)
+    const int nchk = march_chunks(g.n[AX], b.chunk);
+    const int ck = m.local % nchk, rest = m.local / nchk;
+    const int la0 = (rest % nblk_a) * 64;
+    const int lb = ((rest / nblk_a) * waves + wv) * pk;
+    const int clen = b.chunk > 0 ? b.chunk : g.n[AX];
+    const int clo = ck * clen, chi = min(clo + clen, g.n[AX]) - 1;
     unsigned c_lim = 0, c_uns = 0, c_rie = 0;          // per lane; widened below
     double cmax = 0.0;
     bool cbad = false;
     if (lb < g.n[cb])
-        march<T, AX, DISS, FLAT>(g, &B.g, a, la0, (int)(threadIdx.x & 63), lb, pk, min(pk, g.n[cb] - lb), c_lim,
-                                 c_uns, c_rie, cmax, cbad);
+        march<T, AX, DISS, FLAT>(g, &B.g, a, la0, (int)(threadIdx.x & 63), lb, pk, min(pk, g.n[cb] - lb), clo, chi,
+                                 c_lim, c_uns, c_rie, cmax, cbad);
     if (b.cfl) cfl_commit(b.work, m.brick, cmax, cbad);
     // event counters: one atomic per wave and counter
     unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
@@ -673,10 +716,11 @@ void sweep_kernel(BatchArgs<T> b)
 constexpr int kXOut = 56;
 constexpr int kXItems = 8;     // (row, segment) items per wave, at least
 
-// Items per wave: whole rows, at least kXItems items.
-__host__ __device__ __forceinline__ int x_run(int nseg)
+// Items per wave: whole rows, at least kXItems items and min_rows rows.
+__host__ __device__ __forceinline__ int x_run(int nseg, int min_rows)
 {
-    const int rows = kXItems / nseg;
+    int rows = kXItems / nseg;
+    rows = rows > min_rows ? rows : min_rows;
     return (rows > 1 ? rows : 1) * nseg;
 }
 
@@ -775,7 +819,7 @@ void sweep_x_kernel(BatchArgs<T> b)
     // order, segments along the row
     const int nseg = (nx + kXOut - 1) / kXOut;
     const int items = ny * nz * nseg;
-    const int run = x_run(nseg);
+    const int run = x_run(nseg, b.x_rows);
     const int wv = m.local * (int)(blockDim.x >> 6) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int it0 = wv * run;                          // whole rows: it0 is a row start
     if (it0 >= items) return;                          // whole waves only
@@ -790,24 +834,51 @@ void sweep_x_kernel(BatchArgs<T> b)
     double cmax = 0.0;                                 // fused CFL reduction
     bool cbad = false;
 
-    // storage offset of an item's row and its first lane's cell
-    auto item_row = [&](int it) { return (long)(it / nseg) * g.px; };
-    auto item_i0 = [&](int it) { return (it % nseg) * kXOut - NG; };
+    // The work on row r: ns segments of 56 output cells from cell x0.
+    // With solid cells skipped (both arenas hold them alike) the segments
+    // start at the row's first fluid cell and end at or past its last (none
+    // for an all-solid row); else they tile the whole row from 0.
+    auto row_work = [&](int r, int &x0, int &ns) {
+        x0 = 0;
+        ns = nseg;
+        if (!a.skip || !g.sphere) return;
+        const double xt[3] = { 0.0, centre(g, 1, r % ny), centre(g, 2, r / ny) };
+        int flo, fhi;
+        fluid_interval(g, 0, xt, flo, fhi);
+        x0 = __builtin_amdgcn_readfirstlane(flo);
+        ns = __builtin_amdgcn_readfirstlane(flo <= fhi ? (fhi - flo) / kXOut + 1 : 0);
+    };
+    // the first row from r on (below rend) with work, and that work
+    const int rend = (it1 + nseg - 1) / nseg;
+    auto next_row = [&](int r, int &x0, int &ns) {
+        for (; r < rend; ++r) {
+            row_work(r, x0, ns);
+            if (ns > 0) break;
+        }
+        return r;
+    };
 
+    int rowi, rx0, rns;
+    rowi = next_row(it0 / nseg, rx0, rns);
     XIn<T> cur;
-    x_load<T, DISS, FLAT>(a.in, a.rho0, a.p0, a.div, a.flat, nc, item_row(it0), nx, bc, item_i0(it0) + lane, cur);
+    if (rowi < rend)
+        x_load<T, DISS, FLAT>(a.in, a.rho0, a.p0, a.div, a.flat, nc, (long)rowi * g.px, nx, bc, rx0 - NG + lane,
+                              cur);
     // settle the first loads, so that the loop's waits count only the
     // memory operations of the loop itself
     __builtin_amdgcn_s_waitcnt(0);
-    for (int rowi = it0 / nseg; rowi * nseg < it1; ++rowi) {
+    while (rowi < rend) {
       const int y = rowi % ny, z = rowi / ny;
       const long row = (long)rowi * g.px;
       const double yc = centre(g, 1, y), zc = centre(g, 2, z);
       const T xt1 = T(yc), xt2 = T(zc);
       const T rtt = xt1 * xt1 + xt2 * xt2;
-      for (int seg = 0; seg < nseg; ++seg) {
-        const int it = rowi * nseg + seg;
-        const int i = seg * kXOut - NG + lane;         // this lane's cell along x
+      // the row after this one with work (its loads start at this row's
+      // last segment)
+      int nx0 = 0, nns = 0;
+      const int nrow = next_row(rowi + 1, nx0, nns);
+      for (int seg = 0; seg < rns; ++seg) {
+        const int i = rx0 + seg * kXOut - NG + lane;   // this lane's cell along x
 
         // (1) this lane's cell: its inputs are taken over as new values,
         //     then the next segment's loads go into the same registers
@@ -829,9 +900,12 @@ void sweep_x_kernel(BatchArgs<T> b)
         if constexpr (FLAT) fk = fresh(cur.fv);
         __builtin_amdgcn_sched_barrier(0);
         {
-            const int nit = it + 1 < it1 ? it + 1 : it;       // past the run: reload, unused
-            x_load<T, DISS, FLAT>(a.in, a.rho0, a.p0, a.div, a.flat, nc, item_row(nit), nx, bc, item_i0(nit) + lane,
-                                  cur);
+            // the next item: this row's next segment, else the next row's
+            // first; past the run this one again (loaded, unused)
+            const bool more = seg + 1 < rns;
+            const int ni = more ? rx0 + (seg + 1) * kXOut : (nrow < rend ? nx0 : rx0 + seg * kXOut);
+            const long nr = more ? row : (nrow < rend ? (long)nrow * g.px : row);
+            x_load<T, DISS, FLAT>(a.in, a.rho0, a.p0, a.div, a.flat, nc, nr, nx, bc, ni - NG + lane, cur);
         }
         const T xd = ox + (T(s) + T(0.5)) * dxT;
         const T gv = fl * gravity_now<T>(&B.g, 0, xd, rtt + xd * xd);
@@ -877,7 +951,7 @@ void sweep_x_kernel(BatchArgs<T> b)
             bool con = parabola(g.smooth_detect, q[vv], from_left(qf[vv]), qf[vv],
                                 from_left(flm[vv]), flm[vv], from_left(d2[vv]), d2[vv],
                                 from_right(d2[vv]), l, r);
-            if (con && own) ++c_uns;
+            if (con && own && !so) ++c_uns;
             if constexpr (FLAT) {
                 l = fk * q[vv] + (T(1) - fk) * l;
                 r = fk * q[vv] + (T(1) - fk) * r;
@@ -985,6 +1059,9 @@ void sweep_x_kernel(BatchArgs<T> b)
             }
         }
       }
+      rowi = nrow;
+      rx0 = nx0;
+      rns = nns;
     }
     if (a.cfl) cfl_commit(b.work, m.brick, cmax, cbad);
     unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
@@ -1013,14 +1090,15 @@ int pass_blocks(const Geom &g, int axis, const PassShape &sh)
     if (axis == 0 && x_lanes_enabled()) {
         const int nseg = (g.n[0] + kXOut - 1) / kXOut;
         const long items = (long)g.n[1] * g.n[2] * nseg;
-        const long nw = (items + x_run(nseg) - 1) / x_run(nseg);   // whole rows per wave
+        const long nw = (items + x_run(nseg, sh.x_rows) - 1) / x_run(nseg, sh.x_rows);   // whole rows per wave
         return (int)((nw + sh.x_waves - 1) / sh.x_waves);
     }
     const int ca = (axis == 0) ? 1 : 0;
     const int cb = 3 - axis - ca;
     const int pk = march_pack(g, axis);
     const int rows = (g.n[cb] + pk - 1) / pk;          // waves per column of 64 pencils
-    return ((g.n[ca] + 63) / 64) * ((rows + sh.march_waves - 1) / sh.march_waves);
+    return march_chunks(g.n[axis], sh.march_chunk) * ((g.n[ca] + 63) / 64) *
+           ((rows + sh.march_waves - 1) / sh.march_waves);
 }
 
 template <typename T, bool D, bool F>
@@ -1044,12 +1122,12 @@ hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, cons
                         int nblocks, const T *in, T *out, const T *base, const double *dt,
                         unsigned long long *counters, int heat, const double *base64,
                         unsigned long long *work, const unsigned long long *cband, const T *div, double dissk,
-                        const T *flat, int cfl, hipStream_t st)
+                        const T *flat, int cfl, int skip, hipStream_t st)
 {
     if (nblocks <= 0) return hipErrorInvalidValue;
     const bool diss = dissk > 0.0 && div;
     BatchArgs<T> a{bricks, map, in, out, base, dt, counters, base64, work, cband, diss ? div : nullptr,
-                   dissk, flat, heat, cfl};
+                   dissk, flat, heat, cfl, skip, sh.march_chunk, sh.x_rows};
     const bool xl = axis == 0 && x_lanes_enabled();
     if (diss && flat) launch_pass_kernel<T, true, true>(axis, xl, nblocks, sh, st, a);
     else if (diss) launch_pass_kernel<T, true, false>(axis, xl, nblocks, sh, st, a);
@@ -1062,11 +1140,11 @@ template hipError_t launch_sweep<float>(int, const PassShape &, const Brick *, c
                                         const float *, float *, const float *, const double *,
                                         unsigned long long *, int, const double *, unsigned long long *,
                                         const unsigned long long *, const float *, double, const float *, int,
-                                        hipStream_t);
+                                        int, hipStream_t);
 template hipError_t launch_sweep<double>(int, const PassShape &, const Brick *, const BlockMap *, int,
                                          const double *, double *, const double *, const double *,
                                          unsigned long long *, int, const double *, unsigned long long *,
                                          const unsigned long long *, const double *, double, const double *, int,
-                                         hipStream_t);
+                                         int, hipStream_t);
 
 }  // namespace ppmb

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libppmb.so")
+# PPMB_LIB names another build of the same sources (for comparing builds)
+LIB_PATH = os.environ.get("PPMB_LIB") or os.path.join(HERE, "libppmb.so")
 
 FP64, FP32 = 0, 1
 NFIELDS = 15
@@ -33,7 +34,8 @@ EXPORTS = ("ppmb_create", "ppmb_destroy", "ppmb_state_bytes", "ppmb_state_layout
            "ppmb_ppb2d_set", "ppmb_ppb2d_get", "ppmb_ppb2d_steps", "ppmb_ppb2d_get_nstep",
            "ppmb_ppb2d_set_nstep", "ppmb_set_spinup", "ppmb_spin_add", "ppmb_shell_profile",
            "ppmb_set_shock_dissipation", "ppmb_set_flattening", "ppmb_set_gravity",
-           "ppmb_set_heating", "ppmb_set_cfl_check", "ppmb_shell_profile_noalloc")
+           "ppmb_set_heating", "ppmb_set_cfl_check", "ppmb_shell_profile_noalloc",
+           "ppmb_set_solid_skip", "ppmb_set_pass_tiling", "ppmb_get_pass_tiling")
 
 
 class PPMBError(RuntimeError):
@@ -123,6 +125,9 @@ def load():
         "ppmb_set_heating": [p, i, _D, i],
         "ppmb_set_cfl_check": [p, d],
         "ppmb_shell_profile_noalloc": [p, i, i, d, p],
+        "ppmb_set_solid_skip": [p, i],
+        "ppmb_set_pass_tiling": [p, i, i],
+        "ppmb_get_pass_tiling": [p, ctypes.POINTER(i), ctypes.POINTER(i)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -317,6 +322,19 @@ class Sim:
         """Courant check of the dt given to step / pass_ (0: off)."""
         self._check(self.L.ppmb_set_cfl_check(self.h, float(courant_max)))
 
+    def set_solid_skip(self, on: bool):
+        """Passes leave out solid cells beyond the stencil reach (default on)."""
+        self._check(self.L.ppmb_set_solid_skip(self.h, 1 if on else 0))
+
+    def set_tiling(self, march_chunk: int, x_rows: int):
+        """Cells per wave along a pencil (0: whole) and rows per wave of the x pass."""
+        self._check(self.L.ppmb_set_pass_tiling(self.h, int(march_chunk), int(x_rows)))
+
+    def tiling(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        self._check(self.L.ppmb_get_pass_tiling(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def set_spinup(self, omega: float, nramp: int):
         """Steps 0 .. nramp-1 each end with a solid-body rotation increment
         omega / nramp about the z axis."""
@@ -461,6 +479,9 @@ class Batch:
     set_gravity = Sim.set_gravity
     set_heating = Sim.set_heating
     set_cfl_check = Sim.set_cfl_check
+    set_solid_skip = Sim.set_solid_skip
+    set_tiling = Sim.set_tiling
+    tiling = Sim.tiling
 
     def set_spinup(self, omega: float, nramp: int):
         """Steps 0 .. nramp-1 each end with a solid-body rotation increment

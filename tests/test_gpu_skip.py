@@ -1,0 +1,106 @@
+"""Solid cells beyond the stencil reach are skipped by the passes (they keep
+their values, which both state buffers hold alike).  Skipping must change
+no bit: runs with it on and off are compared bitwise, in both precisions,
+with the shock handling on, under graph replay of a batch, after a state
+change in mid-run (the next pass writes every cell again), and the solid
+cells of both buffers must still hold their initial values."""
+import numpy as np
+import pytest
+
+from paper_1810_13416_amd import problems as pr
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(prob, prec, skip, steps, shock=False, reset_at=None):
+    from paper_1810_13416_amd import ppmb
+    S = ppmb.Sim(prob.params, ppmb.FP64 if prec == "fp64" else ppmb.FP32)
+    S.set_solid_skip(skip)
+    S.set_state(prob.state)
+    if shock:
+        S.set_shock_dissipation(0.1)
+        S.set_flattening(True)
+    for s in range(steps):
+        if s == reset_at:
+            S.set_conserved(S.get_conserved())
+        S.step_auto(prob.cfl, 1)
+    out = S.get_conserved()
+    bufs = [b.double().cpu().numpy() for b in S.buffers]
+    layout = S.layout()
+    S.close()
+    return out, bufs, layout
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("shock", [False, True])
+def test_skipping_changes_no_bit(prec, shock):
+    prob = pr.config3(n=40)
+    a, _, _ = _run(prob, prec, True, 5, shock)
+    b, _, _ = _run(prob, prec, False, 5, shock)
+    diffs = [(q, int(np.count_nonzero(a[q] != b[q])), float(np.max(np.abs(a[q] - b[q]))),
+              float(np.max(np.abs(b[q])))) for q in range(15)]
+    print("skip vs no skip (field, cells differing, max |diff|, max |value|):", diffs)
+    for q in range(15):
+        assert np.array_equal(a[q], b[q]), q
+
+
+def test_skipping_after_a_state_change_and_solid_cells_in_both_buffers():
+    prob = pr.config3(n=40)
+    a, bufs, (off, fs, plane, px) = _run(prob, "fp32", True, 6, reset_at=3)
+    b, _, _ = _run(prob, "fp32", False, 6, reset_at=3)
+    for q in range(15):
+        assert np.array_equal(a[q], b[q]), q
+    # the solid cells of both buffers still hold the initial values
+    from paper_1810_13416_amd import ppmb
+    S = ppmb.Sim(prob.params, ppmb.FP32)
+    S.set_state(prob.state)
+    init = S.get_conserved()
+    S.close()
+    n = prob.params.n[0]
+    c = -1.0 + (np.arange(n) + 0.5) * prob.params.dx
+    solid = ((c[:, None, None] ** 2 + c[None, :, None] ** 2) + c[None, None, :] ** 2) >= 1.0
+    k, j, i = np.nonzero(solid)
+    for buf in bufs:
+        for q in range(15):
+            vals = buf[off + q * fs + k * plane + j * px + i]
+            assert np.array_equal(vals, init[q][solid]), q
+
+
+def test_skipping_in_a_batch_under_graph_replay():
+    from paper_1810_13416_amd import ppmb
+    probs = [pr.config3(n=24), pr.config3(n=32), pr.blast((20, 12, 9), p_in=3.0, bc=(1, 0, 1))]
+    res = []
+    for skip in (True, False):
+        B = ppmb.Batch([p.params for p in probs], ppmb.FP32)
+        B.set_solid_skip(skip)
+        for b, p in enumerate(probs):
+            B.set_state(b, p.state)
+        B.step(0.8, 5, mode=1)
+        B.synchronize()
+        res.append([B.get_conserved(b) for b in range(len(probs))])
+        B.close()
+    for b in range(len(probs)):
+        for q in range(15):
+            assert np.array_equal(res[0][b][q], res[1][b][q]), (b, q)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_tiling_changes_no_bit(prec):
+    # every step of the marching kernel runs the same arithmetic, so cutting
+    # the pencils into chunks (each wave reading 4 cells beyond its chunk)
+    # and giving the x pass more rows per wave change no bit
+    from paper_1810_13416_amd import ppmb
+    prob = pr.config3(n=40)
+    res = []
+    for tiling in ((0, 1), (16, 3), (24, 1)):
+        S = ppmb.Sim(prob.params, ppmb.FP64 if prec == "fp64" else ppmb.FP32)
+        S.set_tiling(*tiling)
+        assert S.tiling() == tiling
+        S.set_state(prob.state)
+        S.set_shock_dissipation(0.1)
+        S.step_auto(prob.cfl, 4)
+        res.append(S.get_conserved())
+        S.close()
+    for r in res[1:]:
+        for q in range(15):
+            assert np.array_equal(res[0][q], r[q]), q
