@@ -94,7 +94,7 @@ def run_rotation(sim, n, reps=5):
                               "fluid_volume_over_4pi_3": vol / (4.0 * math.pi / 3.0)}}
 
 
-TILING = (0, 1)        # cells per wave along a pencil (0: whole), x rows per wave
+TILING = (256, 2)      # cells per wave along a pencil (0: whole), x rows per wave
 
 
 def run_gpu(prob, precision, steps, warmup, dev_prims, rotation=False, dissk=0.0, flat=False, skip=True):
@@ -142,6 +142,91 @@ def run_gpu(prob, precision, steps, warmup, dev_prims, rotation=False, dissk=0.0
     del sim
     torch.cuda.empty_cache()
     return info
+
+
+CONFIG5_SUMMARY = os.path.join(ROOT, "profiles", "config5_shell1024_fp32_vs_fp64.json")
+
+
+def run_config5(n=1024, steps=20, warmup=3, slab=64):
+    """The spherical shell at 1024^3 (the 512^3 recipe at half the cell
+    width) in FP32 and then in FP64 on the same GPU.  Both are filled plane
+    slab by plane slab (the FP64 primitives of the whole grid would take
+    129 GB of host memory), warmed up and timed alike; the FP32 state is
+    kept on the host in FP32 and compared field by field with the FP64
+    state after the same steps: relative L1 = sum |a - b| / sum |b| and
+    relative Linf = max |a - b| / max |b| with rho and p as full fields
+    (base added back), velocities against the largest speed component and
+    the fv moments against f0's scale; the perturbation-relative L1 of rho'
+    and p' besides."""
+    import numpy as np
+    import torch
+    from paper_1810_13416_amd import ppmb, problems
+    P = problems.config3_params(n)
+    out = {"grid": [n] * 3, "cells": n ** 3, "steps": steps, "warmup": warmup, "tiling": list(TILING)}
+    kept, base = None, None
+    slabs = [(k0, min(slab, n - k0)) for k0 in range(0, n, slab)]
+    for prec, name in ((ppmb.FP32, "fp32"), (ppmb.FP64, "fp64")):
+        t0 = time.perf_counter()
+        try:
+            S = ppmb.Sim(P, prec, device="cuda:0")
+        except (ppmb.PPMBError, RuntimeError) as e:     # the grid does not fit
+            out[name] = {"error": str(e)[:300]}
+            log(f"config5 {name}: {e}")
+            torch.cuda.empty_cache()
+            continue
+        S.set_tiling(*TILING)
+        for k0, nk in slabs:
+            S.set_state_planes(k0, problems.config3_planes(n, k0, nk))
+        log(f"config5 {name}: state set in {time.perf_counter() - t0:.0f} s")
+        S.step_auto(0.8, warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(S.stream)
+        S.step_auto(0.8, steps)
+        e1.record(S.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[name] = {"ms_per_step": ms, "cell_updates_per_s": n ** 3 / (ms * 1e-3), "dt_last": S.last_dt(),
+                     "totals": [float(v) for v in S.totals()]}
+        log(f"config5 {name}: {ms:.2f} ms/step")
+        if name == "fp32":
+            kept = [[a.astype(np.float32) for a in S.get_state_planes(k0, nk)] for k0, nk in slabs]
+            base = S.base()
+        elif kept is not None:
+            r0, p0 = base
+            acc = np.zeros((15, 4))          # sum |d|, sum |b|, max |d|, max |b| (full fields)
+            pert = np.zeros((2, 2))          # rho', p': sum |d|, sum |b|
+            for s_i, (k0, nk) in enumerate(slabs):
+                b = S.get_state_planes(k0, nk)
+                a = [x.astype(np.float64) for x in kept[s_i]]
+                kept[s_i] = None
+                for i, q in enumerate((0, 4)):
+                    pert[i] += (np.abs(a[q] - b[q]).sum(), np.abs(b[q]).sum())
+                a[0] += r0[k0:k0 + nk]
+                b[0] += r0[k0:k0 + nk]
+                a[4] += p0[k0:k0 + nk]
+                b[4] += p0[k0:k0 + nk]
+                for q in range(15):
+                    d = np.abs(a[q] - b[q])
+                    acc[q] += (d.sum(), np.abs(b[q]).sum(), 0.0, 0.0)
+                    acc[q, 2] = max(acc[q, 2], float(d.max()))
+                    acc[q, 3] = max(acc[q, 3], float(np.abs(b[q]).max()))
+            err = {}
+            for q in range(15):
+                grp = [5] if q >= 5 else ([1, 2, 3] if q in (1, 2, 3) else [q])
+                l1 = sum(acc[g, 1] for g in grp) / len(grp)
+                li = max(acc[g, 3] for g in grp)
+                err[problems.FIELD_NAMES[q]] = {"relL1": acc[q, 0] / max(l1, 1e-300),
+                                                "relLinf": acc[q, 2] / max(li, 1e-300)}
+            out["fp32_vs_fp64"] = err
+            out["perturbation_relL1"] = {"rho'": pert[0, 0] / max(pert[0, 1], 1e-300),
+                                         "p'": pert[1, 0] / max(pert[1, 1], 1e-300)}
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+    if "fp32" in out and "fp64" in out and "ms_per_step" in out["fp64"] and "ms_per_step" in out["fp32"]:
+        out["speedup_fp32_over_fp64"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
+    return out
 
 
 def measured_traffic():
@@ -200,9 +285,12 @@ def run_bricks(steps, warmup):
             B.set_state(b, p.state)
         if shape is None:
             shape = B.autotune(cfl, reps=2)
-            out["autotuned_shape"] = {"march_waves": shape[0], "x_waves": shape[1]}
+            tiling = B.tiling()
+            out["autotuned_shape"] = {"march_waves": shape[0], "x_waves": shape[1],
+                                      "march_chunk": tiling[0], "x_rows": tiling[1]}
         else:
             B.set_shape(*shape)
+            B.set_tiling(*tiling)
         B.step(cfl, warmup, mode)
         B.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -383,6 +471,8 @@ def main():
     ap.add_argument("--no-rotation", action="store_true")
     ap.add_argument("--tiling", type=str, default=None,
                     help="march_chunk,x_rows of the pass kernels (default: %s,%s)" % TILING)
+    ap.add_argument("--config5", action="store_true",
+                    help="run the 1024^3 FP32-vs-FP64 comparison and write its summary to profiles/")
     ap.add_argument("--compare-skip", action="store_true",
                     help="also time the FP32 step with every pass writing every cell")
     ap.add_argument("--calib-copy-mib", type=int, default=0)
@@ -402,6 +492,14 @@ def main():
         TILING = tuple(int(v) for v in args.tiling.split(","))
     if args.calib_copy_mib:
         calib_copy(args.calib_copy_mib)
+    if args.config5:
+        res = run_config5()
+        res["command"] = "python bench.py --config5"
+        res["sweep_sources_sha256"] = __import__("paper_1810_13416_amd.profsum", fromlist=["x"]).sweep_sources_hash()
+        with open(CONFIG5_SUMMARY, "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res), flush=True)
+        return
     log(f"generating the {args.n}^3 shell inputs")
     t0 = time.perf_counter()
     prob = problems.config3(n=args.n)
@@ -530,6 +628,11 @@ def main():
     if not args.no_ppb2d:
         log("2-D PPB: slotted disk")
         out["ppb2d"] = run_ppb2d()
+    if os.path.exists(CONFIG5_SUMMARY):
+        with open(CONFIG5_SUMMARY) as f:
+            c5 = json.load(f)
+        c5["source"] = os.path.relpath(CONFIG5_SUMMARY, ROOT)
+        out["config5_1024"] = c5
     if not args.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline()

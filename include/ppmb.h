@@ -186,6 +186,15 @@ ppmb_status ppmb_set_state(ppmb_ctx *ctx, const double *const host_prim[15]);
 /* Same, from 15 FP64 device arrays (ncell each). */
 ppmb_status ppmb_set_state_device(ppmb_ctx *ctx, const double *const dev_prim[15]);
 
+/* Set / read the z-planes k0 .. k0 + nk - 1 of brick 0 only, from / to 15
+ * FP64 host arrays of nx * ny * nk primitive values each (dense, x
+ * fastest, plane k0 first), so that a grid too large for one host copy of
+ * its fields is filled and checked plane slab by plane slab.  A run sets
+ * every plane before its first step.  Synchronising.  INVALID for planes
+ * outside the grid or a NULL field. */
+ppmb_status ppmb_set_state_planes(ppmb_ctx *ctx, int k0, int nk, const double *const host_prim[15]);
+ppmb_status ppmb_get_state_planes(ppmb_ctx *ctx, int k0, int nk, double *const host_prim[15]);
+
 /* Read the state back as 15 FP64 host arrays of primitive perturbations.
  * Synchronising. */
 ppmb_status ppmb_get_state(ppmb_ctx *ctx, double *const host_prim[15]);
@@ -326,6 +335,22 @@ ppmb_status ppmb_set_flattening(ppmb_ctx *ctx, int on);
  * non-finite omega or nramp < 0.  Host-side setting only. */
 ppmb_status ppmb_set_spinup(ppmb_ctx *ctx, double omega, long nramp);
 
+/* Rotating frame (Sec. 3 names rotating coordinates as the next step of
+ * these runs).  With omega != 0 the equations are those seen from axes
+ * turning at omega about the z axis through the coordinate origin: every
+ * step ends, after its passes and heating and before a spin-up increment,
+ * with the Coriolis acceleration -2 omega z-hat x u = 2 omega (u_y, -u_x,
+ * 0) and, with centrifugal != 0, the centrifugal acceleration
+ * omega^2 (x, y, 0), applied over the step's dt as a split step: half the
+ * centrifugal velocity change, the exact Coriolis rotation of (u_x, u_y)
+ * by the angle -2 omega dt, the other half.  Density and pressure are
+ * kept; m and E' are rebuilt, in FP64, and stored in the working
+ * precision.  Solid cells are not touched.  The step after it takes its dt
+ * from a full CFL reduction.  omega = 0 (the default) is the inertial
+ * frame.  Host-side setting; drops a captured step graph.  INVALID for a
+ * non-finite omega. */
+ppmb_status ppmb_set_rotating_frame(ppmb_ctx *ctx, double omega, int centrifugal);
+
 /* One increment domega now, on the current state of every brick.
  * Asynchronous; INVALID for a non-finite domega or unbound state. */
 ppmb_status ppmb_spin_add(ppmb_ctx *ctx, double domega);
@@ -411,21 +436,27 @@ ppmb_status ppmb_get_pass_shape(const ppmb_ctx *ctx, int *march_waves, int *x_wa
 /* Work per wave of the pass kernels: the marching kernel (y and z passes)
  * cuts each pencil into chunks of march_chunk cells, one wave per chunk
  * (0: one wave marches the whole pencil; else at least 16), and the x pass
- * gives each wave at least x_rows x-rows (1..64).  Shorter chunks and
- * more rows even out the waves' work when solid cells are skipped; every
- * wave reads 4 cells beyond its chunk either side.  Changes no result bit.
- * Synchronising.  The default is chunk 0, 1 row. */
+ * gives each wave at least x_rows x-rows (1..64); x_rows = 0 runs the x
+ * pass by the marching kernel instead (lanes across y, loads gathered from
+ * 64 rows), which can suit short rows.  Shorter chunks and more rows even
+ * out the waves' work when solid cells are skipped; every wave reads 4
+ * cells beyond its chunk either side.  Changes no result bit.
+ * Synchronising.  The default is chunks of 256 cells and 2 rows
+ * (PPMB_X_MARCH=1 at create: x_rows 0). */
 ppmb_status ppmb_set_pass_tiling(ppmb_ctx *ctx, int march_chunk, int x_rows);
 ppmb_status ppmb_get_pass_tiling(const ppmb_ctx *ctx, int *march_chunk, int *x_rows);
 
-/* Autotuner: times every launch shape (waves per block 1, 2, 4 for each of
- * the two pass kernels) on this context's bricks, `reps` passes per axis
- * and shape, with the current dt, reading the current state and writing the
- * spare arena (the state, step count and counters are left as they were),
- * and selects the fastest.  If cache_path is not NULL, a line keyed by
- * precision, brick count and total cells is read from it (no timing when
- * present) or appended to it.  out_shape receives {march_waves, x_waves}.
- * Synchronising. */
+/* Autotuner: times, on this context's bricks, `reps` passes per candidate
+ * (after one untimed pass), reading the current state and writing the
+ * spare arena (the state, step count and counters are left as they were):
+ * first the marching kernel over the y and z passes for waves per block 1,
+ * 2, 4 and chunks of 0 (whole pencils), 128, 256 cells; then the x pass by
+ * the lanes-along-x kernel for waves per block 1, 2, 4 and at least 1, 2, 4
+ * rows per wave, and by the marching kernel with the shape just chosen;
+ * and keeps the fastest of each.  If cache_path is not NULL, a line keyed
+ * by precision, brick count and total cells is read from it (no timing
+ * when present) or appended to it.  out_shape receives {march_waves,
+ * x_waves}; ppmb_get_pass_tiling gives the rest.  Synchronising. */
 ppmb_status ppmb_autotune(ppmb_ctx *ctx, double cfl, int reps, const char *cache_path, int out_shape[2]);
 
 /* Per-pass timing.  While enabled, every pass kernel is bracketed by HIP

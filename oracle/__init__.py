@@ -76,6 +76,7 @@ def lib():
         L.or_set_heating.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
         L.or_flattening.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
         L.or_set_spinup.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_long]
+        L.or_set_rotating_frame.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]
         L.or_shell_profile.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _D]
         L.or_counters.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_ulonglong)]
         L.or_face4.restype = ctypes.c_double
@@ -225,6 +226,9 @@ class Oracle:
 
     def set_spinup(self, omega: float, nramp: int):
         lib().or_set_spinup(self.h, omega, nramp)
+
+    def set_rotating_frame(self, omega: float, centrifugal: bool = True):
+        lib().or_set_rotating_frame(self.h, float(omega), 1 if centrifugal else 0)
 
     def shell_profile(self, nbins: int, dr: float):
         out = np.zeros((nbins, 8))

@@ -94,6 +94,8 @@ typedef struct {
     double   *divu;        /* undivided velocity divergence at the step start */
     int       flat_on;     /* flattening near strong shocks (CW84 Sec. 4) */
     double   *flat;        /* its coefficient for the pass in progress */
+    double    rot_omega;   /* rotating frame: angular velocity about z (0: inertial) */
+    int       rot_centrifugal; /* ... with the centrifugal term */
 } or_sim;
 
 static long cidx(const or_sim *S, int i, int j, int k)
@@ -1121,6 +1123,52 @@ void or_spin_add(void *h, double domega)
             }
 }
 
+/* Rotating frame (Sec. 3: the runs keep the inertial frame and name
+   rotating coordinates as the next step).  [reading] Axes turning at omega
+   about the z axis through the coordinate origin add two accelerations to
+   the momentum equation: the Coriolis term -2 omega z-hat x u =
+   2 omega (u_y, -u_x, 0) and, when `centrifugal` is set, the centrifugal
+   term omega^2 (x, y, 0).  Each step ends, after the passes and the
+   heating, with these sources over dt as a split step of its own, in three
+   parts: half the centrifugal velocity change omega^2 (x, y) dt / 2; then
+   the exact solution of the Coriolis part alone over dt, which turns
+   (u_x, u_y) by the angle -2 omega dt; then the other half of the
+   centrifugal change.  Density and pressure are kept; m and E' are rebuilt
+   from the new velocity.  Solid cells are not touched. */
+static void rotframe(or_sim *S, double dt)
+{
+    const or_params *P = &S->P;
+    const double om = S->rot_omega, gm1 = P->gamma - 1.0;
+    const double th = -2.0 * om * dt, cth = cos(th), sth = sin(th);
+    const double kick = S->rot_centrifugal ? 0.5 * om * om * dt : 0.0;
+    for (int k = 0; k < P->n[2]; ++k)
+        for (int j = 0; j < P->n[1]; ++j)
+            for (int i = 0; i < P->n[0]; ++i) {
+                double x[3];
+                cell_pos(P, i, j, k, x);
+                if (solid_at(P, x)) continue;
+                long c = cidx(S, i, j, k);
+                double rho = S->rho0[c] + S->U[RHO][c];
+                double u = S->U[MX][c] / rho, v = S->U[MY][c] / rho, w = S->U[MZ][c] / rho;
+                double pp = gm1 * (S->U[EN][c] - 0.5 * (S->U[MX][c] * u + S->U[MY][c] * v + S->U[MZ][c] * w));
+                u += kick * x[0];
+                v += kick * x[1];
+                double ur = cth * u - sth * v, vr = sth * u + cth * v;
+                u = ur + kick * x[0];
+                v = vr + kick * x[1];
+                S->U[MX][c] = rho * u;
+                S->U[MY][c] = rho * v;
+                S->U[EN][c] = pp / gm1 + 0.5 * rho * ((u * u + v * v) + w * w);
+            }
+}
+
+void or_set_rotating_frame(void *h, double omega, int centrifugal)
+{
+    or_sim *S = (or_sim *)h;
+    S->rot_omega = omega;
+    S->rot_centrifugal = centrifugal ? 1 : 0;
+}
+
 /* Ramp: the steps with index 0 .. nramp-1 each end with an increment of
    omega / nramp, so that the rotation reaches omega after nramp steps.
    nramp <= 0 or omega == 0 switches the ramp off. */
@@ -1361,6 +1409,7 @@ void or_step(void *h, double dt)
                     S->U[EN][cidx(S, i, j, k)] += heating_at(P, x) * dt;
                 }
     }
+    if (S->rot_omega != 0.0) rotframe(S, dt);
     if (S->nstep < S->spin_nramp) or_spin_add(h, S->spin_omega / (double)S->spin_nramp);
     S->nstep++;
     S->cnt[3]++;

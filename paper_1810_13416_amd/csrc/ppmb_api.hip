@@ -8,6 +8,7 @@
 #include "../../include/ppmb.h"
 #include "ppmb_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -40,8 +41,9 @@ struct ppmb_ctx {
     unsigned long long *cband = nullptr; // per brick: band edge of the fused CFL reduction, redo flag
     double *partials = nullptr;         // totals block partials
     double *out8 = nullptr;             // totals result
-    PassShape shape{ 1, 4, 0, 1 };
-    BlockMap *pmap[3] = { nullptr, nullptr, nullptr };   // per pass axis
+    PassShape shape{ 1, 4, 256, 2 };
+    BlockMap *pmap[3] = { nullptr, nullptr, nullptr };   // per pass axis, brick by brick
+    BlockMap *pmap_all[3] = { nullptr, nullptr, nullptr };   // the same blocks, longest first over all bricks
     std::vector<int> pfirst[3];         // first block of each brick (+ total at the end)
     BlockMap *cmap = nullptr;           // CFL reduction
     std::vector<int> cfirst;
@@ -65,6 +67,8 @@ struct ppmb_ctx {
     // spin-up ramp: steps 0 .. spin_nramp-1 end with + spin_omega / spin_nramp
     double spin_omega = 0.0;
     long spin_nramp = 0;
+    double rot_omega = 0.0;             // rotating frame (0: inertial)
+    int rot_centrifugal = 0;
     double *shell_ws = nullptr;         // shell-sum block partials + result
     size_t shell_ws_bytes = 0;
     double dissk = 0.0;                 // shock dissipation coefficient (0: off)
@@ -135,7 +139,12 @@ static bool solid_all_same(const ppmb_ctx *c, int b0, int b1)
 
 static void free_maps(ppmb_ctx *c)
 {
-    for (int d = 0; d < 3; ++d) { hipFree(c->pmap[d]); c->pmap[d] = nullptr; }
+    for (int d = 0; d < 3; ++d) {
+        hipFree(c->pmap[d]);
+        c->pmap[d] = nullptr;
+        hipFree(c->pmap_all[d]);
+        c->pmap_all[d] = nullptr;
+    }
     hipFree(c->cmap);
     c->cmap = nullptr;
     hipFree(c->dmap);
@@ -158,16 +167,35 @@ static ppmb_status build_maps(ppmb_ctx *c)
     free_graph(c);
     free_maps(c);
     for (int d = 0; d < 3; ++d) {
+        // per brick, blocks longest first (with solid cells skipped their
+        // work differs widely, and a launch ends when its last block does);
+        // for launches over all bricks the same blocks longest first across
+        // bricks of different sizes
         std::vector<BlockMap> m;
+        std::vector<std::pair<double, size_t>> all;
         c->pfirst[d].assign(c->nb + 1, 0);
         for (int b = 0; b < c->nb; ++b) {
             c->pfirst[d][b] = (int)m.size();
-            int n = pass_blocks(c->hb[b].g, d, c->shape);
-            for (int l = 0; l < n; ++l) m.push_back(BlockMap{ b, l });
+            const Geom &g = c->hb[b].g;
+            const int n = pass_blocks(g, d, c->shape);
+            std::vector<std::pair<double, int>> order((size_t)n);
+            for (int l = 0; l < n; ++l) order[l] = { -pass_block_cost(g, d, c->shape, l), l };
+            // (the x pass keeps its rows in storage order: sorted, waves
+            // running together would touch rows all over the grid)
+            if (g.sphere && d != 0) std::stable_sort(order.begin(), order.end());
+            for (const auto &o : order) {
+                all.push_back({ d != 0 ? o.first : 0.0, m.size() });
+                m.push_back(BlockMap{ b, o.second });
+            }
         }
         c->pfirst[d][c->nb] = (int)m.size();
         if (m.size() > 0x7fffffff) return fail(c, PPMB_ERR_INVALID, "too many blocks");
         TRY(upload_map(c, m, &c->pmap[d]));
+        std::stable_sort(all.begin(), all.end());
+        std::vector<BlockMap> ma;
+        ma.reserve(m.size());
+        for (const auto &a : all) ma.push_back(m[a.second]);
+        TRY(upload_map(c, ma, &c->pmap_all[d]));
     }
     std::vector<BlockMap> m;
     c->cfirst.assign(c->nb + 1, 0);
@@ -363,6 +391,9 @@ static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_preci
     c->solid_same.assign(nbricks, 0);
     if (const char *e = getenv("PPMB_CHECK_CFL"))
         if (e[0] == '1' && e[1] == 0) c->courant_max = 1.0;
+    // PPMB_X_MARCH=1: the x pass by the marching kernel (for comparison)
+    if (const char *e = getenv("PPMB_X_MARCH"))
+        if (e[0] == '1' && e[1] == 0) c->shape.x_rows = 0;
     c->table_len = 64 + 2 * maxspan;
     hipError_t e = scratch_of_current_device(&c->device, &c->noalloc_ws);
     if (e != hipSuccess) {
@@ -466,14 +497,15 @@ static ppmb_status enqueue_pass(ppmb_ctx *c, int axis, int heat, int b0, int b1,
     }
     hipError_t e;
     const int skip = c->skip_on && solid_all_same(c, b0, b1) ? 1 : 0;
+    const BlockMap *map = (b0 == 0 && b1 == c->nb) ? c->pmap_all[axis] : c->pmap[axis] + f0;
     if (c->prec == PPMB_FP64)
-        e = launch_sweep<double>(axis, c->shape, c->db, c->pmap[axis] + f0, f1 - f0, arena<double>(c, from),
+        e = launch_sweep<double>(axis, c->shape, c->db, map, f1 - f0, arena<double>(c, from),
                                  arena<double>(c, 1 - from), c->base64, c->dt, c->cnt, heat, c->base64,
                                  c->work, c->cband, static_cast<const double *>(c->divbuf), c->dissk,
                                  c->flat_on ? static_cast<const double *>(c->flatbuf) : nullptr, cfl, skip,
                                  c->stream);
     else
-        e = launch_sweep<float>(axis, c->shape, c->db, c->pmap[axis] + f0, f1 - f0, arena<float>(c, from),
+        e = launch_sweep<float>(axis, c->shape, c->db, map, f1 - f0, arena<float>(c, from),
                                 arena<float>(c, 1 - from), static_cast<const float *>(c->baseT), c->dt,
                                 c->cnt, heat, c->base64, c->work, c->cband, static_cast<const float *>(c->divbuf),
                                 c->dissk, c->flat_on ? static_cast<const float *>(c->flatbuf) : nullptr, cfl,
@@ -560,6 +592,21 @@ static ppmb_status enqueue_spin(ppmb_ctx *c, double domega)
     return PPMB_OK;
 }
 
+// Rotating-frame sources at the end of a step, every brick over its dt.
+// The CFL maxima of the last pass no longer describe the state afterwards.
+static ppmb_status enqueue_rotframe(ppmb_ctx *c)
+{
+    const int nblk = c->cfirst[c->nb];
+    if (c->prec == PPMB_FP64)
+        HIPCHK(c, launch_rotframe<double>(c->db, c->cmap, nblk, arena<double>(c, c->cur), c->base64, c->dt,
+                                          c->rot_omega, c->rot_centrifugal, c->stream));
+    else
+        HIPCHK(c, launch_rotframe<float>(c->db, c->cmap, nblk, arena<float>(c, c->cur), c->base64, c->dt,
+                                         c->rot_omega, c->rot_centrifugal, c->stream));
+    c->cfl_ready = false;
+    return PPMB_OK;
+}
+
 // One step of every brick: a launch per stage covering all bricks
 // (batched) or one launch per stage and brick (per_brick); during a
 // spin-up ramp the step ends with the rotation increment.
@@ -577,6 +624,7 @@ static ppmb_status enqueue_step(ppmb_ctx *c, bool with_cfl, double cfl, bool per
     }
     c->cur = 1 - c->cur;           // three passes: the state ends in the other arena
     c->cfl_ready = true;
+    if (c->rot_omega != 0.0) TRY(enqueue_rotframe(c));
     if (c->nstep < c->spin_nramp) TRY(enqueue_spin(c, c->spin_omega / (double)c->spin_nramp));
     c->nstep++;
     c->steps++;
@@ -816,7 +864,9 @@ ppmb_status ppmb_set_state_device(ppmb_ctx *c, const double *const dev_prim[15])
 // per field, so that the largest grids need no full-size staging copy.
 static const long kChunk = 1L << 24;
 
-ppmb_status ppmb_brick_set_state(ppmb_ctx *c, int brick, const double *const host_prim[15])
+// Dense cells [cbeg, cend) of a brick from host arrays holding exactly
+// those cells (element c - cbeg), through a staging buffer.
+static ppmb_status set_state_cells(ppmb_ctx *c, int brick, long cbeg, long cend, const double *const host_prim[15])
 {
     if (!c || !host_prim) return PPMB_ERR_INVALID;
     TRY(check_brick(c, brick));
@@ -825,15 +875,16 @@ ppmb_status ppmb_brick_set_state(ppmb_ctx *c, int brick, const double *const hos
     for (int q = 0; q < NF; ++q)
         if (!host_prim[q]) return fail(c, PPMB_ERR_INVALID, "set_state: null field");
     const Brick &B = c->hb[brick];
-    const long n = B.ncell, ch = n < kChunk ? n : kChunk;
+    const long n = cend - cbeg, ch = n < kChunk ? n : kChunk;
     Staging st;
     if (hipMalloc(&st.p, sizeof(double) * NF * ch) != hipSuccess)
         return fail(c, PPMB_ERR_NOMEM, "set_state: staging");
-    for (long c0 = 0; c0 < n; c0 += ch) {
-        const long m = (n - c0) < ch ? (n - c0) : ch;
+    for (long o = 0; o < n; o += ch) {
+        const long m = (n - o) < ch ? (n - o) : ch;
+        const long c0 = cbeg + o;
         const double *dev[NF];
         for (int q = 0; q < NF; ++q) {
-            HIPCHK(c, hipMemcpyAsync(st.p + q * ch, host_prim[q] + c0, sizeof(double) * m,
+            HIPCHK(c, hipMemcpyAsync(st.p + q * ch, host_prim[q] + o, sizeof(double) * m,
                                      hipMemcpyHostToDevice, c->stream));
             dev[q] = st.p + q * ch;
         }
@@ -848,24 +899,41 @@ ppmb_status ppmb_brick_set_state(ppmb_ctx *c, int brick, const double *const hos
     return PPMB_OK;
 }
 
+ppmb_status ppmb_brick_set_state(ppmb_ctx *c, int brick, const double *const host_prim[15])
+{
+    if (!c) return PPMB_ERR_INVALID;
+    if (brick < 0 || brick >= c->nb) return fail(c, PPMB_ERR_INVALID, "brick index out of range");
+    return set_state_cells(c, brick, 0, c->hb[brick].ncell, host_prim);
+}
+
+ppmb_status ppmb_set_state_planes(ppmb_ctx *c, int k0, int nk, const double *const host_prim[15])
+{
+    if (!c) return PPMB_ERR_INVALID;
+    const Geom &g = c->hb[0].g;
+    if (k0 < 0 || nk < 1 || k0 + nk > g.n[2]) return fail(c, PPMB_ERR_INVALID, "set_state_planes: planes out of range");
+    const long pl = (long)g.n[0] * g.n[1];
+    return set_state_cells(c, 0, k0 * pl, (k0 + nk) * pl, host_prim);
+}
+
 ppmb_status ppmb_set_state(ppmb_ctx *c, const double *const host_prim[15])
 {
     return ppmb_brick_set_state(c, 0, host_prim);
 }
 
-ppmb_status ppmb_brick_get_state(ppmb_ctx *c, int brick, double *const host_prim[15])
+static ppmb_status get_state_cells(ppmb_ctx *c, int brick, long cbeg, long cend, double *const host_prim[15])
 {
     if (!c || !host_prim) return PPMB_ERR_INVALID;
     TRY(check_brick(c, brick));
     for (int q = 0; q < NF; ++q)
         if (!host_prim[q]) return fail(c, PPMB_ERR_INVALID, "get_state: null field");
     const Brick &B = c->hb[brick];
-    const long n = B.ncell, ch = n < kChunk ? n : kChunk;
+    const long n = cend - cbeg, ch = n < kChunk ? n : kChunk;
     Staging st;
     if (hipMalloc(&st.p, sizeof(double) * NF * ch) != hipSuccess)
         return fail(c, PPMB_ERR_NOMEM, "get_state: staging");
-    for (long c0 = 0; c0 < n; c0 += ch) {
-        const long m = (n - c0) < ch ? (n - c0) : ch;
+    for (long o = 0; o < n; o += ch) {
+        const long m = (n - o) < ch ? (n - o) : ch;
+        const long c0 = cbeg + o;
         if (c->prec == PPMB_FP64)
             HIPCHK(c, launch_cons_to_prim_range<double>(B.g, arena<double>(c, c->cur) + B.off,
                                                         c->base64 + B.boff, st.p, c0, m, ch, c->stream));
@@ -873,11 +941,27 @@ ppmb_status ppmb_brick_get_state(ppmb_ctx *c, int brick, double *const host_prim
             HIPCHK(c, launch_cons_to_prim_range<float>(B.g, arena<float>(c, c->cur) + B.off,
                                                        c->base64 + B.boff, st.p, c0, m, ch, c->stream));
         for (int q = 0; q < NF; ++q)
-            HIPCHK(c, hipMemcpyAsync(host_prim[q] + c0, st.p + q * ch, sizeof(double) * m,
+            HIPCHK(c, hipMemcpyAsync(host_prim[q] + o, st.p + q * ch, sizeof(double) * m,
                                      hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     return PPMB_OK;
+}
+
+ppmb_status ppmb_brick_get_state(ppmb_ctx *c, int brick, double *const host_prim[15])
+{
+    if (!c) return PPMB_ERR_INVALID;
+    if (brick < 0 || brick >= c->nb) return fail(c, PPMB_ERR_INVALID, "brick index out of range");
+    return get_state_cells(c, brick, 0, c->hb[brick].ncell, host_prim);
+}
+
+ppmb_status ppmb_get_state_planes(ppmb_ctx *c, int k0, int nk, double *const host_prim[15])
+{
+    if (!c) return PPMB_ERR_INVALID;
+    const Geom &g = c->hb[0].g;
+    if (k0 < 0 || nk < 1 || k0 + nk > g.n[2]) return fail(c, PPMB_ERR_INVALID, "get_state_planes: planes out of range");
+    const long pl = (long)g.n[0] * g.n[1];
+    return get_state_cells(c, 0, k0 * pl, (k0 + nk) * pl, host_prim);
 }
 
 ppmb_status ppmb_get_state(ppmb_ctx *c, double *const host_prim[15])
@@ -1034,8 +1118,10 @@ static ppmb_status graph_steps(ppmb_ctx *c, double cfl, int nsteps)
     int pairs = nsteps / 2;
     if (pairs > 0) {
         // the captured steps take dt from the maxima in work[]: make them
-        // describe the current state first
-        if (!c->cfl_ready) {
+        // describe the current state first (with the rotating-frame sources,
+        // which change the state after the last pass, every step takes a
+        // full reduction instead, captured ones included)
+        if (!c->cfl_ready && c->rot_omega == 0.0) {
             TRY(enqueue_cfl(c, cfl, 0, c->nb));
             c->cfl_ready = true;
         }
@@ -1173,6 +1259,15 @@ ppmb_status ppmb_set_spinup(ppmb_ctx *c, double omega, long nramp)
     return PPMB_OK;
 }
 
+ppmb_status ppmb_set_rotating_frame(ppmb_ctx *c, double omega, int centrifugal)
+{
+    if (!c || !std::isfinite(omega)) return PPMB_ERR_INVALID;
+    c->rot_omega = omega;
+    c->rot_centrifugal = centrifugal ? 1 : 0;
+    free_graph(c);                       // captured steps hold the previous setting
+    return PPMB_OK;
+}
+
 ppmb_status ppmb_spin_add(ppmb_ctx *c, double domega)
 {
     if (!c || !std::isfinite(domega)) return PPMB_ERR_INVALID;
@@ -1258,8 +1353,8 @@ ppmb_status ppmb_set_pass_shape(ppmb_ctx *c, int march_waves, int x_waves)
 ppmb_status ppmb_set_pass_tiling(ppmb_ctx *c, int march_chunk, int x_rows)
 {
     if (!c) return PPMB_ERR_INVALID;
-    if (march_chunk < 0 || (march_chunk > 0 && march_chunk < 16) || x_rows < 1 || x_rows > 64)
-        return fail(c, PPMB_ERR_INVALID, "pass tiling: chunk 0 or >= 16 cells, 1..64 rows per wave");
+    if (march_chunk < 0 || (march_chunk > 0 && march_chunk < 16) || x_rows < 0 || x_rows > 64)
+        return fail(c, PPMB_ERR_INVALID, "pass tiling: chunk 0 or >= 16 cells, 0..64 rows per wave");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->shape.march_chunk = march_chunk;
     c->shape.x_rows = x_rows;
@@ -1298,6 +1393,32 @@ static std::string tune_key(const ppmb_ctx *c)
     return k;
 }
 
+// Time `reps` passes along the given axes with the current shape (after one
+// untimed pass), reading the current state and writing the spare arena.
+static ppmb_status time_passes(ppmb_ctx *c, const int *axes, int naxes, int reps, hipEvent_t e0, hipEvent_t e1,
+                               float *ms)
+{
+    *ms = 0.f;
+    for (int a = 0; a < naxes; ++a) {
+        TRY(enqueue_pass(c, axes[a], 0, 0, c->nb, c->cur));          // warm-up
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int r = 0; r < reps; ++r) TRY(enqueue_pass(c, axes[a], 0, 0, c->nb, c->cur));
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+        *ms += t;
+    }
+    return PPMB_OK;
+}
+
+static ppmb_status set_shape(ppmb_ctx *c, const PassShape &sh)
+{
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->shape = sh;
+    return build_maps(c);
+}
+
 ppmb_status ppmb_autotune(ppmb_ctx *c, double cfl, int reps, const char *cache_path, int out_shape[2])
 {
     if (!c || !out_shape || !(cfl > 0) || reps < 1) return PPMB_ERR_INVALID;
@@ -1307,12 +1428,13 @@ ppmb_status ppmb_autotune(ppmb_ctx *c, double cfl, int reps, const char *cache_p
         FILE *f = fopen(cache_path, "r");
         if (f) {
             char line[256];
-            int mw = 0, xw = 0;
+            int mw = 0, xw = 0, ck = 0, xr = 0;
             while (fgets(line, sizeof line, f)) {
                 char kbuf[200];
-                if (sscanf(line, "%199[^|]| %d %d", kbuf, &mw, &xw) == 3 && key == std::string(kbuf)) {
+                if (sscanf(line, "%199[^|]| %d %d %d %d", kbuf, &mw, &xw, &ck, &xr) == 5 && key == std::string(kbuf)) {
                     fclose(f);
                     TRY(ppmb_set_pass_shape(c, mw, xw));
+                    TRY(ppmb_set_pass_tiling(c, ck, xr));
                     out_shape[0] = mw;
                     out_shape[1] = xw;
                     return PPMB_OK;
@@ -1329,40 +1451,54 @@ ppmb_status ppmb_autotune(ppmb_ctx *c, double cfl, int reps, const char *cache_p
     TRY(check_flag(c));
     const bool prof = c->profiling;
     c->profiling = false;
-    const int cand[3] = { 1, 2, 4 };
-    float best_m = 1e30f, best_x = 1e30f;
-    int bm = c->shape.march_waves, bx = c->shape.x_waves;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     ppmb_status st = PPMB_OK;
-    for (int a = 0; a < 3 && st == PPMB_OK; ++a) {
-        st = ppmb_set_pass_shape(c, cand[a], cand[a]);
-        float tm = 0.f, tx = 0.f;
-        for (int axis = 0; axis < 3 && st == PPMB_OK; ++axis) {
-            st = enqueue_pass(c, axis, 0, 0, c->nb, c->cur);          // warm-up
-            if (hipEventRecord(e0, c->stream) != hipSuccess) st = PPMB_ERR_HIP;
-            for (int r = 0; r < reps && st == PPMB_OK; ++r) st = enqueue_pass(c, axis, 0, 0, c->nb, c->cur);
-            if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) st = PPMB_ERR_HIP;
-            float ms = 0.f;
-            if (st == PPMB_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = PPMB_ERR_HIP;
-            if (axis == 0) tx = ms; else tm += ms;
+    PassShape best = c->shape;
+    // the marching kernel (y and z passes): waves per block and chunk length
+    const int waves[3] = { 1, 2, 4 };
+    const int chunks[3] = { 0, 128, 256 };
+    const int yz[2] = { 1, 2 };
+    float best_m = 1e30f;
+    for (int w = 0; w < 3 && st == PPMB_OK; ++w)
+        for (int k = 0; k < 3 && st == PPMB_OK; ++k) {
+            PassShape sh = best;
+            sh.march_waves = waves[w];
+            sh.march_chunk = chunks[k];
+            float t = 0.f;
+            st = set_shape(c, sh);
+            if (st == PPMB_OK) st = time_passes(c, yz, 2, reps, e0, e1, &t);
+            if (st == PPMB_OK && t < best_m) { best_m = t; best.march_waves = sh.march_waves; best.march_chunk = sh.march_chunk; }
         }
-        if (st == PPMB_OK && tm < best_m) { best_m = tm; bm = cand[a]; }
-        if (st == PPMB_OK && tx < best_x) { best_x = tx; bx = cand[a]; }
-    }
+    // the x pass: the lanes-along-x kernel (waves per block, rows per wave)
+    // or the marching kernel with the shape just chosen
+    const int rows[4] = { 0, 1, 2, 4 };
+    const int xa[1] = { 0 };
+    float best_x = 1e30f;
+    for (int w = 0; w < 3 && st == PPMB_OK; ++w)
+        for (int r = 0; r < 4 && st == PPMB_OK; ++r) {
+            if (rows[r] == 0 && w > 0) continue;      // x_waves plays no part then
+            PassShape sh = best;
+            sh.x_waves = waves[w];
+            sh.x_rows = rows[r];
+            float t = 0.f;
+            st = set_shape(c, sh);
+            if (st == PPMB_OK) st = time_passes(c, xa, 1, reps, e0, e1, &t);
+            if (st == PPMB_OK && t < best_x) { best_x = t; best.x_waves = sh.x_waves; best.x_rows = sh.x_rows; }
+        }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     c->profiling = prof;
     if (st != PPMB_OK) return st;
     HIPCHK(c, hipMemcpy(c->cnt, saved, sizeof saved, hipMemcpyHostToDevice));
-    TRY(ppmb_set_pass_shape(c, bm, bx));
-    out_shape[0] = bm;
-    out_shape[1] = bx;
+    TRY(set_shape(c, best));
+    out_shape[0] = best.march_waves;
+    out_shape[1] = best.x_waves;
     if (cache_path) {
         FILE *f = fopen(cache_path, "a");
         if (f) {
-            fprintf(f, "%s| %d %d\n", key.c_str(), bm, bx);
+            fprintf(f, "%s| %d %d %d %d\n", key.c_str(), best.march_waves, best.x_waves, best.march_chunk, best.x_rows);
             fclose(f);
         }
     }

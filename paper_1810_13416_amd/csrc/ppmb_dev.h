@@ -66,6 +66,15 @@ __device__ __forceinline__ double trsq(double a) { return 1.0 / sqrt(a); }
 __device__ __forceinline__ float tsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
 __device__ __forceinline__ double tsqrt(double a) { return sqrt(a); }
 
+// Sound speed c = sqrt(x) and 1/c of x = gamma p / rho, from one
+// reciprocal square root.
+template <typename T>
+__device__ __forceinline__ void sound(T x, T &c, T &ic)
+{
+    ic = trsq(x);
+    c = x * ic;
+}
+
 // hardware abs / min / max (operand modifiers and single instructions)
 __device__ __forceinline__ float tabs(float a) { return fabsf(a); }
 __device__ __forceinline__ double tabs(double a) { return fabs(a); }
@@ -135,8 +144,10 @@ __device__ __forceinline__ T gravity(int kind, const C *c, int axis, T xd, T rt2
 {
     if (kind == 1) return c[axis];
     if (kind == 2) {
-        T r = tsqrt(rt2);
-        T h = (r < c[1]) ? T(c[2]) : (c[1] * c[1]) * trcp(rt2 * r);
+        // r and 1/r^3 from one reciprocal square root (r = 0 at the centre)
+        const T ir = trsq(rt2);
+        const T r = rt2 > T(0) ? rt2 * ir : T(0);
+        T h = (r < c[1]) ? T(c[2]) : (c[1] * c[1]) * (ir * ir * ir);
         T t = r <= c[3] ? T(1) : (r >= c[4] ? T(0) : (c[4] - r) * c[5]);
         return -c[0] * xd * h * t;
     }
@@ -277,8 +288,15 @@ __device__ __forceinline__ T smooth_weight_d(T d0, T d1, T d2)
     const T lo = tmin(d0, tmin(d1, d2)), hi = tmax(d0, tmax(d1, d2));
     const T a0 = tabs(d0), a1 = tabs(d1), a2 = tabs(d2);
     const T mx = tmax(a0, tmax(a1, a2)), mn = tmin(a0, tmin(a1, a2));
-    const T r = (T(3) * mn - mx) * trcp(mn);
-    T w = mx <= T(2) * mn ? T(1) : (mx >= T(3) * mn ? T(0) : r);
+    const bool below = mx <= T(2) * mn, above = mx >= T(3) * mn;
+    T w = below ? T(1) : T(0);
+    // the graded band between: few cells of a wave lie in it, so the
+    // reciprocal is computed only when one does
+    const bool band = !below && !above;
+    if (__builtin_amdgcn_ballot_w64(band)) {
+        const T r = (T(3) * mn - mx) * trcp(mn);
+        w = band ? r : w;
+    }
     w = (lo > T(0) || hi < T(0)) ? w : T(0);
     return mx == T(0) ? T(1) : w;
 }
@@ -606,16 +624,16 @@ __device__ __forceinline__ bool parabola(int detect, T q, T qfL, T qfR, T flL, T
 // Characteristic tracing of one cell (CW84 Sec. 3): the states at its right
 // face (TL, seen from the left of that face) and at its left face (TR), from
 // the parabolas of rho', u, v, w, p' (edge values qL, qR, dq, q6), the
-// cell's rho, c, u, rho', gravity, and the base face values, plus the
-// half-step sources (gravity on rho', advection of the base).
+// cell's rho and 1/rho, c and 1/c, u, rho', gravity, and the base face
+// values, plus the half-step sources (gravity on rho', advection of the
+// base).
 template <typename T>
 __device__ __forceinline__ void trace_cell(const T *qL, const T *qR, const T *dq, const T *q6,
-                                           T rj, T cj, T uj, T rpj, T gj, T r0fL, T r0fR,
+                                           T rj, T irj, T cj, T icj, T uj, T rpj, T gj, T r0fL, T r0fR,
                                            T p0fL, T p0fR, T nu, T hdt, T rdx, St<T> &TL, St<T> &TR)
 {
     const T c2 = cj * cj;
     const T lm = uj - cj, l0 = uj, lp = uj + cj;
-    const T irj = trcp(rj), icj = trcp(cj);
     const T rc2 = T(0.5) * rj * icj, cr_ = cj * irj, ic2 = icj * icj, i2c2 = T(0.5) * ic2;
     {   // right face: waves moving right
         T y = tmax(lp, T(0)) * nu;

@@ -34,11 +34,16 @@ struct PassShape {
     int march_waves;
     int x_waves;
     int march_chunk;      // cells per wave along the pencil (0: the whole pencil)
-    int x_rows;           // x pass: at least this many rows per wave
+    int x_rows;           // x pass: at least this many rows per wave (0: by the marching kernel)
 };
 
 // Number of blocks the pass along `axis` needs for one brick.
 int pass_blocks(const Geom &g, int axis, const PassShape &sh);
+
+// Estimated work of block `local` of that pass when solid cells are
+// skipped (the cells its waves march over); the block maps list a brick's
+// blocks longest first, so that the short ones fill the end of a launch.
+double pass_block_cost(const Geom &g, int axis, const PassShape &sh, int local);
 
 // Fused 1-D pass along `axis` for the bricks whose blocks are
 // map[0 .. nblocks): one launch, every brick's pencils.  With `cfl` set the
@@ -152,6 +157,13 @@ hipError_t launch_cfl_finish(const Brick *bricks, int b0, int nb, const BlockMap
 template <typename T>
 hipError_t launch_spin(const Brick *bricks, const BlockMap *map, int nblocks, T *state, const double *base64,
                        double domega, hipStream_t st);
+
+// Rotating-frame sources (Coriolis, optionally centrifugal, about the z
+// axis at omega) over each brick's dt[dti], in every fluid cell of the
+// bricks the CFL block map covers, in place.
+template <typename T>
+hipError_t launch_rotframe(const Brick *bricks, const BlockMap *map, int nblocks, T *state, const double *base64,
+                           const double *dt, double omega, int centrifugal, hipStream_t st);
 
 // Spherical-shell sums (8 per shell, FP64, fixed order) of one brick:
 // block partials and group sums in work (shell_work_doubles(g, nbins)

@@ -10,6 +10,8 @@
 // load and store of a field is one coalesced 256-byte row.
 #include "ppmb_internal.h"
 
+#include <algorithm>
+#include <cmath>
 #include <cstdlib>
 
 namespace ppmb {
@@ -232,6 +234,27 @@ struct AxisInfo {
     static __device__ __forceinline__ bool odd(int q) { return q == 1 || q == 4 || q == 6; }
 };
 
+// Rows of at most 32 pencils (along the lane axis of the marching kernel)
+// are packed whole, 64 / n rows to a wave (a row split between two waves
+// would have each of its loads touch the cache lines of two rows).
+__host__ __device__ inline bool march_packed(const Geom &g, int axis)
+{
+    return g.n[axis == 0 ? 1 : 0] <= 32;
+}
+__host__ __device__ inline int march_rows(const Geom &g, int axis)
+{
+    return march_packed(g, axis) ? 64 / g.n[axis == 0 ? 1 : 0] : 1;
+}
+
+// Waves of the marching kernel per chunk of the pencils: packed rows, or
+// columns of 64 pencils of one row.
+__host__ __device__ inline long march_waves_per_chunk(const Geom &g, int axis)
+{
+    const int ca = axis == 0 ? 1 : 0, cb = 3 - axis - ca;
+    const int R = march_rows(g, axis);
+    return march_packed(g, axis) ? (g.n[cb] + R - 1) / R : (long)((g.n[ca] + 63) / 64) * g.n[cb];
+}
+
 // March one pencil; la / lb index it across the lane and block axes;
 // gmem is the brick's grid in the brick table.
 // Conserved perturbations (rho', m along the pass, the two transverse m,
@@ -247,38 +270,48 @@ __device__ __forceinline__ void cons_of(const T *q, T rho, T rgm1, T *u)
 }
 
 template <typename T, int AX, bool DISS, bool FLAT>
-__device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, int la0, int lane, int lb, int pk,
-                      int nb, int clo, int chi, unsigned &c_lim, unsigned &c_uns, unsigned &c_rie, double &cmax,
+__device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, int la0, int lane, int lb,
+                      int clo, int chi, unsigned &c_lim, unsigned &c_uns, unsigned &c_rie, double &cmax,
                       bool &cbad)
 {
     using AI = AxisInfo<AX>;
     const int n = g.n[AX];
     const int ca = (AX == 0) ? 1 : 0;
     const int cb = 3 - AX - ca;
-    // The wave's pencils: pk rows of pencils (rows lb .. lb + nb - 1 along
-    // cb) of the brick's g.n[ca] pencils each, packed lane after lane when a
-    // row is at most half a wave (pk > 1, la0 = 0), else the 64 pencils from
-    // la0 of row lb.  Lanes past the last pencil march a copy of one and
-    // store nothing.
-    const int na = g.n[ca];
-    const int cnt = min(64, na - la0);
-    const int pr = pk > 1 ? lane / na : 0;
-    const bool valid = pk > 1 ? pr < nb : lane < cnt;
-    const int lld = pk > 1 ? lane - pr * na : (valid ? lane : cnt - 1);
-    const int lrow = pk > 1 ? (valid ? pr : nb - 1) : 0;
+    // The wave's pencils.  Rows (along cb) of g.n[ca] pencils: a row of
+    // more than 32 pencils gives waves the 64 from la0 of row lb; shorter
+    // rows are packed whole, lane after lane, rows lb .. lb + 64 / n - 1
+    // (la0 = 0).  Lanes past the last pencil march a copy of it and store
+    // nothing.
+    const int na = g.n[ca], nrow = g.n[cb];
+    const bool packed = march_packed(g, AX);
+    const int last = packed ? min(march_rows(g, AX), nrow - lb) * na - 1 : 0;
+    int lld, lrow;
+    bool valid;
+    if (packed) {
+        valid = lane <= last;
+        const int pe = valid ? lane : last;
+        lrow = pe / na;
+        lld = pe - lrow * na;
+    } else {
+        const int cnt = min(64, na - la0);
+        valid = lane < cnt;
+        lld = valid ? lane : cnt - 1;
+        lrow = 0;
+    }
     const int la = la0 + lld;
     int ijk0[3];
     ijk0[ca] = la; ijk0[cb] = lb + lrow; ijk0[AX] = 0;
     const long stride[3] = { 1, (long)g.px, g.plane };
     const long sAX = stride[AX];
-    // element index of this lane from the wave's first pencil (stride 1 for
-    // the y and z passes, nx for the x pass, rows stride[cb] apart), and the
-    // element count the wave's rows span
+    // element index of this lane from the wave's first row start (stride 1
+    // for the y and z passes, nx for the x pass, rows stride[cb] apart), and
+    // the element count the wave's pencils span (the index grows with the
+    // pencil number, so the last lane's is the largest)
     const unsigned lix = (unsigned)(lld * stride[ca] + lrow * stride[cb]);
     const unsigned lst = valid ? lix : kNoIdx;
-    const int rcnt = pk > 1 ? (int)((nb - 1) * stride[cb] + (na - 1) * stride[ca] + 1)
-                            : (int)((cnt - 1) * stride[ca] + 1);
-    // wave-uniform offset of the 64-lane row at pencil index 0
+    const int rcnt = (int)__builtin_amdgcn_readlane((int)lix, 63) + 1;
+    // wave-uniform offset of row lb's pencil la0
     const long ubase = (long)la0 * stride[ca] + (long)lb * stride[cb];
     const double xt[3] = { centre(g, 0, ijk0[0]), centre(g, 1, ijk0[1]), centre(g, 2, ijk0[2]) };
     // transverse part of |x|^2 and the fluid interval of this pencil
@@ -327,6 +360,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
     // --- register window ---------------------------------------------
     T q[5][5];            // primitives rho', u, v, w, p' of cells k-4..k
     T rr[3], cr[3];       // rho, c of cells k-2..k
+    T irr[3], icr[3];     // their reciprocals
     T b0[4], b1[4];       // base rho0, p0 of cells k-3..k
     T gr[4];              // gravity along the pass, cells k-3..k
     bool sol[5];          // solid flags of cells k-4..k
@@ -380,7 +414,8 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
         const T mn = flT * nx_mn;
         const T u = mn * ir, v = nx_m1 * ir, w = nx_m2 * ir;
         const T pp = gm1 * (nx_ep - T(0.5) * (mn * u + nx_m1 * v + nx_m2 * w));
-        const T c = tsqrt(gam * (nx_pb + pp) * ir);
+        T c, ic;
+        sound(gam * (nx_pb + pp) * ir, c, ic);
         const T pv[5] = { nx_rp, u, v, w, pp };
 #pragma unroll
         for (int vv = 0; vv < 5; ++vv) {
@@ -392,7 +427,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
             for (int r = 0; r < 3; ++r) { sm[r][vv] = T(0); d2[r][vv] = T(0); }
         }
 #pragma unroll
-        for (int r = 0; r < 3; ++r) { rr[r] = rho; cr[r] = c; }
+        for (int r = 0; r < 3; ++r) { rr[r] = rho; cr[r] = c; irr[r] = ir; icr[r] = ic; }
 #pragma unroll
         for (int r = 0; r < 4; ++r) { b0[r] = nx_r0; b1[r] = nx_pb; }
 #pragma unroll
@@ -451,7 +486,8 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
             T ir = trcp(rho);
             T u = mn * ir, v = m1 * ir, w = m2 * ir;
             T pp = gm1 * (ep - T(0.5) * (mn * u + m1 * v + m2 * w));
-            T c = tsqrt(gam * (pb + pp) * ir);
+            T c, ic;
+            sound(gam * (pb + pp) * ir, c, ic);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -459,6 +495,8 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
             q[4][0] = rp; q[4][1] = u; q[4][2] = v; q[4][3] = w; q[4][4] = pp;
             rr[0] = rr[1]; rr[1] = rr[2]; rr[2] = rho;
             cr[0] = cr[1]; cr[1] = cr[2]; cr[2] = c;
+            irr[0] = irr[1]; irr[1] = irr[2]; irr[2] = ir;
+            icr[0] = icr[1]; icr[1] = icr[2]; icr[2] = ic;
 #pragma unroll
             for (int r = 0; r < 3; ++r) { b0[r] = b0[r + 1]; b1[r] = b1[r + 1]; gr[r] = gr[r + 1]; }
 #pragma unroll
@@ -517,8 +555,8 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
                 dq[vv] = r - l;
                 q6[vv] = T(6) * (q[2][vv] - T(0.5) * (l + r));
             }
-            trace_cell(qL, qR, dq, q6, rr[0], cr[0], q[2][1], q[2][0], gr[1], r0f[0], r0f[1], p0f[0],
-                       p0f[1], nu, hdt, rdx, TL, TR);
+            trace_cell(qL, qR, dq, q6, rr[0], irr[0], cr[0], icr[0], q[2][1], q[2][0], gr[1], r0f[0], r0f[1],
+                       p0f[0], p0f[1], nu, hdt, rdx, TL, TR);
         }
         // ---- (5) Riemann problem and fluxes at face (k-3)+1/2
         T F[5];
@@ -551,11 +589,11 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
             if (a.heat) {
                 T xd = ox + (T(cu_) + T(0.5)) * dxT;
                 T zc = AX == 2 ? xd : zt;
-                if (AX != 2 && pk > 1) {
+                if (AX != 2 && packed) {
                     // the lane id from the exec mask, so that no register
                     // holds it through the march
                     const int ln = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-                    zc = T(centre(g, 2, lb + min(ln / na, nb - 1)));
+                    zc = T(centre(g, 2, lb + min(ln, last) / na));
                 }
                 hn[4] = hn[4] + heating_now<T>(gmem, zc, rtt + xd * xd) * dt;
             }
@@ -646,12 +684,7 @@ __device__ void march(const Geom &g, const Geom *gmem, const SweepArgs<T> &a, in
 // and z passes, across y for the x pass); a block holds blockDim/64 waves
 // on consecutive rows of the other transverse axis.
 // FP32: at most 256 VGPRs, two waves per SIMD; FP64 needs the full file.
-// Rows of pencils one wave of the marching kernel packs: the y and z passes
-// of a brick at most 32 cells wide in x hold 64 / nx rows per wave.
-__host__ __device__ inline int march_pack(const Geom &g, int axis)
-{
-    return (axis != 0 && g.n[0] <= 32) ? 64 / g.n[0] : 1;
-}
+
 
 // Waves of the marching kernel along a pencil of n cells: chunks of
 // `chunk` cells (0: one wave for the whole pencil).  Each wave marches its
@@ -674,20 +707,27 @@ void sweep_kernel(BatchArgs<T> b)
     const int waves = blockDim.x >> 6;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int nblk_a = (g.n[ca] + 63) / 64;
-    const int pk = march_pack(g, AX);
-    // block = (chunk along the pencils, column of 64 pencils, rows)
+    // block = (chunk along the pencils, its waves); a wave = 64 packed
+    // pencils, or a column of 64 pencils of one row
     const int nchk = march_chunks(g.n[AX], b.chunk);
     const int ck = m.local % nchk, rest = m.local / nchk;
-    const int la0 = (rest % nblk_a) * 64;
-    const int lb = ((rest / nblk_a) * waves + wv) * pk;
+    const long wq = (long)rest * waves + wv;
+    int la0, lb;
+    if (march_packed(g, AX)) {
+        la0 = 0;
+        lb = (int)(wq * march_rows(g, AX));
+    } else {
+        la0 = (int)(wq % nblk_a) * 64;
+        lb = (int)(wq / nblk_a);
+    }
     const int clen = b.chunk > 0 ? b.chunk : g.n[AX];
     const int clo = ck * clen, chi = min(clo + clen, g.n[AX]) - 1;
     unsigned c_lim = 0, c_uns = 0, c_rie = 0;          // per lane; widened below
     double cmax = 0.0;
     bool cbad = false;
     if (lb < g.n[cb])
-        march<T, AX, DISS, FLAT>(g, &B.g, a, la0, (int)(threadIdx.x & 63), lb, pk, min(pk, g.n[cb] - lb), clo, chi,
-                                 c_lim, c_uns, c_rie, cmax, cbad);
+        march<T, AX, DISS, FLAT>(g, &B.g, a, la0, (int)(threadIdx.x & 63), lb, clo, chi, c_lim, c_uns, c_rie,
+                                 cmax, cbad);
     if (b.cfl) cfl_commit(b.work, m.brick, cmax, cbad);
     // event counters: one atomic per wave and counter
     unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
@@ -918,7 +958,8 @@ void sweep_x_kernel(BatchArgs<T> b)
         q[2] = cu[2] * ir;
         q[3] = cu[3] * ir;
         q[4] = gm1 * (cu[4] - T(0.5) * (cu[1] * q[1] + cu[2] * q[2] + cu[3] * q[3]));
-        const T c = tsqrt(gam * (pb + q[4]) * ir);
+        T c, ic;
+        sound(gam * (pb + q[4]) * ir, c, ic);
 
         // (2) face values at i+1/2, second differences, limited slopes
         T qf[5], d2[5], sm[5], flm[5];
@@ -962,7 +1003,7 @@ void sweep_x_kernel(BatchArgs<T> b)
         }
         St<T> TL, TR;
         const T r0fL = from_left(r0f), p0fL = from_left(p0f);
-        trace_cell(qL, qR, dqv, q6, rho, c, q[1], q[0], gv, r0fL, r0f, p0fL, p0f, nu, hdt, rdx, TL, TR);
+        trace_cell(qL, qR, dqv, q6, rho, ir, c, ic, q[1], q[0], gv, r0fL, r0f, p0fL, p0f, nu, hdt, rdx, TL, TR);
 
         // (4) Riemann problem and fluxes at face i+1/2
         T F[5], sg;
@@ -1077,28 +1118,97 @@ void sweep_x_kernel(BatchArgs<T> b)
     }
 }
 
-// The x pass uses the lanes-along-x kernel unless PPMB_X_MARCH=1 selects
-// the marching kernel (kept for comparison; both compute the same pass).
-static bool x_lanes_enabled()
-{
-    const char *e = getenv("PPMB_X_MARCH");
-    return !(e && e[0] == '1');
-}
+// The x pass uses the lanes-along-x kernel unless the shape asks for the
+// marching kernel (x_rows = 0; both compute the same pass).
+static bool x_lanes(const PassShape &sh) { return sh.x_rows > 0; }
 
 int pass_blocks(const Geom &g, int axis, const PassShape &sh)
 {
-    if (axis == 0 && x_lanes_enabled()) {
+    if (axis == 0 && x_lanes(sh)) {
         const int nseg = (g.n[0] + kXOut - 1) / kXOut;
         const long items = (long)g.n[1] * g.n[2] * nseg;
         const long nw = (items + x_run(nseg, sh.x_rows) - 1) / x_run(nseg, sh.x_rows);   // whole rows per wave
         return (int)((nw + sh.x_waves - 1) / sh.x_waves);
     }
+    const long nw = march_waves_per_chunk(g, axis);
+    return (int)(march_chunks(g.n[axis], sh.march_chunk) * ((nw + sh.march_waves - 1) / sh.march_waves));
+}
+
+// Fluid cells of a pencil along `axis` whose transverse centre coordinates
+// are t1, t2, estimated from the sphere's chord (for ordering work only):
+// the index interval [lo, hi) it covers, clipped to the grid.
+static void chord(const Geom &g, int axis, double t1, double t2, double &lo, double &hi)
+{
+    const int n = g.n[axis];
+    lo = 0.0;
+    hi = n;
+    if (!g.sphere) return;
+    const double rt2 = t1 * t1 + t2 * t2, R2 = g.sphere_r * g.sphere_r;
+    if (!(rt2 < R2)) { lo = hi = 0.0; return; }
+    const double h = std::sqrt(R2 - rt2) / g.dx, mid = -g.origin[axis] / g.dx;
+    lo = std::max(0.0, mid - h - 1.0);
+    hi = std::min((double)n, mid + h + 1.0);
+}
+
+static double centre_h(const Geom &g, int axis, int i) { return g.origin[axis] + ((double)i + 0.5) * g.dx; }
+
+double pass_block_cost(const Geom &g, int axis, const PassShape &sh, int local)
+{
+    if (axis == 0 && x_lanes(sh)) {
+        // the x rows of the block's waves: segments of 56 cells over each
+        // row's fluid cells
+        const int nseg = (g.n[0] + kXOut - 1) / kXOut;
+        const long items = (long)g.n[1] * g.n[2] * nseg;
+        const long run = x_run(nseg, sh.x_rows);
+        double cost = 0.0;
+        for (int w = 0; w < sh.x_waves; ++w) {
+            const long it0 = ((long)local * sh.x_waves + w) * run;
+            for (long it = it0; it < std::min(it0 + run, items); it += nseg) {
+                const long r = it / nseg;
+                double lo, hi;
+                chord(g, 0, centre_h(g, 1, (int)(r % g.n[1])), centre_h(g, 2, (int)(r / g.n[1])), lo, hi);
+                if (hi > lo) cost += std::ceil((hi - lo) / kXOut) * (kXOut + 2 * NG);
+            }
+        }
+        return cost;
+    }
+    // marching waves: the widest pencil's fluid cells inside the chunk, plus
+    // the 8 cells read beyond it (sampled on a few of the wave's pencils)
     const int ca = (axis == 0) ? 1 : 0;
     const int cb = 3 - axis - ca;
-    const int pk = march_pack(g, axis);
-    const int rows = (g.n[cb] + pk - 1) / pk;          // waves per column of 64 pencils
-    return march_chunks(g.n[axis], sh.march_chunk) * ((g.n[ca] + 63) / 64) *
-           ((rows + sh.march_waves - 1) / sh.march_waves);
+    const int na = g.n[ca];
+    const int nchk = march_chunks(g.n[axis], sh.march_chunk);
+    const int clen = sh.march_chunk > 0 ? sh.march_chunk : g.n[axis];
+    const int ck = local % nchk, rest = local / nchk;
+    const int nblk_a = (na + 63) / 64;
+    const double clo = ck * clen, chi = std::min(clo + clen, (double)g.n[axis]);
+    double cost = 0.0;
+    for (int w = 0; w < sh.march_waves; ++w) {
+        const long wq = (long)rest * sh.march_waves + w;
+        double best = -1.0;
+        for (int l = 0; l < 64; l += 9) {
+            long la, lb;
+            if (march_packed(g, axis)) {
+                const long rows = march_rows(g, axis);
+                if (l >= rows * na) break;
+                la = l % na;
+                lb = wq * rows + l / na;
+                if (lb >= g.n[cb]) break;
+            } else {
+                la = (wq % nblk_a) * 64 + l;
+                lb = wq / nblk_a;
+                if (lb >= g.n[cb] || la >= na) break;
+            }
+            double t[3];
+            t[ca] = centre_h(g, ca, (int)la);
+            t[cb] = centre_h(g, cb, (int)lb);
+            double lo, hi;
+            chord(g, axis, t[(axis + 1) % 3], t[(axis + 2) % 3], lo, hi);
+            best = std::max(best, std::min(hi, chi) - std::max(lo, clo));
+        }
+        if (best > 0.0) cost += best + 2 * NG;
+    }
+    return cost;
 }
 
 template <typename T, bool D, bool F>
@@ -1128,7 +1238,7 @@ hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, cons
     const bool diss = dissk > 0.0 && div;
     BatchArgs<T> a{bricks, map, in, out, base, dt, counters, base64, work, cband, diss ? div : nullptr,
                    dissk, flat, heat, cfl, skip, sh.march_chunk, sh.x_rows};
-    const bool xl = axis == 0 && x_lanes_enabled();
+    const bool xl = axis == 0 && x_lanes(sh);
     if (diss && flat) launch_pass_kernel<T, true, true>(axis, xl, nblocks, sh, st, a);
     else if (diss) launch_pass_kernel<T, true, false>(axis, xl, nblocks, sh, st, a);
     else if (flat) launch_pass_kernel<T, false, true>(axis, xl, nblocks, sh, st, a);

@@ -35,7 +35,8 @@ EXPORTS = ("ppmb_create", "ppmb_destroy", "ppmb_state_bytes", "ppmb_state_layout
            "ppmb_ppb2d_set_nstep", "ppmb_set_spinup", "ppmb_spin_add", "ppmb_shell_profile",
            "ppmb_set_shock_dissipation", "ppmb_set_flattening", "ppmb_set_gravity",
            "ppmb_set_heating", "ppmb_set_cfl_check", "ppmb_shell_profile_noalloc",
-           "ppmb_set_solid_skip", "ppmb_set_pass_tiling", "ppmb_get_pass_tiling")
+           "ppmb_set_solid_skip", "ppmb_set_pass_tiling", "ppmb_get_pass_tiling",
+           "ppmb_set_rotating_frame", "ppmb_set_state_planes", "ppmb_get_state_planes")
 
 
 class PPMBError(RuntimeError):
@@ -128,6 +129,9 @@ def load():
         "ppmb_set_solid_skip": [p, i],
         "ppmb_set_pass_tiling": [p, i, i],
         "ppmb_get_pass_tiling": [p, ctypes.POINTER(i), ctypes.POINTER(i)],
+        "ppmb_set_rotating_frame": [p, d, i],
+        "ppmb_set_state_planes": [p, i, i, _DD],
+        "ppmb_get_state_planes": [p, i, i, _DD],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -244,6 +248,16 @@ class Sim:
         self._check(self.L.ppmb_get_state(self.h, _ptrs(out)))
         return out
 
+    def set_state_planes(self, k0, state):
+        """z-planes k0 .. k0 + nk - 1 from 15 arrays of shape (nk, ny, nx)."""
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in state]
+        self._check(self.L.ppmb_set_state_planes(self.h, int(k0), int(arrs[0].shape[0]), _ptrs(arrs)))
+
+    def get_state_planes(self, k0, nk):
+        out = [np.empty((int(nk), self.shape[1], self.shape[2])) for _ in range(NFIELDS)]
+        self._check(self.L.ppmb_get_state_planes(self.h, int(k0), int(nk), _ptrs(out)))
+        return out
+
     def get_conserved(self):
         out = [np.empty(self.shape) for _ in range(NFIELDS)]
         self._check(self.L.ppmb_get_conserved(self.h, _ptrs(out)))
@@ -342,6 +356,10 @@ class Sim:
 
     def spin_add(self, domega: float):
         self._check(self.L.ppmb_spin_add(self.h, float(domega)))
+
+    def set_rotating_frame(self, omega: float, centrifugal: bool = True):
+        """Coriolis (and centrifugal) sources of axes turning at omega about z."""
+        self._check(self.L.ppmb_set_rotating_frame(self.h, float(omega), 1 if centrifugal else 0))
 
     def shell_profile(self, nbins: int, dr: float, brick: int = 0):
         """(nbins, 8) FP64 shell sums: volume, mass, f0, rho u_r, rho u_r^2,
@@ -482,6 +500,7 @@ class Batch:
     set_solid_skip = Sim.set_solid_skip
     set_tiling = Sim.set_tiling
     tiling = Sim.tiling
+    set_rotating_frame = Sim.set_rotating_frame
 
     def set_spinup(self, omega: float, nramp: int):
         """Steps 0 .. nramp-1 each end with a solid-body rotation increment

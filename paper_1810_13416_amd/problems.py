@@ -111,10 +111,11 @@ def _lattice_dirs(rng, d: int, count: int):
 
 
 def fv_moments_quadrature(params: GridParams, func, mask=None, order: int = 4,
-                          chunk: int = 1 << 16):
+                          chunk: int = 1 << 16, k0: int = 0):
     """Cell average and 9 moments of fv = func(x, y, z) by order^3-point
     Gauss-Legendre quadrature per cell.  Only cells where `mask` is True are
-    integrated (default: all)."""
+    integrated (default: all).  k0: the grid's first z index, for a slab of
+    planes of a larger grid with the same origin."""
     g, w = np.polynomial.legendre.leggauss(order)
     s = 0.5 * g                       # nodes on [-1/2, 1/2]
     wt = 0.5 * w                      # weights summing to 1
@@ -139,12 +140,14 @@ def fv_moments_quadrature(params: GridParams, func, mask=None, order: int = 4,
         k = ii // (nx * ny)
         xc = params.origin[0] + (i + 0.5) * params.dx
         yc = params.origin[1] + (j + 0.5) * params.dx
-        zc = params.origin[2] + (k + 0.5) * params.dx
+        zc = params.origin[2] + (k + k0 + 0.5) * params.dx
         X = xc[:, None] + params.dx * xi[None, :]
         Y = yc[:, None] + params.dx * eta[None, :]
         Z = zc[:, None] + params.dx * zeta[None, :]
         F = func(X, Y, Z)                                  # (cells, P)
-        M = F @ proj.T                                     # (cells, 10)
+        # row by row, in a fixed order (a matrix product's rounding could
+        # depend on how many cells a chunk holds)
+        M = np.stack([(F * proj[q][None, :]).sum(axis=1) for q in range(10)], axis=1)
         for q in range(10):
             out[q].reshape(-1)[ii] = M[:, q]
     return out
@@ -588,3 +591,53 @@ def render_subcells(coef, sub: int = 4) -> np.ndarray:
             val = (f0 * m[0] + fx * m[1] + fy * m[2] + fxx * m[3] + fyy * m[4] + fxy * m[5]) / area
             out[b::sub, a::sub] = val
     return out
+
+
+def config3_params(n: int = 512, g0: float = 6.0) -> GridParams:
+    """The grid and physics of the spherical convection shell (config3) at
+    n^3 cells, without its state."""
+    dx = 2.0 / n
+    return GridParams(n=(n, n, n), dx=dx, origin=(-1.0, -1.0, -1.0),
+                      bc=(BC_REFLECT,) * 3, gamma=5.0 / 3.0, sphere=1, sphere_r=1.0,
+                      grav_kind=GRAV_RADIAL, grav=(g0, 0.1, 1.0 - 5 * dx, 1.0 - dx),
+                      base_kind=BASE_POLY_R,
+                      base=(1.0, 1.0, 0.0, 0.5, 0.5, math.sqrt(3.0) + dx),
+                      heat_kind=HEAT_BALL, heat=(0.1, 0.2, 0.0))
+
+
+def config3_planes(n: int, k0: int, nk: int, seed: int = 1813, g0: float = 6.0,
+                   quad_order: int = 6) -> list:
+    """Planes k0 .. k0 + nk - 1 of config3(n, seed)'s state, the same values
+    (15 arrays of shape (nk, n, n)): the velocity noise is drawn from the
+    same PCG64 stream advanced to the slab's first cell (component d of cell
+    c is draw d n^3 + c), the fv moments come from the same exact values
+    and quadrature of the cut cells.  For grids too large to hold whole."""
+    P = config3_params(n, g0)
+    S = GridParams(n=(n, n, nk), dx=P.dx, origin=P.origin, bc=P.bc, gamma=P.gamma, sphere=1, sphere_r=1.0)
+    shape = S.shape
+    c_ref = math.sqrt(P.gamma)
+    z = _centres(P, 2)[k0:k0 + nk]
+    y = _centres(P, 1)
+    x = _centres(P, 0)
+    r2 = (z * z)[:, None, None] + (y * y)[None, :, None] + (x * x)[None, None, :]
+    solid = r2 >= 1.0
+    vel = []
+    for d in range(3):
+        bg = np.random.PCG64(seed)
+        bg.advance(d * n ** 3 + k0 * n * n)
+        u = np.random.Generator(bg).uniform(-1.0, 1.0, size=shape)
+        u *= 1e-4 * c_ref
+        u[solid] = 0.0
+        vel.append(u)
+    half = 0.5 * math.sqrt(3.0) * P.dx
+    r = np.sqrt(r2)
+    cut = np.abs(r - 0.5) < half
+    fv = [np.zeros(shape) for _ in range(10)]
+    fv[0][r >= 0.5 + half] = 1.0
+    if np.any(cut):
+        def shell(X, Y, Z):
+            return (X * X + Y * Y + Z * Z >= 0.25).astype(np.float64)
+        mom = fv_moments_quadrature(S, shell, mask=cut, order=quad_order, k0=k0)
+        for q in range(10):
+            fv[q][cut] = mom[q][cut]
+    return [np.zeros(shape), *vel, np.zeros(shape), *fv]

@@ -141,6 +141,12 @@ def _calib_value(per, mib):
     return k, v
 
 
+def _median(v):
+    v = sorted(v)
+    m = len(v) // 2
+    return v[m] if len(v) % 2 else 0.5 * (v[m - 1] + v[m])
+
+
 def write_traffic(fetch_csv, write_csv, mib, cells, out_path, command):
     fe = read_counters(fetch_csv, "FETCH_SIZE")
     wr = read_counters(write_csv, "WRITE_SIZE")
@@ -150,9 +156,13 @@ def write_traffic(fetch_csv, write_csv, mib, cells, out_path, command):
     sf, sw = true_kib / cf, true_kib / cw
     alg = 2 * 15 * 4 * cells
     lines = ["# HBM traffic of the FP32 pass kernels, spherical shell 512^3", "",
-             "Counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two separate",
-             "rocprofv3 --pmc runs of the same command, scaled by what they read for",
-             f"one plain elementwise copy of {mib} MiB in and {mib} MiB out.", "",
+             "Counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch, the median over a",
+             "kernel's dispatches: the first pass after the state is set writes every",
+             "cell, later ones skip the solid cells beyond the stencil reach) from two",
+             "separate rocprofv3 --pmc runs of the same command, scaled by what they read",
+             f"for one plain elementwise copy of {mib} MiB in and {mib} MiB out.",
+             f"Algorithmic bytes: 15 fields read and written once per updated (fluid)",
+             f"cell, {cells} cells.", "",
              "Command (run once with --pmc FETCH_SIZE, once with --pmc WRITE_SIZE):", "",
              "    " + command, "",
              f"sweep_sources_sha256: {sweep_sources_hash()}",
@@ -164,8 +174,8 @@ def write_traffic(fetch_csv, write_csv, mib, cells, out_path, command):
              "|---|---|---|---|---|---|"]
     result = {}
     for k in sorted(set(fe) & set(wr)):
-        f_kib = sum(fe[k]) / len(fe[k])
-        w_kib = sum(wr[k]) / len(wr[k])
+        f_kib = _median(fe[k])
+        w_kib = _median(wr[k])
         b = (f_kib * sf + w_kib * sw) * 1024.0
         lines.append(f"| `{k}` | {len(fe[k])} | {f_kib:.0f} | {w_kib:.0f} | {b:.4g} | "
                      f"{b / alg:.3f} |")
@@ -241,7 +251,8 @@ def write_counters(out_path, title, csvs, command, only_prefix=("sweep", "cfl_ke
     names = sorted({c for cs in per.values() for c in cs})
     lines = [f"# {title}", "", "Command (one run per counter group):", "", "    " + command, "",
              f"sweep_sources_sha256: {sweep_sources_hash()}", "",
-             "Mean per dispatch.", "",
+             "Median per dispatch (the first pass after the state is set writes every",
+             "cell; later passes skip the solid cells beyond the stencil reach).", "",
              "| kernel | " + " | ".join(names) + " |", "|---|" + "---|" * len(names)]
     for k in sorted(per):
         if only_prefix and not k.startswith(only_prefix):
@@ -249,7 +260,7 @@ def write_counters(out_path, title, csvs, command, only_prefix=("sweep", "cfl_ke
         vals = []
         for c in names:
             v = per[k].get(c)
-            vals.append(f"{sum(v) / len(v):.4g}" if v else "")
+            vals.append(f"{_median(v):.4g}" if v else "")
         lines.append(f"| `{k}` | " + " | ".join(vals) + " |")
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")

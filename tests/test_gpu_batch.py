@@ -111,14 +111,18 @@ def test_launch_shape_and_autotune_change_no_bit(tmp_path):
     c0 = B.counters()
     cache = str(tmp_path / "tune.txt")
     shape = B.autotune(0.8, reps=2, cache_path=cache)
+    tiling = B.tiling()
     assert shape[0] in (1, 2, 4) and shape[1] in (1, 2, 4)
+    assert tiling[0] in (0, 128, 256) and tiling[1] in (0, 1, 2, 4)
     assert B.counters() == c0
     after = [B.get_conserved(b) for b in range(len(probs))]
     for b in range(len(probs)):
         for q in range(15):
             assert np.array_equal(before[b][q], after[b][q])
     # second call reads the cache
+    B.set_tiling(0, 1)
     assert B.autotune(0.8, reps=2, cache_path=cache) == shape
+    assert B.tiling() == tiling
     B.step(0.8, 3, mode=1)
     for b in range(len(probs)):
         for q in range(15):

@@ -139,3 +139,23 @@ def test_nonphysical_state_is_reported_after_async_steps():
     T.step_auto(0.8, 1)
     with pytest.raises(ppmb.PPMBError, match="-4"):
         T.totals()
+
+
+def test_state_by_plane_slabs_equals_whole_state():
+    # a grid filled slab by slab (the way a grid too large for one host copy
+    # of its fields is filled) holds exactly what set_state gives, and reads
+    # back slab by slab exactly as get_state does
+    prob = pr.config3(n=24)
+    A = sim(prob.params, "fp32")
+    A.set_state(prob.state)
+    B = sim(prob.params, "fp32")
+    for k0, nk in ((0, 7), (7, 10), (17, 7)):
+        B.set_state_planes(k0, [a[k0:k0 + nk] for a in prob.state])
+    for q, (a, b) in enumerate(zip(A.get_conserved(), B.get_conserved())):
+        assert np.array_equal(a, b), q
+    B.step_auto(prob.cfl, 2)
+    whole = B.get_state()
+    for k0, nk in ((0, 5), (5, 19)):
+        part = B.get_state_planes(k0, nk)
+        for q in range(15):
+            assert np.array_equal(part[q], whole[q][k0:k0 + nk]), (k0, q)

@@ -25,6 +25,7 @@ ROOT = os.path.dirname(HERE)
 SOURCES = "test_oracle_sources.py"
 PHYSICS = "test_oracle_physics.py"
 FLATTEN = "test_oracle_flatten.py"
+ROTATION = "test_oracle_rotation.py"
 
 # (name, [(fragment, replacement, occurrences)], pins that must fail)
 MUTATIONS = [
@@ -35,7 +36,9 @@ MUTATIONS = [
                      f"{SOURCES}::test_acoustic_simple_wave_order",
                      f"{PHYSICS}::test_hydrostatic_base_is_exactly_static",
                      f"{PHYSICS}::test_convergence_order_1d",
-                     f"{FLATTEN}::test_convergence_margin_ignores_rounding_and_keeps_real_compression"]),
+                     f"{FLATTEN}::test_convergence_margin_ignores_rounding_and_keeps_real_compression",
+                     f"{ROTATION}::test_inertial_oscillation_turns_velocity_at_twice_omega",
+                     f"{ROTATION}::test_rotating_frame_keeps_the_inertial_rest_state_steady"]),
     ("momentum_gravity_sign",
      [("+ dt * pc->g[J] * (0.5 * (pc->rhop[J] + rn))", "- dt * pc->g[J] * (0.5 * (pc->rhop[J] + rn))", 1)],
      [f"{SOURCES}::test_free_fall_closed_form"]),
@@ -97,6 +100,22 @@ MUTATIONS = [
      [("u[o + 2] - u[o + 4] > FLAT_TIE * (fabs(u[o + 2]) + fabs(u[o + 4]))",
        "u[o + 2] - u[o + 4] > 1e-6 * (fabs(u[o + 2]) + fabs(u[o + 4]))", 1)],
      [f"{FLATTEN}::test_convergence_margin_ignores_rounding_and_keeps_real_compression"]),
+    ("coriolis_rate_omega_not_twice",
+     [("const double th = -2.0 * om * dt", "const double th = -1.0 * om * dt", 1)],
+     [f"{ROTATION}::test_inertial_oscillation_turns_velocity_at_twice_omega"]),
+    ("coriolis_sense_reversed",
+     [("const double th = -2.0 * om * dt", "const double th = 2.0 * om * dt", 1)],
+     [f"{ROTATION}::test_inertial_oscillation_turns_velocity_at_twice_omega"]),
+    ("coriolis_as_a_kick_not_a_rotation",
+     [("double ur = cth * u - sth * v, vr = sth * u + cth * v;",
+       "double ur = u - sth * v, vr = sth * u + v;", 1)],
+     [f"{ROTATION}::test_inertial_oscillation_turns_velocity_at_twice_omega"]),
+    ("centrifugal_sign",
+     [("kick = S->rot_centrifugal ? 0.5 * om * om * dt", "kick = S->rot_centrifugal ? -0.5 * om * om * dt", 1)],
+     [f"{ROTATION}::test_rotating_frame_keeps_the_inertial_rest_state_steady"]),
+    ("centrifugal_half_dropped",
+     [("u = ur + kick * x[0];", "u = ur;", 1), ("v = vr + kick * x[1];", "v = vr;", 1)],
+     [f"{ROTATION}::test_rotating_frame_keeps_the_inertial_rest_state_steady"]),
     ("mass_flux_base_density_dropped",
      [("double rf = r0f[J] + f[0];", "double rf = f[0];", 1)],
      [f"{SOURCES}::test_moving_hydrostatic_column_converges"]),

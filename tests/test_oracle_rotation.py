@@ -158,3 +158,80 @@ def test_shell_membership_at_exact_radii():
     prof2 = O.shell_profile(2, 1.0)
     assert np.array_equal(prof2[:, 0], [1.0, 1.0])
     O.close()
+
+
+# ---------------------------------------------------------------------
+# Rotating frame (Coriolis and centrifugal source terms)
+# ---------------------------------------------------------------------
+
+def test_inertial_oscillation_turns_velocity_at_twice_omega():
+    # a uniform flow in a periodic box feels only the Coriolis term (the
+    # passes keep a uniform state exactly): du/dt = 2 omega (v, -u), so the
+    # horizontal velocity turns clockwise at the rate 2 omega, keeping its
+    # length, while u_z, the density, the pressure and the total energy stay
+    om, u0 = 0.8, np.array([0.3, -0.2, 0.1])
+    prob = pr.uniform(n=(8, 8, 8), rho=1.2, vel=tuple(u0), p=0.9)
+    O = oracle.Oracle(prob.params, threads=2)
+    O.set_state(prob.state)
+    O.set_rotating_frame(om, centrifugal=False)
+    e0 = O.totals()[4]
+    dt, nsteps = 0.01, 37
+    for _ in range(nsteps):
+        O.step(dt)
+    st = O.get_state()
+    th = -2.0 * om * dt * nsteps
+    want = (math.cos(th) * u0[0] - math.sin(th) * u0[1], math.sin(th) * u0[0] + math.cos(th) * u0[1])
+    assert np.allclose(st[1], want[0], rtol=0, atol=1e-13)
+    assert np.allclose(st[2], want[1], rtol=0, atol=1e-13)
+    assert np.allclose(st[3], u0[2], rtol=0, atol=1e-15)
+    assert np.allclose(st[0], 1.2, rtol=1e-15, atol=0) and np.allclose(st[4], 0.9, rtol=1e-13, atol=0)
+    assert abs(O.totals()[4] - e0) <= 1e-13 * e0
+    # half a period of the oscillation, pi / (2 omega): the flow reversed
+    O2 = oracle.Oracle(prob.params, threads=2)
+    O2.set_state(prob.state)
+    O2.set_rotating_frame(om, centrifugal=False)
+    for _ in range(40):
+        O2.step(math.pi / (2.0 * om) / 40)
+    st = O2.get_state()
+    assert np.allclose(st[1], -u0[0], atol=1e-13) and np.allclose(st[2], -u0[1], atol=1e-13)
+    O.close()
+    O2.close()
+
+
+def _rigid_rotation_deviation(n, om=0.5, T=0.2, centrifugal=True):
+    """Gas at rest in the inertial frame, seen from axes turning at omega:
+    a rigid rotation u = -omega z-hat x x = omega (y, -x, 0) of a uniform gas
+    in the sphere.  In the rotating frame its advection (centripetal
+    -omega^2 r) is balanced exactly by the Coriolis (-2 omega^2 r) and
+    centrifugal (+omega^2 r) terms, so it is steady.  Returns the largest
+    velocity change over time T inside r < 0.6 (away from the staircase
+    wall, whose disturbance has not arrived there yet)."""
+    prob = pr.ball(n, rho=1.0, p=1.0, fv=0.0)
+    z, y, x = np.meshgrid(*(pr._centres(prob.params, a) for a in (2, 1, 0)), indexing="ij")
+    fluid = (x * x + y * y) + z * z < 1.0
+    st = list(prob.state)
+    st[1] = np.where(fluid, om * y, 0.0)
+    st[2] = np.where(fluid, -om * x, 0.0)
+    O = oracle.Oracle(prob.params, threads=8)
+    O.set_state(st)
+    O.set_rotating_frame(om, centrifugal)
+    t = 0.0
+    while t < T - 1e-12:
+        dt = min(O.dt(0.8), T - t)
+        O.step(dt)
+        t += dt
+    g = O.get_state()
+    O.close()
+    inner = (x * x + y * y) + z * z < 0.36
+    return max(float(np.max(np.abs(g[1] - st[1])[inner])), float(np.max(np.abs(g[2] - st[2])[inner])))
+
+
+def test_rotating_frame_keeps_the_inertial_rest_state_steady():
+    # a missing or misweighted source term leaves an acceleration of order
+    # omega^2 r, a velocity change ~ 0.03 by T = 0.2 at r = 0.6 on every grid
+    e32, e64 = _rigid_rotation_deviation(32), _rigid_rotation_deviation(64)
+    print("rigid rotation in the rotating frame, max |du| inside r < 0.6:", e32, e64)
+    assert e64 <= 1e-4
+    assert e32 / e64 >= 8.0          # the deviation is truncation error
+    # the same flow with the centrifugal term left out is not steady
+    assert _rigid_rotation_deviation(32, centrifugal=False) >= 0.02
