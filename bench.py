@@ -48,6 +48,8 @@ SQ_SUMMARY = os.path.join(ROOT, "profiles", "sweep_sq_counters_shell512_fp32.md"
 # VALU issue peak without packed FP32 (disabled in every HIP unit here): 256 CUs x 4
 # SIMDs x 16 lanes per cycle x 2.4 GHz, in 10^12 lane-instructions per second
 VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
+FP32_PEAK_TFLOPS = 157.3                       # MI355X vector FP32, published (packed instructions)
+FP32_NONPACKED_TFLOPS = 2 * VALU_PEAK_T        # one FMA per lane per cycle without them
 # the kernels behind each pass of the FP32 step
 PASS_KERNELS = {"x": "sweep_x_kernel<float, false, false>", "y": "sweep_kernel<float, 1, false, false>",
                 "z": "sweep_kernel<float, 2, false, false>"}
@@ -151,19 +153,21 @@ def run_config5(n=1024, steps=20, warmup=3, slab=64):
     """The spherical shell at 1024^3 (the 512^3 recipe at half the cell
     width) in FP32 and then in FP64 on the same GPU.  Both are filled plane
     slab by plane slab (the FP64 primitives of the whole grid would take
-    129 GB of host memory), warmed up and timed alike; the FP32 state is
-    kept on the host in FP32 and compared field by field with the FP64
-    state after the same steps: relative L1 = sum |a - b| / sum |b| and
+    129 GB of host memory) and advanced by the same warmup + steps steps of
+    one fixed dt (the FP32 state's dt at Courant number 0.6), timed; the
+    FP32 state is then kept on the host in FP32 and compared field by field
+    with the FP64 state: relative L1 = sum |a - b| / sum |b| and
     relative Linf = max |a - b| / max |b| with rho and p as full fields
     (base added back), velocities against the largest speed component and
     the fv moments against f0's scale; the perturbation-relative L1 of rho'
-    and p' besides."""
+    and p' besides.  After the comparison each precision is timed for
+    `steps` more steps with dt computed on the device (the bench's step)."""
     import numpy as np
     import torch
     from paper_1810_13416_amd import ppmb, problems
     P = problems.config3_params(n)
     out = {"grid": [n] * 3, "cells": n ** 3, "steps": steps, "warmup": warmup, "tiling": list(TILING)}
-    kept, base = None, None
+    kept, base, dt = None, None, None
     slabs = [(k0, min(slab, n - k0)) for k0 in range(0, n, slab)]
     for prec, name in ((ppmb.FP32, "fp32"), (ppmb.FP64, "fp64")):
         t0 = time.perf_counter()
@@ -177,18 +181,23 @@ def run_config5(n=1024, steps=20, warmup=3, slab=64):
         S.set_tiling(*TILING)
         for k0, nk in slabs:
             S.set_state_planes(k0, problems.config3_planes(n, k0, nk))
+            log(f"config5 {name}: planes {k0}..{k0 + nk - 1} set")
         log(f"config5 {name}: state set in {time.perf_counter() - t0:.0f} s")
-        S.step_auto(0.8, warmup)
-        torch.cuda.synchronize()
+        if dt is None:
+            dt = S.dt(0.6)
+            out["dt_fixed"] = dt
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(warmup):
+            S.step(dt)
+        torch.cuda.synchronize()
         e0.record(S.stream)
-        S.step_auto(0.8, steps)
+        for _ in range(steps):
+            S.step(dt)
         e1.record(S.stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        out[name] = {"ms_per_step": ms, "cell_updates_per_s": n ** 3 / (ms * 1e-3), "dt_last": S.last_dt(),
-                     "totals": [float(v) for v in S.totals()]}
-        log(f"config5 {name}: {ms:.2f} ms/step")
+        ms_fixed = e0.elapsed_time(e1) / steps
+        tot = [float(v) for v in S.totals()]
+        log(f"config5 {name}: {ms_fixed:.2f} ms/step at fixed dt")
         if name == "fp32":
             kept = [[a.astype(np.float32) for a in S.get_state_planes(k0, nk)] for k0, nk in slabs]
             base = S.base()
@@ -221,6 +230,17 @@ def run_config5(n=1024, steps=20, warmup=3, slab=64):
             out["fp32_vs_fp64"] = err
             out["perturbation_relL1"] = {"rho'": pert[0, 0] / max(pert[0, 1], 1e-300),
                                          "p'": pert[1, 0] / max(pert[1, 1], 1e-300)}
+            log("config5: compared")
+        S.step_auto(0.8, 1)
+        torch.cuda.synchronize()
+        e0.record(S.stream)
+        S.step_auto(0.8, steps)
+        e1.record(S.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[name] = {"ms_per_step": ms, "cell_updates_per_s": n ** 3 / (ms * 1e-3),
+                     "ms_per_step_fixed_dt": ms_fixed, "dt_last": S.last_dt(), "totals_after_fixed_dt": tot}
+        log(f"config5 {name}: {ms:.2f} ms/step with device dt")
         S.close()
         del S
         torch.cuda.empty_cache()
@@ -472,9 +492,13 @@ def main():
     ap.add_argument("--tiling", type=str, default=None,
                     help="march_chunk,x_rows of the pass kernels (default: %s,%s)" % TILING)
     ap.add_argument("--config5", action="store_true",
-                    help="run the 1024^3 FP32-vs-FP64 comparison and write its summary to profiles/")
+                    help="run the 1024^3 FP32-vs-FP64 comparison and write its summary (JSON)")
+    ap.add_argument("--config5-out", default=CONFIG5_SUMMARY,
+                    help="where --config5 writes its summary (default: the committed one in profiles/)")
     ap.add_argument("--compare-skip", action="store_true",
                     help="also time the FP32 step with every pass writing every cell")
+    ap.add_argument("--bricks-only", action="store_true",
+                    help="time only the batched-brick workload and print its summary (for profiling its kernels)")
     ap.add_argument("--calib-copy-mib", type=int, default=0)
     ap.add_argument("--dissipation", type=float, default=0.1,
                     help="coefficient of the extra FP32 runs with shock handling (0: skip them)")
@@ -496,8 +520,12 @@ def main():
         res = run_config5()
         res["command"] = "python bench.py --config5"
         res["sweep_sources_sha256"] = __import__("paper_1810_13416_amd.profsum", fromlist=["x"]).sweep_sources_hash()
-        with open(CONFIG5_SUMMARY, "w") as f:
+        with open(args.config5_out, "w") as f:
             json.dump(res, f, indent=1)
+        print(json.dumps(res), flush=True)
+        return
+    if args.bricks_only:
+        res = run_bricks(args.steps, args.warmup)
         print(json.dumps(res), flush=True)
         return
     log(f"generating the {args.n}^3 shell inputs")
@@ -587,17 +615,34 @@ def main():
     }
     valu = measured_valu()
     if valu:
-        per = {}
+        # VALU issue (lane-instructions) and VALU FLOPs (an FMA counts 2, a
+        # transcendental 1) per launch, from the committed counter summary,
+        # over the live launch duration; per fluid cell, the cells updated
+        per, flop = {}, {}
         for k, v in kernels.items():
-            n = valu["kernels"].get(k, {}).get("SQ_INSTS_VALU")
+            cs = valu["kernels"].get(k, {})
+            n = cs.get("SQ_INSTS_VALU")
+            t = v["avg_launch_ms"] * 1e-3
             if n:
-                per[k] = {"valu_per_cell": 64 * n / cells,
-                          "achieved": 64 * n / (v["avg_launch_ms"] * 1e-3) / 1e12}
+                per[k] = {"valu_per_fluid_cell": 64 * n / fluid, "achieved": 64 * n / t / 1e12}
+            f = 0.0
+            for prec in ("F32", "F64"):
+                f += sum(cs.get(f"SQ_INSTS_VALU_{op}_{prec}", 0.0) for op in ("ADD", "MUL", "TRANS"))
+                f += 2.0 * cs.get(f"SQ_INSTS_VALU_FMA_{prec}", 0.0)
+            if f:
+                flop[k] = {"flop_per_fluid_cell": 64 * f / fluid, "achieved_TFLOPs": 64 * f / t / 1e12}
         if dom in per:
             out["roofline_alu"] = {"bound": "alu", "kernel": dom, "achieved": per[dom]["achieved"],
                                    "peak": VALU_PEAK_T, "unit": "T VALU lane-instructions/s",
                                    "frac": per[dom]["achieved"] / VALU_PEAK_T, "kernels": per,
                                    "source": os.path.relpath(SQ_SUMMARY, ROOT)}
+        if dom in flop:
+            out["roofline_valu_flops"] = {
+                "bound": "alu", "kernel": dom, "achieved": flop[dom]["achieved_TFLOPs"], "unit": "TFLOP/s",
+                "peak": FP32_PEAK_TFLOPS, "frac": flop[dom]["achieved_TFLOPs"] / FP32_PEAK_TFLOPS,
+                "peak_nonpacked": FP32_NONPACKED_TFLOPS,
+                "frac_nonpacked": flop[dom]["achieved_TFLOPs"] / FP32_NONPACKED_TFLOPS,
+                "kernels": flop, "source": os.path.relpath(SQ_SUMMARY, ROOT)}
     if "rotation" in r32:
         out["rotation"] = r32["rotation"]
         log(f"spin-up increment {r32['rotation']['spin_add']['ms']:.3f} ms, shell sums "
@@ -632,6 +677,8 @@ def main():
         with open(CONFIG5_SUMMARY) as f:
             c5 = json.load(f)
         c5["source"] = os.path.relpath(CONFIG5_SUMMARY, ROOT)
+        c5["taken_from_current_sources"] = c5.get("sweep_sources_sha256") == \
+            __import__("paper_1810_13416_amd.profsum", fromlist=["x"]).sweep_sources_hash()
         out["config5_1024"] = c5
     if not args.no_cpu:
         log("CPU oracle baseline")

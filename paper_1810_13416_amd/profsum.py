@@ -103,8 +103,34 @@ def write_stats(csv_path, out_path, command):
     for r in rows:
         lines.append(f"| `{r['name']}` | {r['calls']} | {r['total_ms']:.3f} | {r['avg_ms']:.4f} | "
                      f"{r['min_ms']:.4f} | {r['max_ms']:.4f} | {100 * r['total_ms'] / tot:.1f} |")
+    trace = os.path.join(os.path.dirname(csv_path), os.path.basename(csv_path).replace("kernel_stats", "kernel_trace"))
+    if trace != csv_path and os.path.exists(trace):
+        lines += _steady_table(trace)
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
+
+
+def _steady_table(trace_csv):
+    """The pass kernels' dispatches after the first of each: the first pass
+    after a state is set updates every cell (the solid cells are not yet
+    known to be equal in both buffers), the later ones only the cells within
+    the stencil reach of the fluid; these are the launches the bench times."""
+    with open(trace_csv, newline="") as f:
+        rows = list(csv.reader(f))
+    hdr, body = rows[0], rows[1:]
+    iname, i0, i1 = _col(hdr, "kernel_name"), _col(hdr, "start_timestamp"), _col(hdr, "end_timestamp")
+    per = {}
+    for r in body:
+        if r and short_name(r[iname]).startswith("sweep"):
+            per.setdefault(short_name(r[iname]), []).append(int(r[i1]) - int(r[i0]))
+    out = ["", "Pass kernels without their first dispatch (the launches the bench times):", "",
+           "| kernel | dispatches | avg ms | median ms | min ms | max ms |", "|---|---|---|---|---|---|"]
+    for k in sorted(per):
+        ns = per[k][1:]
+        if ns:
+            out.append(f"| `{k}` | {len(ns)} | {sum(ns) / len(ns) * 1e-6:.4f} | {_median(ns) * 1e-6:.4f} | "
+                       f"{min(ns) * 1e-6:.4f} | {max(ns) * 1e-6:.4f} |")
+    return out
 
 
 def read_counters(path, counter):
