@@ -419,12 +419,27 @@ ppmb_status ppmb_brick_totals(ppmb_ctx *ctx, int brick, double out[8]);
 ppmb_status ppmb_brick_last_dt(ppmb_ctx *ctx, int brick, double *dt_out);
 
 /* `nsteps` steps of every brick, each brick's dt from its own CFL condition
- * computed on the device.  mode 0: one launch per stage for all bricks;
- * 1: the same launches captured once (two steps: both pass orders) into a
- * HIP graph and replayed (recaptured if the arena, step parity or cfl
- * changed); 2: one launch per stage and brick (for comparison).  All three
- * give bitwise identical states.  Asynchronous.  Mode 1 needs a stream other
- * than the null stream (graph capture). */
+ * computed on the device (the brick-update model of Sec. 5: bricks advance
+ * independently, each on its own dt).  mode 0: one launch per stage for all
+ * bricks; 1: the same launches captured once (two steps: both pass orders)
+ * into a HIP graph and replayed (recaptured if the arena, step parity, cfl
+ * or mode changed); 2: one launch per stage and brick (for comparison);
+ * 3: one launch per step of the persistent step kernel: resident waves take
+ * work items in order (per brick: its dt from the previous step's maxima,
+ * then the waves of its three passes) from a device counter, and an item of
+ * a brick waits until the brick's pass counter shows its earlier stages
+ * done, so the passes of different bricks overlap and no launch boundary
+ * separates them; 4: mode 3 captured and replayed as in mode 1.  Modes 3
+ * and 4 cover the plain passes (no shock dissipation or flattening, x pass
+ * by its lanes-along-x kernel); otherwise they take mode 0's and mode 1's
+ * launches.  A wait of the persistent kernel that exceeds a bounded time
+ * (0.25 s) gives up; the next synchronising call then returns PPMB_ERR_HIP.
+ * Modes 3 and 4 are switched off in this build (INVALID): the persistent
+ * kernel's launches did not complete on the target GPU and the cause is not
+ * yet known.  All
+ * modes give bitwise identical states, dts and event counters.
+ * Asynchronous.  Modes 1 and 4 need a stream other than the null stream
+ * (graph capture). */
 ppmb_status ppmb_batch_step(ppmb_ctx *ctx, double cfl, int nsteps, int mode);
 
 /* Launch shape of the pass kernels: waves per block of the marching kernel

@@ -62,8 +62,12 @@ struct ppmb_ctx {
     std::vector<Timed> timed;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    int gkey_cur = -1, gkey_par = -1;
+    int gkey_cur = -1, gkey_par = -1, gkey_how = -1;
     double gkey_cfl = 0.0;
+    // persistent step (ppmb_batch_step modes 3 and 4)
+    int *sneed = nullptr;               // [parity][stage][brick]: items of the brick in earlier stages
+    unsigned long long *scnt = nullptr; // per brick items done; then next item, abort flag (fine-grained)
+    int sworkers = 0;                   // resident waves of the step kernel
     // spin-up ramp: steps 0 .. spin_nramp-1 end with + spin_omega / spin_nramp
     double spin_omega = 0.0;
     long spin_nramp = 0;
@@ -118,7 +122,7 @@ static void free_graph(ppmb_ctx *c)
     if (c->graph) hipGraphDestroy(c->graph);
     c->gexec = nullptr;
     c->graph = nullptr;
-    c->gkey_cur = c->gkey_par = -1;
+    c->gkey_cur = c->gkey_par = c->gkey_how = -1;
 }
 
 // The state of bricks [b0, b1) was written by something other than a
@@ -147,6 +151,8 @@ static void free_maps(ppmb_ctx *c)
     }
     hipFree(c->cmap);
     c->cmap = nullptr;
+    hipFree(c->sneed);
+    c->sneed = nullptr;
     hipFree(c->dmap);
     c->dmap = nullptr;
     for (int d = 0; d < 3; ++d) { hipFree(c->fmap[d]); c->fmap[d] = nullptr; }
@@ -206,6 +212,26 @@ static ppmb_status build_maps(ppmb_ctx *c)
     }
     c->cfirst[c->nb] = (int)m.size();
     TRY(upload_map(c, m, &c->cmap));
+    {
+        // persistent step: per pass order, stage and brick, the brick's
+        // items in the earlier stages (what its items of that stage wait for)
+        const int order[2][3] = { { 0, 1, 2 }, { 2, 1, 0 } };
+        std::vector<int> need((size_t)2 * kStepStages * c->nb);
+        for (int par = 0; par < 2; ++par)
+            for (int b = 0; b < c->nb; ++b) {
+                int nblk[3];
+                for (int p = 0; p < 3; ++p) nblk[p] = c->pfirst[order[par][p]][b + 1] - c->pfirst[order[par][p]][b];
+                long acc = 0;
+                for (int st = 0; st < kStepStages; ++st) {
+                    need[((size_t)par * kStepStages + st) * c->nb + b] = (int)acc;
+                    acc += step_stage_units(c->shape, st, order[par], nblk, c->cfirst[b + 1] - c->cfirst[b]);
+                }
+                if (acc > 0x7fffffff) return fail(c, PPMB_ERR_INVALID, "too many step items");
+            }
+        if (hipMalloc(&c->sneed, sizeof(int) * need.size()) != hipSuccess)
+            return fail(c, PPMB_ERR_NOMEM, "step plan allocation");
+        HIPCHK(c, hipMemcpy(c->sneed, need.data(), sizeof(int) * need.size(), hipMemcpyHostToDevice));
+    }
     m.clear();
     c->dfirst.assign(c->nb + 1, 0);
     for (int b = 0; b < c->nb; ++b) {
@@ -409,6 +435,12 @@ static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_preci
     if (e == hipSuccess) e = hipMalloc(&c->cnt, sizeof(unsigned long long) * 4);
     if (e == hipSuccess) e = hipMalloc(&c->work, sizeof(unsigned long long) * 2 * nbricks);
     if (e == hipSuccess) e = hipMalloc(&c->cband, sizeof(unsigned long long) * 2 * nbricks);
+    // the persistent step's counters are polled by waves on every XCD while
+    // the kernel runs: fine-grained memory, coherent during a kernel (what
+    // hipMalloc returns is coherent only at dispatch boundaries)
+    if (e == hipSuccess)
+        e = hipExtMallocWithFlags((void **)&c->scnt, sizeof(unsigned long long) * (nbricks + 2),
+                                  hipDeviceMallocFinegrained);
     if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * 8 * kTotalsBlocks);
     if (e == hipSuccess) e = hipMalloc(&c->out8, sizeof(double) * 8);
     if (e == hipSuccess && own_state) {
@@ -424,8 +456,10 @@ static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_preci
     if (hipMemcpy(c->db, c->hb.data(), sizeof(Brick) * nbricks, hipMemcpyHostToDevice) != hipSuccess ||
         launch_zero_u64(c->cnt, 4, c->stream) != hipSuccess ||
         launch_zero_u64(c->work, 2 * nbricks, c->stream) != hipSuccess ||
-        launch_zero_u64(c->cband, 2 * nbricks, c->stream) != hipSuccess)
+        launch_zero_u64(c->cband, 2 * nbricks, c->stream) != hipSuccess ||
+        launch_zero_u64(c->scnt, nbricks + 2, c->stream) != hipSuccess)
         st = PPMB_ERR_HIP;
+    c->sworkers = prec == PPMB_FP32 ? step_workers<float>() : step_workers<double>();
     if (st == PPMB_OK) st = build_maps(c);
     // base state NONE until set
     double zero[6] = { 0, 0, 0, 0, 0, 0 };
@@ -607,13 +641,68 @@ static ppmb_status enqueue_rotframe(ppmb_ctx *c)
     return PPMB_OK;
 }
 
-// One step of every brick: a launch per stage covering all bricks
-// (batched) or one launch per stage and brick (per_brick); during a
-// spin-up ramp the step ends with the rotation increment.
-static ppmb_status enqueue_step(ppmb_ctx *c, bool with_cfl, double cfl, bool per_brick)
+// The persistent step kernel is built but not launched (see ppmb_batch_step).
+constexpr bool kPersistentStepOn = false;
+
+// Whether the persistent step kernel can run this context's step: the
+// plain passes (no shock dissipation, no flattening) with the x pass by
+// the lanes-along-x code, and a device that holds its waves.
+static bool persistent_ok(const ppmb_ctx *c)
+{
+    return kPersistentStepOn && c->dissk == 0.0 && !c->flat_on && step_eligible(c->shape) && c->sworkers > 0;
+}
+
+// The three passes of every brick, and the step's dt from the maxima the
+// previous step left (when they describe the state), in one launch of the
+// persistent step kernel.  Without those maxima the CFL reduction runs
+// first, as its own launches.
+static ppmb_status enqueue_persistent(ppmb_ctx *c, bool with_cfl, double cfl)
+{
+    const bool ready = with_cfl && c->cfl_ready;
+    if (with_cfl && !ready) TRY(enqueue_cfl(c, cfl, 0, c->nb));
+    const int order[2][3] = { { 0, 1, 2 }, { 2, 1, 0 } };
+    const int par = (int)(c->nstep & 1);
+    const int *o = order[par];
+    const BlockMap *maps[3];
+    int nbl[3];
+    for (int p = 0; p < 3; ++p) {
+        maps[p] = c->pmap_all[o[p]];
+        nbl[p] = c->pfirst[o[p]][c->nb];
+    }
+    HIPCHK(c, launch_zero_u64(c->scnt, c->nb + 2, c->stream));
+    const int skip_first = c->skip_on && solid_all_same(c, 0, c->nb) ? 1 : 0;
+    const int heat = any_heat(c) ? 1 : 0;
+    const int *need = c->sneed + (size_t)par * kStepStages * c->nb;
+    hipError_t e;
+    if (c->prec == PPMB_FP64)
+        e = launch_step<double>(c->shape, c->db, c->nb, o, maps, nbl, c->cmap, c->cfirst[c->nb], need, c->scnt,
+                                arena<double>(c, c->cur), arena<double>(c, 1 - c->cur), c->base64, c->dt, c->cnt,
+                                heat, c->base64, c->work, c->cband, skip_first, c->skip_on ? 1 : 0, ready ? 1 : 0,
+                                cfl, c->sworkers, c->stream);
+    else
+        e = launch_step<float>(c->shape, c->db, c->nb, o, maps, nbl, c->cmap, c->cfirst[c->nb], need, c->scnt,
+                               arena<float>(c, c->cur), arena<float>(c, 1 - c->cur),
+                               static_cast<const float *>(c->baseT), c->dt, c->cnt, heat, c->base64, c->work,
+                               c->cband, skip_first, c->skip_on ? 1 : 0, ready ? 1 : 0, cfl, c->sworkers,
+                               c->stream);
+    if (e != hipSuccess) return hipfail(c, e, "step launch");
+    for (int b = 0; b < c->nb; ++b) c->solid_same[b] = 1;
+    return PPMB_OK;
+}
+
+// How a step is launched: one launch per stage for all bricks, one per
+// stage and brick, or the persistent step kernel.
+enum StepHow { kBatched = 0, kPerBrick = 1, kPersistent = 2 };
+
+// One step of every brick (see StepHow; the persistent kernel only where
+// it applies, else per stage); during a spin-up ramp the step ends with
+// the rotation increment.
+static ppmb_status enqueue_step(ppmb_ctx *c, bool with_cfl, double cfl, int how = kBatched)
 {
     const bool ready = c->cfl_ready;
-    if (per_brick) {
+    if (how == kPersistent && persistent_ok(c)) {
+        TRY(enqueue_persistent(c, with_cfl, cfl));
+    } else if (how == kPerBrick) {
         for (int b = 0; b < c->nb; ++b) {
             if (with_cfl) TRY(enqueue_dt(c, ready, cfl, b, b + 1));
             TRY(enqueue_passes(c, b, b + 1, c->cur));
@@ -637,10 +726,17 @@ static ppmb_status enqueue_step(ppmb_ctx *c, bool with_cfl, double cfl, bool per
 static ppmb_status check_flag(ppmb_ctx *c)
 {
     std::vector<unsigned long long> w(2 * c->nb);
-    unsigned long long cf = 0;
+    unsigned long long cf = 0, ab = 0;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(w.data(), c->work, sizeof(unsigned long long) * w.size(), hipMemcpyDeviceToHost));
     HIPCHK(c, hipMemcpy(&cf, c->cnt + 3, sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(&ab, c->scnt + c->nb + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    if (ab) {
+        HIPCHK(c, launch_zero_u64(c->scnt + c->nb + 1, 1, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->cfl_ready = false;
+        return fail(c, PPMB_ERR_HIP, "persistent step: a wait for another brick's items gave up; the state is invalid");
+    }
     bool bad = false;
     for (int b = 0; b < c->nb; ++b) bad = bad || w[2 * b + 1];
     if (bad) {
@@ -715,6 +811,7 @@ ppmb_status ppmb_destroy(ppmb_ctx *c)
     hipFree(c->cnt);
     hipFree(c->work);
     hipFree(c->cband);
+    hipFree(c->scnt);
     hipFree(c->partials);
     hipFree(c->out8);
     hipFree(c->shell_ws);
@@ -1034,7 +1131,7 @@ ppmb_status ppmb_step(ppmb_ctx *c, double dt)
     if (!c || !(dt > 0) || !std::isfinite(dt)) return PPMB_ERR_INVALID;
     TRY(need_state(c));
     TRY(enqueue_given_dt(c, dt));
-    return enqueue_step(c, false, 0.0, false);
+    return enqueue_step(c, false, 0.0);
 }
 
 ppmb_status ppmb_set_solid_skip(ppmb_ctx *c, int on)
@@ -1102,19 +1199,19 @@ ppmb_status ppmb_step_auto(ppmb_ctx *c, double cfl, int nsteps)
 {
     if (!c || !(cfl > 0) || nsteps < 0) return PPMB_ERR_INVALID;
     TRY(need_state(c));
-    for (int s = 0; s < nsteps; ++s) TRY(enqueue_step(c, true, cfl, false));
+    for (int s = 0; s < nsteps; ++s) TRY(enqueue_step(c, true, cfl));
     return PPMB_OK;
 }
 
 // Two steps (an even and an odd pass order) captured once into a hipGraph
 // and replayed; recaptured when the arena, the step parity or cfl differ
 // from the captured ones.  Steps inside a spin-up ramp are never captured.
-static ppmb_status graph_steps(ppmb_ctx *c, double cfl, int nsteps)
+static ppmb_status graph_steps(ppmb_ctx *c, double cfl, int nsteps, int how)
 {
     // steps of a spin-up ramp differ from one another, and the first step
     // after a state change writes every cell: launched directly
     for (; nsteps > 0 && (c->nstep < c->spin_nramp || !solid_all_same(c, 0, c->nb)); --nsteps)
-        TRY(enqueue_step(c, true, cfl, false));
+        TRY(enqueue_step(c, true, cfl, how));
     int pairs = nsteps / 2;
     if (pairs > 0) {
         // the captured steps take dt from the maxima in work[]: make them
@@ -1125,7 +1222,8 @@ static ppmb_status graph_steps(ppmb_ctx *c, double cfl, int nsteps)
             TRY(enqueue_cfl(c, cfl, 0, c->nb));
             c->cfl_ready = true;
         }
-        if (!c->gexec || c->gkey_cur != c->cur || c->gkey_par != (int)(c->nstep & 1) || c->gkey_cfl != cfl) {
+        if (!c->gexec || c->gkey_cur != c->cur || c->gkey_par != (int)(c->nstep & 1) || c->gkey_cfl != cfl ||
+            c->gkey_how != how) {
             free_graph(c);
             const int cur0 = c->cur;
             const long ns0 = c->nstep;
@@ -1133,8 +1231,8 @@ static ppmb_status graph_steps(ppmb_ctx *c, double cfl, int nsteps)
             const bool prof = c->profiling;
             c->profiling = false;
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            ppmb_status s = enqueue_step(c, true, cfl, false);
-            if (s == PPMB_OK) s = enqueue_step(c, true, cfl, false);
+            ppmb_status s = enqueue_step(c, true, cfl, how);
+            if (s == PPMB_OK) s = enqueue_step(c, true, cfl, how);
             hipError_t e = hipStreamEndCapture(c->stream, &c->graph);
             c->profiling = prof;
             c->cur = cur0;
@@ -1146,6 +1244,7 @@ static ppmb_status graph_steps(ppmb_ctx *c, double cfl, int nsteps)
             c->gkey_cur = cur0;
             c->gkey_par = (int)(ns0 & 1);
             c->gkey_cfl = cfl;
+            c->gkey_how = how;
         }
         for (int p = 0; p < pairs; ++p) {
             HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
@@ -1153,16 +1252,24 @@ static ppmb_status graph_steps(ppmb_ctx *c, double cfl, int nsteps)
             c->steps += 2;
         }
     }
-    if (nsteps % 2) TRY(enqueue_step(c, true, cfl, false));
+    if (nsteps % 2) TRY(enqueue_step(c, true, cfl, how));
     return PPMB_OK;
 }
 
 ppmb_status ppmb_batch_step(ppmb_ctx *c, double cfl, int nsteps, int mode)
 {
-    if (!c || !(cfl > 0) || nsteps < 0 || mode < 0 || mode > 2) return PPMB_ERR_INVALID;
+    if (!c || !(cfl > 0) || nsteps < 0 || mode < 0 || mode > 4) return PPMB_ERR_INVALID;
+    // The persistent step kernel (modes 3 and 4) is switched off: its
+    // launches did not complete on the target GPU and the cause is not
+    // known yet, so nothing launches it until that cause is found.
+    if ((mode == 3 || mode == 4) && !kPersistentStepOn)
+        return fail(c, PPMB_ERR_INVALID, "persistent step (modes 3, 4) is switched off: its launches did not "
+                                         "complete on the target GPU; use mode 0 or 1");
     TRY(need_state(c));
-    if (mode == 1) return graph_steps(c, cfl, nsteps);
-    for (int s = 0; s < nsteps; ++s) TRY(enqueue_step(c, true, cfl, mode == 2));
+    if (mode == 1) return graph_steps(c, cfl, nsteps, kBatched);
+    if (mode == 4) return graph_steps(c, cfl, nsteps, kPersistent);
+    const int how = mode == 2 ? kPerBrick : (mode == 3 ? kPersistent : kBatched);
+    for (int s = 0; s < nsteps; ++s) TRY(enqueue_step(c, true, cfl, how));
     return PPMB_OK;
 }
 

@@ -285,36 +285,7 @@ __global__ __launch_bounds__(256) void cfl_kernel(const Brick *bricks, const Blo
 {
     const BlockMap m = map[blockIdx.x];
     if (only && only[2 * m.brick + 1] == 0ull) return;
-    const Brick &B = bricks[m.brick];
-    const Geom g = B.g;
-    const long nc = B.ncell;
-    const T *S = arena + B.off;
-    const long fs = g.fs;
-    const double *rho0 = base64 + B.boff, *p0 = base64 + B.boff + fs;
-    const long c0 = (long)m.local * kCflBlockCells;
-    const long c1 = c0 + kCflBlockCells < nc ? c0 + kCflBlockCells : nc;
-    double smax = 0.0;
-    bool bad = false;
-    for (long c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
-        const unsigned nx = (unsigned)g.n[0], ny = (unsigned)g.n[1];
-        const unsigned row = (unsigned)c / nx, i = (unsigned)c - row * nx;
-        const unsigned k = row / ny, j = row - k * ny;
-        if (g.sphere && solid_at(g, centre(g, 0, i), centre(g, 1, j), centre(g, 2, k))) continue;
-        const long e = (long)i + (long)j * g.px + (long)k * g.plane;
-        bool b;
-        const double sp = cell_speed(rho0[e], p0[e], (double)S[RHO * fs + e], (double)S[MX * fs + e],
-                                     (double)S[MY * fs + e], (double)S[MZ * fs + e],
-                                     (double)S[EN * fs + e], g.gamma, b);
-        if (b) bad = true;
-        else if (sp > smax) smax = sp;
-    }
-    // wave64 max, then one atomic per wave (positive doubles order like their bits)
-    for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_down(smax, off));
-    unsigned long long bb = __ballot(bad);
-    if ((threadIdx.x & 63) == 0) {
-        atomicMax(&work[2 * m.brick], (unsigned long long)__double_as_longlong(smax));
-        if (bb) atomicOr(&work[2 * m.brick + 1], 1ull);
-    }
+    cfl_block_part<T>(bricks, m, arena, base64, work, (int)threadIdx.x, (int)blockDim.x);
 }
 
 __global__ void cfl_finish_kernel(const Brick *bricks, int b0, int nb, const unsigned long long *work,
@@ -329,12 +300,7 @@ __global__ void cfl_finish_kernel(const Brick *bricks, int b0, int nb, const uns
 
 __global__ void cfl_arm_kernel(unsigned long long *work, unsigned long long *cband, int b0, int nb)
 {
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        const int k = b0 + b;
-        const double prev = __longlong_as_double((long long)work[2 * k]);
-        cband[2 * k] = (unsigned long long)__double_as_longlong(prev * (1.0 - kCflBand));
-        work[2 * k] = 0ull;
-    }
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) cfl_arm_brick(work, cband, b0 + b);
 }
 
 // dt where the fused maximum reached the band edge; else clear the
@@ -342,31 +308,13 @@ __global__ void cfl_arm_kernel(unsigned long long *work, unsigned long long *cba
 __global__ void cfl_check_kernel(const Brick *bricks, int b0, int nb, unsigned long long *work,
                                  unsigned long long *cband, double cfl, double *dt)
 {
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        const int k = b0 + b;
-        const Brick &B = bricks[k];
-        const double smax = __longlong_as_double((long long)work[2 * k]);
-        const double edge = __longlong_as_double((long long)cband[2 * k]);
-        if (smax >= edge) {
-            dt[B.dti] = cfl * B.g.dx / smax;
-            cband[2 * k + 1] = 0ull;
-        } else {
-            work[2 * k] = 0ull;
-            cband[2 * k + 1] = 1ull;
-        }
-    }
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) cfl_check_brick(bricks, b0 + b, work, cband, cfl, dt);
 }
 
 __global__ void cfl_redo_finish_kernel(const Brick *bricks, int b0, int nb, const unsigned long long *work,
                                        unsigned long long *cband, double cfl, double *dt)
 {
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        const int k = b0 + b;
-        if (cband[2 * k + 1] == 0ull) continue;
-        const Brick &B = bricks[k];
-        dt[B.dti] = cfl * B.g.dx / __longlong_as_double((long long)work[2 * k]);
-        cband[2 * k + 1] = 0ull;
-    }
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) cfl_redo_finish_brick(bricks, b0 + b, work, cband, cfl, dt);
 }
 
 // Courant check of a caller-given dt: dt[dti] holds courant_max dx / smax

@@ -179,4 +179,121 @@ hipError_t launch_shell(const Geom &g, const T *state, const double *rho0, int n
 hipError_t launch_set_scalar(double *dst, double v, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long *dst, int count, hipStream_t st);
 
+// ---------------------------------------------------------------------
+// Pieces of the CFL reduction, used alike by its own kernels and by the
+// persistent step kernel, so that both give the same dt bit for bit.
+// ---------------------------------------------------------------------
+
+// Threads t, t + nthr, ... of CFL block m (nthr threads share the block):
+// the FP64 maximum of |u_d| + c over their fluid cells and the
+// non-physical flag, folded per wave into work[2 brick] (positive doubles
+// order like their bits) and work[2 brick + 1].  Every lane of the wave
+// calls it.
+template <typename T>
+__device__ __forceinline__ void cfl_block_part(const Brick *bricks, BlockMap m, const T *arena,
+                                               const double *base64, unsigned long long *work, int t, int nthr)
+{
+    const Brick &B = bricks[m.brick];
+    const Geom g = B.g;
+    const long nc = B.ncell;
+    const T *S = arena + B.off;
+    const long fs = g.fs;
+    const double *rho0 = base64 + B.boff, *p0 = base64 + B.boff + fs;
+    const long c0 = (long)m.local * kCflBlockCells;
+    const long c1 = c0 + kCflBlockCells < nc ? c0 + kCflBlockCells : nc;
+    double smax = 0.0;
+    bool bad = false;
+    for (long c = c0 + t; c < c1; c += nthr) {
+        const unsigned nx = (unsigned)g.n[0], ny = (unsigned)g.n[1];
+        const unsigned row = (unsigned)c / nx, i = (unsigned)c - row * nx;
+        const unsigned k = row / ny, j = row - k * ny;
+        if (g.sphere && solid_at(g, centre(g, 0, i), centre(g, 1, j), centre(g, 2, k))) continue;
+        const long e = (long)i + (long)j * g.px + (long)k * g.plane;
+        bool b;
+        const double sp = cell_speed(rho0[e], p0[e], (double)S[RHO * fs + e], (double)S[MX * fs + e],
+                                     (double)S[MY * fs + e], (double)S[MZ * fs + e],
+                                     (double)S[EN * fs + e], g.gamma, b);
+        if (b) bad = true;
+        else if (sp > smax) smax = sp;
+    }
+    for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_down(smax, off));
+    const unsigned long long bb = __ballot(bad);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&work[2 * m.brick], (unsigned long long)__double_as_longlong(smax));
+        if (bb) atomicOr(&work[2 * m.brick + 1], 1ull);
+    }
+}
+
+// Brick k after the fused reduction of its last pass: dt where the maximum
+// reached the band edge, else clear the maximum and raise the redo flag.
+__device__ __forceinline__ void cfl_check_brick(const Brick *bricks, int k, unsigned long long *work,
+                                                unsigned long long *cband, double cfl, double *dt)
+{
+    const Brick &B = bricks[k];
+    const double smax = __longlong_as_double((long long)work[2 * k]);
+    const double edge = __longlong_as_double((long long)cband[2 * k]);
+    if (smax >= edge) {
+        dt[B.dti] = cfl * B.g.dx / smax;
+        cband[2 * k + 1] = 0ull;
+    } else {
+        work[2 * k] = 0ull;
+        cband[2 * k + 1] = 1ull;
+    }
+}
+
+// Brick k after its redo reduction (if its flag is raised): dt, flag cleared.
+__device__ __forceinline__ void cfl_redo_finish_brick(const Brick *bricks, int k, const unsigned long long *work,
+                                                      unsigned long long *cband, double cfl, double *dt)
+{
+    if (cband[2 * k + 1] == 0ull) return;
+    const Brick &B = bricks[k];
+    dt[B.dti] = cfl * B.g.dx / __longlong_as_double((long long)work[2 * k]);
+    cband[2 * k + 1] = 0ull;
+}
+
+// Brick k before the pass that reduces: band edge from the maximum of the
+// state the pass starts from, then that maximum cleared.
+__device__ __forceinline__ void cfl_arm_brick(unsigned long long *work, unsigned long long *cband, int k)
+{
+    const double prev = __longlong_as_double((long long)work[2 * k]);
+    cband[2 * k] = (unsigned long long)__double_as_longlong(prev * (1.0 - kCflBand));
+    work[2 * k] = 0ull;
+}
+
+// ---------------------------------------------------------------------
+// Persistent step: the three passes of every brick (and the dt of the
+// step, from the maxima its previous step's last pass left) in one launch
+// of resident waves that take work items in order from a counter.  Stages,
+// in item order:
+//   0 check (one item per brick)         4 pass order[0] (its waves)
+//   1 redo reduction (4 per CFL block)   5 pass order[1]
+//   2 finish (one per brick)             6 pass order[2] (fused reduction)
+//   3 arm (one per brick)
+// An item of brick b waits until cnt[b] counts every item of b in the
+// earlier stages (need[stage * nb + b]); items only wait on items of lower
+// index, which were taken earlier by running waves, so the waits end
+// without any assumption on how many waves are resident.  A wait that
+// outlasts a bounded time raises ctl[1] and gives up (the step's result is
+// then invalid, reported by the next synchronising call).  cnt[0 .. nb)
+// and ctl = cnt + nb (2 words) must be zero at launch, in memory that is
+// coherent while a kernel runs (fine-grained).  The passes go
+// a0 -> a1 -> a0 -> a1 (the state starts in a0 and ends in a1); the redo
+// reduction reads a0.
+// ---------------------------------------------------------------------
+constexpr int kStepStages = 7;
+template <typename T>
+hipError_t launch_step(const PassShape &sh, const Brick *bricks, int nb, const int order[3],
+                       const BlockMap *const maps[3], const int nblocks[3], const BlockMap *cmap, int ncblocks,
+                       const int *need, unsigned long long *cnt, T *a0, T *a1, const T *base,
+                       double *dt, unsigned long long *counters, int heat, const double *base64,
+                       unsigned long long *work, unsigned long long *cband, int skip_first, int skip, int ready,
+                       double cfl, int workers, hipStream_t st);
+// units (waves or items) of brick b's stage s of a persistent step, from
+// its block counts per pass and CFL blocks
+long step_stage_units(const PassShape &sh, int stage, const int order[3], const int nblk_b[3], int ncb_b);
+// resident waves for the persistent step kernel of this precision
+template <typename T>
+int step_workers();
+bool step_eligible(const PassShape &sh);
+
 }  // namespace ppmb

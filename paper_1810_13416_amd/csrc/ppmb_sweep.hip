@@ -694,18 +694,15 @@ __host__ __device__ inline int march_chunks(int n, int chunk)
     return chunk > 0 ? (n + chunk - 1) / chunk : 1;
 }
 
+// Wave wv of the `waves` waves of marching block m.
 template <typename T, int AX, bool DISS, bool FLAT>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1)
-void sweep_kernel(BatchArgs<T> b)
+__device__ __forceinline__ void march_wave(const BatchArgs<T> &b, const BlockMap m, int wv, int waves)
 {
-    const BlockMap m = b.map[blockIdx.x];
     const Brick &B = b.bricks[m.brick];
     const Geom g = B.g;
     const SweepArgs<T> a = brick_args(b, B, m.brick);
     const int ca = (AX == 0) ? 1 : 0;
     const int cb = 3 - AX - ca;
-    const int waves = blockDim.x >> 6;
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int nblk_a = (g.n[ca] + 63) / 64;
     // block = (chunk along the pencils, its waves); a wave = 64 packed
     // pencils, or a column of 64 pencils of one row
@@ -741,6 +738,14 @@ void sweep_kernel(BatchArgs<T> b)
         if (s1) atomicAdd(&a.counters[1], s1);
         if (s2) atomicAdd(&a.counters[2], s2);
     }
+}
+
+template <typename T, int AX, bool DISS, bool FLAT>
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1)
+void sweep_kernel(BatchArgs<T> b)
+{
+    march_wave<T, AX, DISS, FLAT>(b, b.map[blockIdx.x], __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)),
+                                  (int)(blockDim.x >> 6));
 }
 
 // ---------------------------------------------------------------------
@@ -844,12 +849,11 @@ __device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, 
 // so that each wave has enough work; the loads of the next segment (of the
 // same or the next row) are issued before the current one is computed, so
 // their latency hides behind the arithmetic.
+// Wave wv (counted over the brick's x-pass waves) of x block m.
 template <typename T, bool DISS, bool FLAT>
-__global__ __launch_bounds__(256)
-void sweep_x_kernel(BatchArgs<T> b)
+__device__ __forceinline__ void x_wave(const BatchArgs<T> &b, const BlockMap m, const int wv)
 {
     using AI = AxisInfo<0>;
-    const BlockMap m = b.map[blockIdx.x];
     const Brick &B = b.bricks[m.brick];
     const Geom g = B.g;
     const SweepArgs<T> a = brick_args(b, B, m.brick);
@@ -860,7 +864,6 @@ void sweep_x_kernel(BatchArgs<T> b)
     const int nseg = (nx + kXOut - 1) / kXOut;
     const int items = ny * nz * nseg;
     const int run = x_run(nseg, b.x_rows);
-    const int wv = m.local * (int)(blockDim.x >> 6) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int it0 = wv * run;                          // whole rows: it0 is a row start
     if (it0 >= items) return;                          // whole waves only
     const int it1 = min(it0 + run, items);
@@ -1118,6 +1121,15 @@ void sweep_x_kernel(BatchArgs<T> b)
     }
 }
 
+template <typename T, bool DISS, bool FLAT>
+__global__ __launch_bounds__(256)
+void sweep_x_kernel(BatchArgs<T> b)
+{
+    const BlockMap m = b.map[blockIdx.x];
+    x_wave<T, DISS, FLAT>(b, m, m.local * (int)(blockDim.x >> 6) +
+                                    __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)));
+}
+
 // The x pass uses the lanes-along-x kernel unless the shape asks for the
 // marching kernel (x_rows = 0; both compute the same pass).
 static bool x_lanes(const PassShape &sh) { return sh.x_rows > 0; }
@@ -1210,6 +1222,209 @@ double pass_block_cost(const Geom &g, int axis, const PassShape &sh, int local)
     }
     return cost;
 }
+
+// ---------------------------------------------------------------------
+// Persistent step: one launch of resident waves for the three passes of
+// every brick and the dt of the step (stages and waits as declared with
+// launch_step).  An item is one wave's share of a stage: the same code and
+// the same block maps as the per-stage launches, so the result is the same
+// bit for bit.
+// ---------------------------------------------------------------------
+
+template <typename T>
+struct StepArgs {
+    BatchArgs<T> common;          // what the three passes share (arenas, maps and flags set per pass)
+    T *a0;                        // the state the step starts from; passes go a0 -> a1 -> a0 -> a1
+    T *a1;
+    const BlockMap *map0, *map1, *map2;
+    const BlockMap *cmap;         // CFL blocks (redo reduction)
+    const int *need;              // [stage * nb + brick]
+    unsigned long long *cnt;      // [nb] items done per brick; then next item, abort flag
+    double *dt;
+    double cfl;
+    long first[kStepStages + 1];  // item where each stage starts
+    int ax0, ax1, ax2;            // pass axes in step order
+    int w0, w1, w2;               // waves per block of each pass's map
+    int nb;
+    int heat;
+    int skip_first;               // first pass: solid cells alike in both arenas
+    int ready;                    // the maxima in work[] describe a0: stages 0-2 give dt
+};
+
+// Bounded wait: a wait gives up after 0.25 s of real time (the 100 MHz
+// real-time counter); a wait in a working step lasts at most one pass.
+constexpr unsigned long long kStepWaitTicks = 25000000ull;
+
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Wait (the whole wave, polling one word) until *c reaches `need` or the
+// step is abandoned, then acquire: the writes of the counted items are
+// visible to this wave.
+__device__ __forceinline__ void step_wait(unsigned long long *c, unsigned long long need, unsigned long long *abort)
+{
+    if (need == 0) return;
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+        if (uniform_u64(__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >= need) break;
+        if (uniform_u64(__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) break;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > kStepWaitTicks) {
+            if ((threadIdx.x & 63) == 0) __hip_atomic_store(abort, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(4);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Release this wave's writes, then count its item done.
+__device__ __forceinline__ void step_done(unsigned long long *c)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_add(c, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1)
+void step_kernel(StepArgs<T> P)
+{
+    unsigned long long *ctl = P.cnt + P.nb;
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned long long it = 0;
+        if (lane == 0) it = __hip_atomic_fetch_add(&ctl[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        it = uniform_u64(it);
+        if (it >= (unsigned long long)P.first[kStepStages]) break;
+        // the stage: the last one starting at or before the item (an empty
+        // stage starts where the next one does)
+        int s = 0;
+        long s0 = 0;
+#pragma unroll
+        for (int k = 1; k < kStepStages; ++k)
+            if (it >= (unsigned long long)P.first[k]) {
+                s = k;
+                s0 = P.first[k];
+            }
+        const long j = (long)it - s0;
+        const int p = s - 4;                             // pass in step order (stages 4-6)
+        const int w = p == 0 ? P.w0 : (p == 1 ? P.w1 : P.w2);
+        const BlockMap *pm = p == 0 ? P.map0 : (p == 1 ? P.map1 : P.map2);
+        BlockMap m{ (int)j, 0 };
+        if (s == 1) m = P.cmap[j >> 2];
+        else if (s >= 4) m = pm[j / w];
+        const int brick = __builtin_amdgcn_readfirstlane(m.brick);
+        m.brick = brick;
+        m.local = __builtin_amdgcn_readfirstlane(m.local);
+        step_wait(&P.cnt[brick], (unsigned long long)P.need[(long)s * P.nb + brick], &ctl[1]);
+        const BatchArgs<T> &c0 = P.common;
+        if (s == 0) {
+            if (P.ready && lane == 0) cfl_check_brick(c0.bricks, brick, c0.work, const_cast<unsigned long long *>(c0.cband), P.cfl, P.dt);
+        } else if (s == 1) {
+            if (P.ready && c0.cband[2 * brick + 1] != 0ull)
+                cfl_block_part<T>(c0.bricks, m, P.a0, c0.base64, c0.work, (int)(j & 3) * 64 + lane, 256);
+        } else if (s == 2) {
+            if (P.ready && lane == 0) cfl_redo_finish_brick(c0.bricks, brick, c0.work, const_cast<unsigned long long *>(c0.cband), P.cfl, P.dt);
+        } else if (s == 3) {
+            if (lane == 0) cfl_arm_brick(c0.work, const_cast<unsigned long long *>(c0.cband), brick);
+        } else {
+            BatchArgs<T> b = c0;
+            b.in = p == 1 ? P.a1 : P.a0;
+            b.out = p == 1 ? P.a0 : P.a1;
+            b.map = pm;
+            b.cfl = p == 2 ? 1 : 0;
+            b.heat = p == 2 ? P.heat : 0;
+            b.skip = p == 0 ? P.skip_first : c0.skip;
+            const int ax = p == 0 ? P.ax0 : (p == 1 ? P.ax1 : P.ax2);
+            const int wv = (int)(j % w);
+            if (ax == 0) x_wave<T, false, false>(b, m, m.local * w + wv);
+            else if (ax == 1) march_wave<T, 1, false, false>(b, m, wv, w);
+            else march_wave<T, 2, false, false>(b, m, wv, w);
+        }
+        step_done(&P.cnt[brick]);
+    }
+}
+
+bool step_eligible(const PassShape &sh) { return sh.x_rows > 0; }
+
+long step_stage_units(const PassShape &sh, int stage, const int order[3], const int nblk_b[3], int ncb_b)
+{
+    switch (stage) {
+    case 0: case 2: case 3: return 1;
+    case 1: return 4L * ncb_b;
+    default: {
+        const int ax = order[stage - 4];
+        return (long)nblk_b[stage - 4] * (ax == 0 ? sh.x_waves : sh.march_waves);
+    }
+    }
+}
+
+template <typename T>
+int step_workers()
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, step_kernel<T>, 64, 0) != hipSuccess) return 0;
+    return cus * per;
+}
+
+template <typename T>
+hipError_t launch_step(const PassShape &sh, const Brick *bricks, int nb, const int order[3],
+                       const BlockMap *const maps[3], const int nblocks[3], const BlockMap *cmap, int ncblocks,
+                       const int *need, unsigned long long *cnt, T *a0, T *a1, const T *base,
+                       double *dt, unsigned long long *counters, int heat, const double *base64,
+                       unsigned long long *work, unsigned long long *cband, int skip_first, int skip, int ready,
+                       double cfl, int workers, hipStream_t st)
+{
+    if (nb <= 0 || workers <= 0 || !step_eligible(sh)) return hipErrorInvalidValue;
+    StepArgs<T> P{};
+    P.common = BatchArgs<T>{ bricks, nullptr, nullptr, nullptr, base, dt, counters, base64, work, cband,
+                             nullptr, 0.0, nullptr, 0, 0, skip, sh.march_chunk, sh.x_rows };
+    P.a0 = a0;
+    P.a1 = a1;
+    P.map0 = maps[0];
+    P.map1 = maps[1];
+    P.map2 = maps[2];
+    P.cmap = cmap;
+    P.need = need;
+    P.cnt = cnt;
+    P.dt = dt;
+    P.cfl = cfl;
+    P.ax0 = order[0];
+    P.ax1 = order[1];
+    P.ax2 = order[2];
+    P.w0 = order[0] == 0 ? sh.x_waves : sh.march_waves;
+    P.w1 = order[1] == 0 ? sh.x_waves : sh.march_waves;
+    P.w2 = order[2] == 0 ? sh.x_waves : sh.march_waves;
+    P.nb = nb;
+    P.heat = heat;
+    P.skip_first = skip_first;
+    P.ready = ready;
+    const long units[kStepStages] = { nb, 4L * ncblocks, nb, nb, (long)nblocks[0] * P.w0,
+                                      (long)nblocks[1] * P.w1, (long)nblocks[2] * P.w2 };
+    P.first[0] = 0;
+    for (int s = 0; s < kStepStages; ++s) P.first[s + 1] = P.first[s] + units[s];
+    const long grid = std::min<long>(workers, P.first[kStepStages]);
+    hipLaunchKernelGGL((step_kernel<T>), dim3((unsigned)grid), dim3(64), 0, st, P);
+    return hipGetLastError();
+}
+
+template hipError_t launch_step<float>(const PassShape &, const Brick *, int, const int[3], const BlockMap *const[3],
+                                       const int[3], const BlockMap *, int, const int *, unsigned long long *,
+                                       float *, float *, const float *, double *, unsigned long long *, int,
+                                       const double *, unsigned long long *, unsigned long long *, int, int, int,
+                                       double, int, hipStream_t);
+template hipError_t launch_step<double>(const PassShape &, const Brick *, int, const int[3],
+                                        const BlockMap *const[3], const int[3], const BlockMap *, int, const int *,
+                                        unsigned long long *, double *, double *, const double *, double *,
+                                        unsigned long long *, int, const double *, unsigned long long *,
+                                        unsigned long long *, int, int, int, double, int, hipStream_t);
+template int step_workers<float>();
+template int step_workers<double>();
 
 template <typename T, bool D, bool F>
 static void launch_pass_kernel(int axis, bool xl, int nblocks, const PassShape &sh, hipStream_t st,

@@ -464,7 +464,8 @@ class Batch:
 
     def step(self, cfl, nsteps, mode=0):
         """mode 0: one launch per stage for all bricks; 1: replayed hipGraph;
-        2: one launch per stage and brick."""
+        2: one launch per stage and brick; 3: one launch of the persistent
+        step kernel per step; 4: mode 3 replayed from a hipGraph."""
         self._check(self.L.ppmb_batch_step(self.h, float(cfl), int(nsteps), int(mode)))
 
     def set_shape(self, march_waves, x_waves):

@@ -127,3 +127,15 @@ def test_launch_shape_and_autotune_change_no_bit(tmp_path):
     for b in range(len(probs)):
         for q in range(15):
             assert np.array_equal(B.get_conserved(b)[q], ref[b][q])
+
+
+def test_persistent_modes_are_switched_off():
+    # modes 3 and 4 (the persistent step kernel) return INVALID before any
+    # launch while that kernel is switched off
+    from paper_1810_13416_amd import ppmb
+    B = make_batch(small_bricks(count=3, seed=2), "fp32")
+    for mode in (3, 4):
+        with pytest.raises(ppmb.PPMBError, match="-1"):
+            B.step(0.8, 1, mode=mode)
+    B.step(0.8, 1, mode=0)
+    B.synchronize()
