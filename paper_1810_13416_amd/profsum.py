@@ -180,15 +180,15 @@ def write_traffic(fetch_csv, write_csv, mib, cells, out_path, command):
     _, cw = _calib_value(wr, mib)
     true_kib = mib * 1024.0
     sf, sw = true_kib / cf, true_kib / cw
-    alg = 2 * 15 * 4 * cells
+    alg = (2 * 15 + 2) * 4 * cells
     lines = ["# HBM traffic of the FP32 pass kernels, spherical shell 512^3", "",
              "Counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch, the median over a",
              "kernel's dispatches: the first pass after the state is set writes every",
              "cell, later ones skip the solid cells beyond the stencil reach) from two",
              "separate rocprofv3 --pmc runs of the same command, scaled by what they read",
              f"for one plain elementwise copy of {mib} MiB in and {mib} MiB out.",
-             f"Algorithmic bytes: 15 fields read and written once per updated (fluid)",
-             f"cell, {cells} cells.", "",
+             f"Algorithmic bytes: 15 fields read and written once and the base rho0 and",
+             f"p0 read once per updated (fluid) cell, {cells} cells.", "",
              "Command (run once with --pmc FETCH_SIZE, once with --pmc WRITE_SIZE):", "",
              "    " + command, "",
              f"sweep_sources_sha256: {sweep_sources_hash()}",
