@@ -771,11 +771,13 @@ __host__ __device__ __forceinline__ int x_run(int nseg, int min_rows)
 
 // Neighbour values inside the wave by DPP whole-wave shifts (wave_shr:1,
 // wave_shl:1): a VALU move, no LDS round trip.  The lane at the wave's edge
-// keeps its own value, so every lane holds a physical state.
+// reads zero (bound_ctrl): its results are halo, outside every owned
+// cell's dependency cone, and with no old value to keep the shift needs no
+// register copy and can fold into the instruction that uses it.
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v)
 {
-    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, true);
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp_v(float v)
@@ -1019,8 +1021,8 @@ __device__ __forceinline__ void x_wave(const BatchArgs<T> &b, const BlockMap m, 
             if constexpr (DISS) {
                 // shock dissipation across a face between fluid cells; the
                 // neighbour's divergence is read on every lane (a DPP read
-                // from a lane masked off by a branch returns the reader's own
-                // value), then the wall faces are zeroed
+                // from a lane masked off by a branch would not return the
+                // neighbour's value), then the wall faces are zeroed
                 const T dvr = from_right(dv);
                 const T nv = (so || sb) ? T(0) : a.dissk * tmax(T(0), T(-0.5) * (dv + dvr));
 #pragma unroll
