@@ -142,14 +142,17 @@ __device__ __forceinline__ double grav_taper(const Geom &g, double r)
 template <typename T, typename C>
 __device__ __forceinline__ T gravity(int kind, const C *c, int axis, T xd, T rt2)
 {
-    if (kind == 1) return c[axis];
+    // every constant is read before any branch, so that the loads are
+    // issued together and waited for once
+    const T c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5];
+    if (kind == 1) return axis == 0 ? c0 : (axis == 1 ? c1 : c2);
     if (kind == 2) {
         // r and 1/r^3 from one reciprocal square root (r = 0 at the centre)
         const T ir = trsq(rt2);
         const T r = rt2 > T(0) ? rt2 * ir : T(0);
-        T h = (r < c[1]) ? T(c[2]) : (c[1] * c[1]) * (ir * ir * ir);
-        T t = r <= c[3] ? T(1) : (r >= c[4] ? T(0) : (c[4] - r) * c[5]);
-        return -c[0] * xd * h * t;
+        T h = (r < c1) ? c2 : (c1 * c1) * (ir * ir * ir);
+        T t = r <= c3 ? T(1) : (r >= c4 ? T(0) : (c4 - r) * c5);
+        return -c0 * xd * h * t;
     }
     return T(0);
 }
@@ -168,8 +171,9 @@ __device__ __forceinline__ T heat_shape(T xi)
 template <typename T, typename C>
 __device__ __forceinline__ T heating(int kind, const C *c, T z, T rt2)
 {
-    if (kind == 1) return c[0] * heat_shape((z - c[2]) * c[1]);
-    if (kind == 2) return c[0] * heat_shape(tsqrt(rt2) * c[1]);
+    const T c0 = c[0], c1 = c[1], c2 = c[2];       // read before any branch, as in gravity
+    if (kind == 1) return c0 * heat_shape((z - c2) * c1);
+    if (kind == 2) return c0 * heat_shape(tsqrt(rt2) * c1);
     return T(0);
 }
 
