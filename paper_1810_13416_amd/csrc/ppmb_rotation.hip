@@ -170,7 +170,7 @@ template <typename T>
 __global__ __launch_bounds__(64) void shell_kernel(Geom g, const T *S, const double *rho0, int nbins,
                                                    double dr, int rows_per_block, double *work)
 {
-    extern __shared__ double bins[];           // nbins * 8
+    extern __shared__ double bins[];           // 8 * nbins, quantity-major: bins[q * nbins + shell]
     const int lane = threadIdx.x;
     for (int q = lane; q < nbins * 8; q += 64) bins[q] = 0.0;
     __syncthreads();
@@ -262,16 +262,19 @@ __global__ __launch_bounds__(64) void shell_kernel(Geom g, const T *S, const dou
         const bool last = key >= 0 && (lane == 63 || knext != key);
         for (int side = 0; side < 2; ++side) {
             if (last && (key & 1) == side) {
+                // the runs' shells are consecutive along a side, so the
+                // lanes of one update hit consecutive doubles (no bank
+                // conflicts beyond those of a plain row access)
                 const int b = key >> 1;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) bins[b * 8 + q] += v[q];
+                for (int q = 0; q < 8; ++q) bins[q * nbins + b] += v[q];
             }
         }
         cur = nxt;
     }
     __syncthreads();
     double *P = work + (long)blockIdx.x * nbins * 8;
-    for (int q = lane; q < nbins * 8; q += 64) P[q] = bins[q];
+    for (int t = lane; t < nbins * 8; t += 64) P[t] = bins[(t & 7) * nbins + (t >> 3)];   // out: 8 shell + quantity
 }
 
 // Block partials are added in two fixed levels: groups of kShellGroup
