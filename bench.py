@@ -22,7 +22,9 @@ The JSON carries
   bricks        256 independent bricks (16..64 cells per axis) advanced
                 together in FP32: one launch per stage for all bricks, the
                 same replayed from a HIP graph, and one launch per stage and
-                brick, after the launch-shape autotuner;
+                brick, after the launch-shape autotuner; the same bricks in
+                FP64, and the FP32 batch against the FP64 one after the same
+                fixed-dt steps;
   accuracy      the stratified box at 128^3 in FP32 and FP64 against the
                 same at 256^3 in FP64 (fixed dt, restricted to 128^3): the
                 FP32 round-off error against the truncation error;
@@ -292,8 +294,9 @@ def calib_copy(mib):
     torch.cuda.empty_cache()
 
 
-def run_bricks(steps, warmup):
-    """The batched-brick workload in each launch mode (FP32)."""
+def run_bricks(steps, warmup, fp64=True):
+    """The batched-brick workload in each launch mode (FP32), and with
+    `fp64` the same in FP64 against it."""
     import numpy as np
     import torch
     from paper_1810_13416_amd import ppmb, problems
@@ -328,7 +331,79 @@ def run_bricks(steps, warmup):
         B.close()
         del B
         torch.cuda.empty_cache()
+    if fp64:
+        out["fp64"] = run_bricks_fp64(probs, cells, steps, warmup, cfl, shape, tiling)
+        out["fp64"]["speedup_fp32_batched_over_fp64"] = \
+            out["fp64"]["ms_per_step"] / out["modes"]["batched"]["ms_per_step"]
     return out
+
+
+def run_bricks_fp64(probs, cells, steps, warmup, cfl, shape, tiling, nfixed=10):
+    """The bricks in FP64: the batched step's time, and the FP32 batch
+    against the FP64 one after the same `nfixed` steps of one fixed dt (half
+    the smallest brick dt at Courant 0.8 of the FP64 initial state): per
+    field the relative L1 difference of the conserved fields (the fv
+    moments against f0's scale, momenta against the momentum vector's),
+    the largest over the bricks."""
+    import numpy as np
+    import torch
+    from paper_1810_13416_amd import ppmb
+    nb = len(probs)
+
+    def batch(prec):
+        B = ppmb.Batch([p.params for p in probs], prec)
+        for b, p in enumerate(probs):
+            B.set_state(b, p.state)
+        B.set_shape(*shape)
+        B.set_tiling(*tiling)
+        return B
+    B = batch(ppmb.FP64)
+    B.step(cfl, warmup, 0)
+    B.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(B.stream)
+    B.step(cfl, steps, 0)
+    e1.record(B.stream)
+    B.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    log(f"bricks fp64 batched: {ms:.3f} ms/step")
+    B.close()
+    del B
+    # equal accuracy: both precisions over the same fixed-dt steps
+    T = batch(ppmb.FP64)
+    T.step(cfl, 1, 0)
+    dt = 0.5 * min(T.last_dt(b) for b in range(nb))
+    T.close()
+    del T
+    # fresh batches: both start at step 0 (the pass order alternates with
+    # the step number)
+    R = batch(ppmb.FP64)
+    A = batch(ppmb.FP32)
+    for _ in range(nfixed):
+        A.step_dt(dt)
+        R.step_dt(dt)
+    A.synchronize()
+    R.synchronize()
+    kinds = sorted(set(p.name for p in probs))
+    worst = {k: np.zeros(15) for k in kinds}
+    for b in range(nb):
+        a, r = A.get_conserved(b), R.get_conserved(b)
+        w = worst[probs[b].name]
+        for q in range(15):
+            grp = [5] if q >= 5 else ([1, 2, 3] if q in (1, 2, 3) else [q])
+            s1 = sum(float(np.sum(np.abs(r[x]))) for x in grp) / len(grp)
+            w[q] = max(w[q], float(np.sum(np.abs(a[q] - r[q]))) / max(s1, 1e-300))
+    A.close()
+    R.close()
+    del A, R
+    torch.cuda.empty_cache()
+    names = ["rho'", "m_x", "m_y", "m_z", "E'", "f0", "fx", "fy", "fz", "fxx", "fyy", "fzz", "fxy", "fyz", "fzx"]
+    for k in kinds:
+        log(f"bricks {k} fp32 vs fp64 after {nfixed} steps: worst relative L1 {max(worst[k]):.2e}")
+    return {"ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3), "fixed_dt": dt, "fixed_steps": nfixed,
+            "fp32_vs_fp64_relL1_worst_brick": {k: {names[q]: float(worst[k][q]) for q in range(15)} for k in kinds},
+            "note": "brick_sine: periodic sine flows (rho' and E' start at zero, so their scale is the small "
+                    "compressive part of the flow); brick_strat: stratified boxes with seeded per-cell noise"}
 
 
 def _restrict(a):
@@ -528,7 +603,7 @@ def main():
         print(json.dumps(res), flush=True)
         return
     if args.bricks_only:
-        res = run_bricks(args.steps, args.warmup)
+        res = run_bricks(args.steps, args.warmup, fp64=not args.no_fp64)
         print(json.dumps(res), flush=True)
         return
     log(f"generating the {args.n}^3 shell inputs")
@@ -670,7 +745,7 @@ def main():
                        "speedup_fp32_over_fp64": r64["ms_per_step"] / r32["ms_per_step"]}
     if not args.no_bricks:
         log("batched bricks")
-        out["bricks"] = run_bricks(max(5, args.steps // 2), 2)
+        out["bricks"] = run_bricks(max(5, args.steps // 2), 2, fp64=not args.no_fp64)
     if not args.no_accuracy:
         log("accuracy: FP32 round-off vs truncation error")
         out["accuracy"] = run_accuracy()

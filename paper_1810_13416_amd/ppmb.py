@@ -462,6 +462,10 @@ class Batch:
         self._check(self.L.ppmb_brick_last_dt(self.h, int(b), ctypes.byref(v)))
         return v.value
 
+    def step_dt(self, dt):
+        """One step of every brick with the same given dt (asynchronous)."""
+        self._check(self.L.ppmb_step(self.h, float(dt)))
+
     def step(self, cfl, nsteps, mode=0):
         """mode 0: one launch per stage for all bricks; 1: replayed hipGraph;
         2: one launch per stage and brick; 3: one launch of the persistent
