@@ -36,7 +36,7 @@ struct ppmb_ctx {
     double *table = nullptr;            // base-state RK4 nodes (reused brick by brick)
     long table_len = 0;
     double *dt = nullptr;               // per-brick dt
-    unsigned long long *cnt = nullptr;  // [0..2] event counters, [3] Courant-check flag
+    unsigned long long *cnt = nullptr;  // event counter slots (kCntSlots x kCntStride); word 3: Courant-check flag
     unsigned long long *work = nullptr; // per brick: smax bits, non-physical flag
     unsigned long long *cband = nullptr; // per brick: band edge of the fused CFL reduction, redo flag
     double *partials = nullptr;         // totals block partials
@@ -432,7 +432,7 @@ static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_preci
     if (e == hipSuccess && prec == PPMB_FP32) e = hipMalloc(&c->baseT, sizeof(float) * boff);
     if (e == hipSuccess) e = hipMalloc(&c->table, sizeof(double) * c->table_len);
     if (e == hipSuccess) e = hipMalloc(&c->dt, sizeof(double) * nbricks);
-    if (e == hipSuccess) e = hipMalloc(&c->cnt, sizeof(unsigned long long) * 4);
+    if (e == hipSuccess) e = hipMalloc(&c->cnt, sizeof(unsigned long long) * kCntWords);
     if (e == hipSuccess) e = hipMalloc(&c->work, sizeof(unsigned long long) * 2 * nbricks);
     if (e == hipSuccess) e = hipMalloc(&c->cband, sizeof(unsigned long long) * 2 * nbricks);
     // the persistent step's counters are polled by waves on every XCD while
@@ -454,7 +454,7 @@ static ppmb_status create_common(int nbricks, const ppmb_grid *grids, ppmb_preci
     }
     ppmb_status st = PPMB_OK;
     if (hipMemcpy(c->db, c->hb.data(), sizeof(Brick) * nbricks, hipMemcpyHostToDevice) != hipSuccess ||
-        launch_zero_u64(c->cnt, 4, c->stream) != hipSuccess ||
+        launch_zero_u64(c->cnt, kCntWords, c->stream) != hipSuccess ||
         launch_zero_u64(c->work, 2 * nbricks, c->stream) != hipSuccess ||
         launch_zero_u64(c->cband, 2 * nbricks, c->stream) != hipSuccess ||
         launch_zero_u64(c->scnt, nbricks + 2, c->stream) != hipSuccess)
@@ -1441,7 +1441,12 @@ ppmb_status ppmb_counters(ppmb_ctx *c, unsigned long long out[4])
 {
     if (!c || !out) return PPMB_ERR_INVALID;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(out, c->cnt, sizeof(unsigned long long) * 3, hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> w(kCntWords);
+    HIPCHK(c, hipMemcpy(w.data(), c->cnt, sizeof(unsigned long long) * kCntWords, hipMemcpyDeviceToHost));
+    for (int q = 0; q < 3; ++q) {
+        out[q] = 0;
+        for (int s = 0; s < kCntSlots; ++s) out[q] += w[s * kCntStride + q];
+    }
     out[3] = c->steps;
     return check_flag(c);
 }
@@ -1550,9 +1555,9 @@ ppmb_status ppmb_autotune(ppmb_ctx *c, double cfl, int reps, const char *cache_p
             fclose(f);
         }
     }
-    unsigned long long saved[3];
+    std::vector<unsigned long long> saved(kCntWords);
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(saved, c->cnt, sizeof saved, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(saved.data(), c->cnt, sizeof(unsigned long long) * kCntWords, hipMemcpyDeviceToHost));
     TRY(enqueue_cfl(c, cfl, 0, c->nb));
     c->cfl_ready = true;                 // the passes below leave the state as it is
     TRY(check_flag(c));
@@ -1598,7 +1603,7 @@ ppmb_status ppmb_autotune(ppmb_ctx *c, double cfl, int reps, const char *cache_p
     hipEventDestroy(e1);
     c->profiling = prof;
     if (st != PPMB_OK) return st;
-    HIPCHK(c, hipMemcpy(c->cnt, saved, sizeof saved, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->cnt, saved.data(), sizeof(unsigned long long) * kCntWords, hipMemcpyHostToDevice));
     TRY(set_shape(c, best));
     out_shape[0] = best.march_waves;
     out_shape[1] = best.x_waves;

@@ -62,6 +62,15 @@ double pass_block_cost(const Geom &g, int axis, const PassShape &sh, int local);
 // from a fluid cell: a wave of pencils marches over the union of their
 // fluid intervals, the x pass visits only the 56-cell segments holding
 // fluid cells.
+// Event counters (limiter, unsmooth, Riemann) are spread over slots a
+// cache line apart, one for each residue of the block index, so that the
+// waves' atomic adds (one per wave and counter) do not all queue on one
+// address; readers sum the slots.  Element 3 of slot 0 is the Courant-check
+// flag, which no pass adds to.
+constexpr int kCntSlots = 64;
+constexpr int kCntStride = 16;                      // words per slot: 128 bytes
+constexpr int kCntWords = kCntSlots * kCntStride;
+
 template <typename T>
 hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, const BlockMap *map,
                         int nblocks, const T *in, T *out, const T *base, const double *dt,

@@ -105,13 +105,33 @@ __device__ __forceinline__ void to_global(T n, T t1, T t2, T &x, T &y, T &z)
 
 // One wave's share of the CFL reduction: maximum and non-physical flag over
 // its lanes into the brick's slots (positive doubles order like their bits).
+// A wave with no exact speed (no cell reached the band) adds nothing: the
+// slot starts each pass at zero, so its maximum would change nothing.
 __device__ __forceinline__ void cfl_commit(unsigned long long *work, int brick, double smax, bool bad)
 {
     for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_down(smax, off));
     const unsigned long long bb = __ballot(bad);
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(&work[2 * brick], (unsigned long long)__double_as_longlong(smax));
+        if (smax > 0.0) atomicMax(&work[2 * brick], (unsigned long long)__double_as_longlong(smax));
         if (bb) atomicOr(&work[2 * brick + 1], 1ull);
+    }
+}
+
+// One wave's event counts into its block's counter slot.
+__device__ __forceinline__ void count_commit(unsigned long long *counters, unsigned c_lim, unsigned c_uns,
+                                             unsigned c_rie)
+{
+    unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
+    for (int off = 32; off > 0; off >>= 1) {
+        s0 += __shfl_down(s0, off);
+        s1 += __shfl_down(s1, off);
+        s2 += __shfl_down(s2, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        unsigned long long *slot = counters + (blockIdx.x % kCntSlots) * kCntStride;
+        if (s0) atomicAdd(&slot[0], s0);
+        if (s1) atomicAdd(&slot[1], s1);
+        if (s2) atomicAdd(&slot[2], s2);
     }
 }
 
@@ -726,18 +746,7 @@ __device__ __forceinline__ void march_wave(const BatchArgs<T> &b, const BlockMap
         march<T, AX, DISS, FLAT>(g, &B.g, a, la0, (int)(threadIdx.x & 63), lb, clo, chi, c_lim, c_uns, c_rie,
                                  cmax, cbad);
     if (b.cfl) cfl_commit(b.work, m.brick, cmax, cbad);
-    // event counters: one atomic per wave and counter
-    unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
-    for (int off = 32; off > 0; off >>= 1) {
-        s0 += __shfl_down(s0, off);
-        s1 += __shfl_down(s1, off);
-        s2 += __shfl_down(s2, off);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (s0) atomicAdd(&a.counters[0], s0);
-        if (s1) atomicAdd(&a.counters[1], s1);
-        if (s2) atomicAdd(&a.counters[2], s2);
-    }
+    count_commit(a.counters, c_lim, c_uns, c_rie);
 }
 
 template <typename T, int AX, bool DISS, bool FLAT>
@@ -1110,17 +1119,7 @@ __device__ __forceinline__ void x_wave(const BatchArgs<T> &b, const BlockMap m, 
       rns = nns;
     }
     if (a.cfl) cfl_commit(b.work, m.brick, cmax, cbad);
-    unsigned long long s0 = c_lim, s1 = c_uns, s2 = c_rie;
-    for (int off = 32; off > 0; off >>= 1) {
-        s0 += __shfl_down(s0, off);
-        s1 += __shfl_down(s1, off);
-        s2 += __shfl_down(s2, off);
-    }
-    if (lane == 0) {
-        if (s0) atomicAdd(&a.counters[0], s0);
-        if (s1) atomicAdd(&a.counters[1], s1);
-        if (s2) atomicAdd(&a.counters[2], s2);
-    }
+    count_commit(a.counters, c_lim, c_uns, c_rie);
 }
 
 template <typename T, bool DISS, bool FLAT>
