@@ -166,6 +166,44 @@ struct ShellCell {
     T rp, mx, my, mz, f;
 };
 
+// Cross-lane moves of the shell kernel's scan (DPP: a VALU operand, no LDS
+// round trip).  Within a row of 16 lanes row_shr:n reads the lane n below
+// (a lane whose source lies below its row reads 0); row_bcast:15 gives
+// rows 1 and 3 (row mask 0xa) lane 15 of the row below, row_bcast:31 gives
+// rows 2 and 3 (row mask 0xc) lane 31; lanes of rows the mask leaves out
+// read 0.  wave_shr:1 / wave_shl:1 read lane l - 1 / l + 1 (0 past the
+// wave's ends).
+constexpr int kRowShr = 0x110;
+constexpr int kRowBcast15 = 0x142;
+constexpr int kRowBcast31 = 0x143;
+constexpr int kWaveShr1 = 0x138;
+constexpr int kWaveShl1 = 0x130;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xf, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xf, true);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// One step of the segmented scan: a lane's window (the lanes whose values
+// its partial holds) grows by the source lane's window unless it already
+// holds a run head; a source outside the row or the mask gives 0 and no
+// head, which leaves the lane as it was.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_step(double v[8], int &head)
+{
+    const int hup = __builtin_amdgcn_update_dpp(0, head, CTRL, ROWS, 0xf, true);
+    double up[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) up[q] = dpp_f64<CTRL, ROWS>(v[q]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = head ? v[q] : up[q] + v[q];
+    head |= hup;
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void shell_kernel(Geom g, const T *S, const double *rho0, int nbins,
                                                    double dr, int rows_per_block, double *work)
@@ -241,24 +279,28 @@ __global__ __launch_bounds__(64) void shell_kernel(Geom g, const T *S, const dou
             v[6] = on ? cur.x * my - cur.y * mx : 0.0;
             v[7] = on ? f * f : 0.0;
         }
-        // segmented inclusive scan: a lane adds the partial d lanes below
-        // while no run boundary lies between them
-        const int kprev = __shfl_up(key, 1);
+        // segmented inclusive scan over the runs of equal keys, by DPP row
+        // shifts within each 16-lane row and then the two row broadcasts:
+        // a lane whose window has met no run head adds the partial of the
+        // lane the step names; the steps stop once every window that could
+        // still grow already meets a head
+        const int kprev = __builtin_amdgcn_update_dpp(0, key, kWaveShr1, 0xf, 0xf, true);
         int head = (lane == 0 || kprev != key) ? 1 : 0;
-        // after the step with shift d a lane's window spans 2d lanes; stop
-        // once every window that could still grow already meets a boundary
-        for (int d = 1; d < 64; d <<= 1) {
-            const int hup = __shfl_up(head, d);
-            double up[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) up[q] = __shfl_up(v[q], d);
-            const bool take = lane >= d && !head;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = take ? up[q] + v[q] : v[q];
-            head = lane >= d ? (head | hup) : head;
-            if (__ballot(lane >= 2 * d && !head) == 0) break;
+        seg_step<kRowShr + 1, 0xf>(v, head);
+        if (__ballot(lane >= 2 && !head)) {
+            seg_step<kRowShr + 2, 0xf>(v, head);
+            if (__ballot(lane >= 4 && !head)) {
+                seg_step<kRowShr + 4, 0xf>(v, head);
+                if (__ballot(lane >= 8 && !head)) {
+                    seg_step<kRowShr + 8, 0xf>(v, head);
+                    if (__ballot(lane >= 16 && !head)) {
+                        seg_step<kRowBcast15, 0xa>(v, head);
+                        if (__ballot(lane >= 32 && !head)) seg_step<kRowBcast31, 0xc>(v, head);
+                    }
+                }
+            }
         }
-        const int knext = __shfl_down(key, 1);
+        const int knext = __builtin_amdgcn_update_dpp(0, key, kWaveShl1, 0xf, 0xf, true);
         const bool last = key >= 0 && (lane == 63 || knext != key);
         for (int side = 0; side < 2; ++side) {
             if (last && (key & 1) == side) {
