@@ -135,15 +135,18 @@ hipError_t launch_rotframe(const Brick *bricks, const BlockMap *map, int nblocks
 //
 // Along an x-row r^2 = x^2 + const falls for x < 0 and rises for x >= 0, so
 // on each side of x = 0 the cells of one shell are one contiguous run.
-// Block b (one wave) walks a fixed run of rows in chunks of 64 cells (the
-// next chunk's loads in flight while the current one is reduced); a
-// segmented inclusive scan over the lanes (runs = equal shell and side)
-// leaves each run's sum in its last lane, which adds it to the block's
-// shell array in LDS, the x < 0 side first: the runs of one side have
-// distinct shells, so no two lanes of one LDS update share an address.
-// The block arrays go to `work`; they are added per (shell, quantity) in
-// two fixed levels (groups of consecutive blocks, then the groups).  Every association is fixed, so the result is
-// bitwise reproducible.
+// Block b walks a fixed run of rows in chunks of 64 cells, its waves
+// taking the chunks in turn (each wave's next chunk in flight while the
+// current one is reduced); a segmented inclusive scan over the lanes (runs
+// = equal shell and side) leaves each run's sum in its last lane, which
+// adds it to the block's shell array in LDS, the x < 0 side first: the
+// runs of one side have distinct shells, so no two lanes of one LDS update
+// share an address.  The waves of a block update the array one after the
+// other, separated by barriers, so that it receives the chunks in chunk
+// order.  The block arrays go to `work`; they are added per (shell,
+// quantity) in two fixed levels (groups of consecutive blocks, then the
+// groups).  Every association is fixed, so the result is bitwise
+// reproducible, and the same for any number of waves per block.
 // ---------------------------------------------------------------------
 
 // shell of a radius: a first guess from r / dr, then the squared bounds
@@ -204,13 +207,14 @@ __device__ __forceinline__ void seg_step(double v[8], int &head)
     head |= hup;
 }
 
-template <typename T>
-__global__ __launch_bounds__(64) void shell_kernel(Geom g, const T *S, const double *rho0, int nbins,
-                                                   double dr, int rows_per_block, double *work)
+template <typename T, int W>
+__global__ __launch_bounds__(64 * W) void shell_kernel(Geom g, const T *S, const double *rho0, int nbins,
+                                                       double dr, int rows_per_block, double *work)
 {
     extern __shared__ double bins[];           // 8 * nbins, quantity-major: bins[q * nbins + shell]
-    const int lane = threadIdx.x;
-    for (int q = lane; q < nbins * 8; q += 64) bins[q] = 0.0;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int q = threadIdx.x; q < nbins * 8; q += 64 * W) bins[q] = 0.0;
     __syncthreads();
     const int ny = g.n[1];
     const long nrows = (long)ny * g.n[2];
@@ -223,101 +227,114 @@ __global__ __launch_bounds__(64) void shell_kernel(Geom g, const T *S, const dou
     const double inv_dr = 1.0 / dr;
     const long fs = g.fs;
 
-    auto fetch = [&](int ci, int j, int k, ShellCell<T> &c) {
+    // chunk c of the block: 64 cells of row r0 + c / cpr
+    auto fetch = [&](long c, ShellCell<T> &cell) {
+        const long row = r0 + c / cpr;
+        const int ci = (int)(c - (row - r0) * cpr);
+        const int j = (int)(row % ny), k = (int)(row / ny);
         const int i = ci * 64 + lane;
         const bool in = i < g.n[0];
-        c.x = centre(g, 0, in ? i : 0);
-        c.y = centre(g, 1, j);
-        c.z = centre(g, 2, k);
+        cell.x = centre(g, 0, in ? i : 0);
+        cell.y = centre(g, 1, j);
+        cell.z = centre(g, 2, k);
         const long e = (long)(in ? i : 0) + (long)j * g.px + (long)k * g.plane;
-        const double r2 = r2_exact(c.x, c.y, c.z);
-        c.r = sqrt(r2);
-        c.key = -1;
+        const double r2 = r2_exact(cell.x, cell.y, cell.z);
+        cell.r = sqrt(r2);
+        cell.key = -1;
         if (in && !(g.sphere && r2 >= g.sphere_t) && r2 < rmax2)
-            c.key = 2 * shell_of(r2, c.r, inv_dr, dr, nbins) + (c.x >= 0.0 ? 1 : 0);
-        c.r0 = 0.0;
-        c.rp = c.mx = c.my = c.mz = c.f = T(0);
-        if (c.key >= 0) {                      // solid cells and cells beyond the shells: no loads
-            c.r0 = rho0[e];
-            c.rp = S[RHO * fs + e];
-            c.mx = S[MX * fs + e];
-            c.my = S[MY * fs + e];
-            c.mz = S[MZ * fs + e];
-            c.f = S[F0 * fs + e];
+            cell.key = 2 * shell_of(r2, cell.r, inv_dr, dr, nbins) + (cell.x >= 0.0 ? 1 : 0);
+        cell.r0 = 0.0;
+        cell.rp = cell.mx = cell.my = cell.mz = cell.f = T(0);
+        if (cell.key >= 0) {                   // solid cells and cells beyond the shells: no loads
+            cell.r0 = rho0[e];
+            cell.rp = S[RHO * fs + e];
+            cell.mx = S[MX * fs + e];
+            cell.my = S[MY * fs + e];
+            cell.mz = S[MZ * fs + e];
+            cell.f = S[F0 * fs + e];
         }
     };
 
-    int ci = 0, j = (int)(r0 % ny), k = (int)(r0 / ny);
+    // Wave wv takes chunks wv, wv + W, ...; the W waves of a block add their
+    // chunks' runs to the bins in turn, so the bins receive the chunks in
+    // chunk order whatever W is (the same sums, bit for bit).
     ShellCell<T> cur, nxt;
-    if (nchunk > 0) fetch(ci, j, k, cur);
-    for (long c = 0; c < nchunk; ++c) {
-        // the next chunk (this row, else the next row) goes in flight first
-        if (++ci == cpr) {
-            ci = 0;
-            if (++j == ny) { j = 0; ++k; }
-        }
-        if (c + 1 < nchunk) fetch(ci, j, k, nxt);
-        const int key = cur.key;
-        if (__ballot(key >= 0) == 0) {         // no cell of this chunk takes part
-            cur = nxt;
-            continue;
-        }
+    if (wv < nchunk) fetch(wv, cur);
+    const long niter = (nchunk + W - 1) / W;
+    for (long t = 0; t < niter; ++t) {
+        const long c = t * W + wv;
+        // this wave's next chunk goes in flight first
+        if (c + W < nchunk) fetch(c + W, nxt);
+        const int key = c < nchunk ? cur.key : -1;
+        const bool any = __ballot(key >= 0) != 0;   // some cell of this chunk takes part
         double v[8];
-        {
-            const bool on = key >= 0;
-            const double rho = cur.r0 + (double)cur.rp;
-            const double irho = on ? 1.0 / rho : 0.0;
-            const double mx = (double)cur.mx, my = (double)cur.my, mz = (double)cur.mz;
-            const double f = (double)cur.f;
-            const double mr = cur.r > 0.0 ? ((cur.x * mx + cur.y * my) + cur.z * mz) / cur.r : 0.0;
-            v[0] = on ? 1.0 : 0.0;
-            v[1] = on ? rho : 0.0;
-            v[2] = on ? f : 0.0;
-            v[3] = on ? mr : 0.0;
-            v[4] = on ? mr * mr * irho : 0.0;
-            v[5] = on ? ((mx * mx + my * my) + mz * mz) * irho : 0.0;
-            v[6] = on ? cur.x * my - cur.y * mx : 0.0;
-            v[7] = on ? f * f : 0.0;
-        }
-        // segmented inclusive scan over the runs of equal keys, by DPP row
-        // shifts within each 16-lane row and then the two row broadcasts:
-        // a lane whose window has met no run head adds the partial of the
-        // lane the step names; the steps stop once every window that could
-        // still grow already meets a head
-        const int kprev = __builtin_amdgcn_update_dpp(0, key, kWaveShr1, 0xf, 0xf, true);
-        int head = (lane == 0 || kprev != key) ? 1 : 0;
-        seg_step<kRowShr + 1, 0xf>(v, head);
-        if (__ballot(lane >= 2 && !head)) {
-            seg_step<kRowShr + 2, 0xf>(v, head);
-            if (__ballot(lane >= 4 && !head)) {
-                seg_step<kRowShr + 4, 0xf>(v, head);
-                if (__ballot(lane >= 8 && !head)) {
-                    seg_step<kRowShr + 8, 0xf>(v, head);
-                    if (__ballot(lane >= 16 && !head)) {
-                        seg_step<kRowBcast15, 0xa>(v, head);
-                        if (__ballot(lane >= 32 && !head)) seg_step<kRowBcast31, 0xc>(v, head);
+        bool last = false;
+        if (any) {
+            {
+                const bool on = key >= 0;
+                const double rho = cur.r0 + (double)cur.rp;
+                const double irho = on ? 1.0 / rho : 0.0;
+                const double mx = (double)cur.mx, my = (double)cur.my, mz = (double)cur.mz;
+                const double f = (double)cur.f;
+                const double mr = cur.r > 0.0 ? ((cur.x * mx + cur.y * my) + cur.z * mz) / cur.r : 0.0;
+                v[0] = on ? 1.0 : 0.0;
+                v[1] = on ? rho : 0.0;
+                v[2] = on ? f : 0.0;
+                v[3] = on ? mr : 0.0;
+                v[4] = on ? mr * mr * irho : 0.0;
+                v[5] = on ? ((mx * mx + my * my) + mz * mz) * irho : 0.0;
+                v[6] = on ? cur.x * my - cur.y * mx : 0.0;
+                v[7] = on ? f * f : 0.0;
+            }
+            // segmented inclusive scan over the runs of equal keys, by DPP
+            // row shifts within each 16-lane row and then the two row
+            // broadcasts: a lane whose window has met no run head adds the
+            // partial of the lane the step names; the steps stop once every
+            // window that could still grow already meets a head
+            const int kprev = __builtin_amdgcn_update_dpp(0, key, kWaveShr1, 0xf, 0xf, true);
+            int head = (lane == 0 || kprev != key) ? 1 : 0;
+            seg_step<kRowShr + 1, 0xf>(v, head);
+            if (__ballot(lane >= 2 && !head)) {
+                seg_step<kRowShr + 2, 0xf>(v, head);
+                if (__ballot(lane >= 4 && !head)) {
+                    seg_step<kRowShr + 4, 0xf>(v, head);
+                    if (__ballot(lane >= 8 && !head)) {
+                        seg_step<kRowShr + 8, 0xf>(v, head);
+                        if (__ballot(lane >= 16 && !head)) {
+                            seg_step<kRowBcast15, 0xa>(v, head);
+                            if (__ballot(lane >= 32 && !head)) seg_step<kRowBcast31, 0xc>(v, head);
+                        }
                     }
                 }
             }
+            const int knext = __builtin_amdgcn_update_dpp(0, key, kWaveShl1, 0xf, 0xf, true);
+            last = key >= 0 && (lane == 63 || knext != key);
         }
-        const int knext = __builtin_amdgcn_update_dpp(0, key, kWaveShl1, 0xf, 0xf, true);
-        const bool last = key >= 0 && (lane == 63 || knext != key);
-        for (int side = 0; side < 2; ++side) {
-            if (last && (key & 1) == side) {
-                // the runs' shells are consecutive along a side, so the
-                // lanes of one update hit consecutive doubles (no bank
-                // conflicts beyond those of a plain row access)
-                const int b = key >> 1;
+        for (int u = 0; u < W; ++u) {
+            if (u == wv && any) {
+                for (int side = 0; side < 2; ++side) {
+                    if (last && (key & 1) == side) {
+                        // the runs' shells are consecutive along a side, so
+                        // the lanes of one update hit consecutive doubles
+                        // (no bank conflicts beyond those of a plain row
+                        // access)
+                        const int b = key >> 1;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) bins[q * nbins + b] += v[q];
+                        for (int q = 0; q < 8; ++q) bins[q * nbins + b] += v[q];
+                    }
+                }
             }
+            if constexpr (W > 1) __syncthreads();
         }
         cur = nxt;
     }
     __syncthreads();
     double *P = work + (long)blockIdx.x * nbins * 8;
-    for (int t = lane; t < nbins * 8; t += 64) P[t] = bins[(t & 7) * nbins + (t >> 3)];   // out: 8 shell + quantity
+    for (int t = threadIdx.x; t < nbins * 8; t += 64 * W) P[t] = bins[(t & 7) * nbins + (t >> 3)];   // out: 8 shell + quantity
 }
+
+// Waves per block of the shell kernel (they share the block's bins).
+constexpr int kShellWaves = 4;
 
 // Block partials are added in two fixed levels: groups of kShellGroup
 // consecutive blocks (in block order), then the group sums (in group order).
@@ -377,7 +394,8 @@ hipError_t launch_shell(const Geom &g, const T *state, const double *rho0, int n
     const size_t lds = sizeof(double) * 8 * (size_t)nbins;
     const int m = nbins * 8, ng = (nb + kShellGroup - 1) / kShellGroup;
     double *gsum = work + (long)nb * m;
-    hipLaunchKernelGGL((shell_kernel<T>), dim3(nb), dim3(64), lds, st, g, state, rho0, nbins, dr, rpb, work);
+    hipLaunchKernelGGL((shell_kernel<T, kShellWaves>), dim3(nb), dim3(64 * kShellWaves), lds, st, g, state, rho0, nbins,
+                       dr, rpb, work);
     hipLaunchKernelGGL(shell_group_kernel, dim3((m + 255) / 256, ng), dim3(256), 0, st, work, nb, m, gsum);
     hipLaunchKernelGGL(shell_finish_kernel, dim3((m + 255) / 256), dim3(256), 0, st, gsum, ng, m,
                        g.dx * g.dx * g.dx, out);
