@@ -512,8 +512,9 @@ static ppmb_status enqueue_cfl(ppmb_ctx *c, double cfl, int b0, int b1)
 // `cfl` it also reduces the signal speeds of its output into work[].
 static ppmb_status enqueue_pass(ppmb_ctx *c, int axis, int heat, int b0, int b1, int from, int cfl = 0)
 {
-    if (c->flat_on) {
-        // flattening coefficients of this pass's input along its axis
+    if (c->flat_on && !(axis == 0 && c->shape.x_rows > 0)) {
+        // flattening coefficients of this pass's input along its axis (the
+        // lanes-along-x kernel evaluates its own)
         const int g0 = c->ffirst[axis][b0], g1 = c->ffirst[axis][b1];
         if (c->prec == PPMB_FP64)
             HIPCHK(c, launch_flattening<double>(axis, c->db, c->fmap[axis] + g0, g1 - g0, arena<double>(c, from),

@@ -643,50 +643,14 @@ hipError_t launch_divergence(const Brick *bricks, const BlockMap *map, int nbloc
 }
 
 // ---------------------------------------------------------------------
-// Flattening near strong shocks (Colella & Woodward 1984, Sec. 4), the
-// companion of the shock dissipation: per cell and pass axis d, from the
-// full pressure p over three cells each side and the velocity u along d
-// over two, neighbours through the boundary conditions (a reflecting
-// image's u flipped):
-//   raw(i) = 0 unless |p(i+1) - p(i-1)| > eps min(p(i+1), p(i-1)) and
-//            u(i-1) - u(i+1) > tie (|u(i-1)| + |u(i+1)|); else
-//            min(1, max(0, w2 (z - w1))),
-//            z = (p(i+1) - p(i-1)) / (p(i+2) - p(i-2)) (0 if that is 0);
-//   f(i)   = max(raw(i), raw(i + 1)) if p(i+1) < p(i-1), max(raw(i),
-//            raw(i - 1)) if p(i+1) > p(i-1), max of all three when
-//            |p(i+1) - p(i-1)| <= tie (p(i+1) + p(i-1)).
-// The tie margins keep the decisions off values that are equal but for
-// rounding.  FP64 arithmetic, stored in the working precision.
+// Flattening coefficients (formulas and constants with flat_pu, flat_raw
+// and flat_pick): a kernel per pass axis writes the field of the pass's
+// input, stored in the working precision.
 // ---------------------------------------------------------------------
 
-constexpr double kFlatEps = 0.33, kFlatW1 = 0.75, kFlatW2 = 10.0, kFlatTie = 1e-10;
 constexpr int kFlatChunk = 64;     // cells along the pass per thread (march form)
 constexpr int kFlatXOut = 58;      // outputs per 64-lane row segment (x form)
 
-// the coefficient from the raw values of the cell and its two neighbours
-__device__ __forceinline__ double flat_pick(double pm1, double pp1, double rm, double r0, double rp)
-{
-    const double dp = pp1 - pm1;
-    double nb;
-    if (fabs(dp) <= kFlatTie * (pp1 + pm1)) nb = fmax(rm, rp);
-    else nb = dp < 0.0 ? rp : rm;
-    return fmax(r0, nb);
-}
-
-__device__ __forceinline__ double flat_raw(double pm2, double pm1, double pp1, double pp2, double um1, double up1)
-{
-    const double dp1 = pp1 - pm1, dp2 = pp2 - pm2;
-    const bool cand = fabs(dp1) > kFlatEps * fmin(pp1, pm1) && um1 - up1 > kFlatTie * (fabs(um1) + fabs(up1));
-    if (!cand) return 0.0;
-    const double z = dp2 != 0.0 ? dp1 / dp2 : 0.0;
-    return fmin(1.0, fmax(0.0, kFlatW2 * (z - kFlatW1)));
-}
-
-// Full pressure and the velocity along d of element e (flip fl on u), each
-// velocity a correctly rounded quotient m / rho: the compression test
-// compares two velocities that are often equal but for rounding (a uniform
-// transverse flow after a pass), so FP64 runs take exactly the decisions of
-// any other evaluation of these formulas in the same order.
 // a copy of v as a new value (an identity DPP move)
 __device__ __forceinline__ float aux_fresh(float v)
 {
@@ -732,11 +696,8 @@ __device__ __forceinline__ FlatRaw<T> flat_take(const FlatRaw<T> &r)
 template <typename T>
 __device__ __forceinline__ void flat_eval(const Geom &g, const FlatRaw<T> &r, int d, double &p, double &u)
 {
-    const double rho = r.r0 + (double)r.rp;
-    const double mx = (double)r.mx, my = (double)r.my, mz = (double)r.mz;
-    const double vx = mx / rho, vy = my / rho, vz = mz / rho;
-    p = r.p0 + (g.gamma - 1.0) * ((double)r.ep - 0.5 * (mx * vx + my * vy + mz * vz));
-    u = r.fl * (d == 0 ? vx : (d == 1 ? vy : vz));
+    flat_pu(r.r0, r.p0, (double)r.rp, (double)r.mx, (double)r.my, (double)r.mz, (double)r.ep, g.gamma, d, r.fl,
+            p, u);
 }
 
 int flat_blocks(const Geom &g, int axis)

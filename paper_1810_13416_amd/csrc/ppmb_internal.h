@@ -228,9 +228,66 @@ __device__ __forceinline__ void cfl_block_part(const Brick *bricks, BlockMap m, 
     for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_down(smax, off));
     const unsigned long long bb = __ballot(bad);
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(&work[2 * m.brick], (unsigned long long)__double_as_longlong(smax));
+        // a wave of solid cells has nothing to add (the maximum starts at 0)
+        if (smax > 0.0) atomicMax(&work[2 * m.brick], (unsigned long long)__double_as_longlong(smax));
         if (bb) atomicOr(&work[2 * m.brick + 1], 1ull);
     }
+}
+
+// ---------------------------------------------------------------------
+// Flattening near strong shocks (Colella & Woodward 1984, Sec. 4), the
+// companion of the shock dissipation: per cell and pass axis d, from the
+// full pressure p over three cells each side and the velocity u along d
+// over two, neighbours through the boundary conditions (a reflecting
+// image's u flipped):
+//   raw(i) = 0 unless |p(i+1) - p(i-1)| > eps min(p(i+1), p(i-1)) and
+//            u(i-1) - u(i+1) > tie (|u(i-1)| + |u(i+1)|); else
+//            min(1, max(0, w2 (z - w1))),
+//            z = (p(i+1) - p(i-1)) / (p(i+2) - p(i-2)) (0 if that is 0);
+//   f(i)   = max(raw(i), raw(i + 1)) if p(i+1) < p(i-1), max(raw(i),
+//            raw(i - 1)) if p(i+1) > p(i-1), max of all three when
+//            |p(i+1) - p(i-1)| <= tie (p(i+1) + p(i-1)).
+// The tie margins keep the decisions off values that are equal but for
+// rounding.  FP64 arithmetic without contraction, so that the flattening
+// kernels and the x pass (which evaluates the coefficients of its own
+// segment) take the same decisions.
+// ---------------------------------------------------------------------
+
+constexpr double kFlatEps = 0.33, kFlatW1 = 0.75, kFlatW2 = 10.0, kFlatTie = 1e-10;
+
+// Full pressure and the velocity along d of one cell (flip fl on u), each
+// velocity a correctly rounded quotient m / rho: the compression test
+// compares two velocities that are often equal but for rounding (a uniform
+// transverse flow after a pass).
+__device__ __forceinline__ void flat_pu(double r0, double p0, double rp, double mx, double my, double mz,
+                                        double ep, double gamma, int d, double fl, double &p, double &u)
+{
+#pragma clang fp contract(off)
+    const double rho = r0 + rp;
+    const double vx = mx / rho, vy = my / rho, vz = mz / rho;
+    p = p0 + (gamma - 1.0) * (ep - 0.5 * (mx * vx + my * vy + mz * vz));
+    u = fl * (d == 0 ? vx : (d == 1 ? vy : vz));
+}
+
+// the coefficient from the raw values of the cell and its two neighbours
+__device__ __forceinline__ double flat_pick(double pm1, double pp1, double rm, double r0, double rp)
+{
+#pragma clang fp contract(off)
+    const double dp = pp1 - pm1;
+    double nb;
+    if (fabs(dp) <= kFlatTie * (pp1 + pm1)) nb = fmax(rm, rp);
+    else nb = dp < 0.0 ? rp : rm;
+    return fmax(r0, nb);
+}
+
+__device__ __forceinline__ double flat_raw(double pm2, double pm1, double pp1, double pp2, double um1, double up1)
+{
+#pragma clang fp contract(off)
+    const double dp1 = pp1 - pm1, dp2 = pp2 - pm2;
+    const bool cand = fabs(dp1) > kFlatEps * fmin(pp1, pm1) && um1 - up1 > kFlatTie * (fabs(um1) + fabs(up1));
+    if (!cand) return 0.0;
+    const double z = dp2 != 0.0 ? dp1 / dp2 : 0.0;
+    return fmin(1.0, fmax(0.0, kFlatW2 * (z - kFlatW1)));
 }
 
 // Brick k after the fused reduction of its last pass: dt where the maximum

@@ -825,13 +825,13 @@ struct XIn {
     T pq[10];
     T r0, pb;
     T dv;             // divergence (shock dissipation only)
-    T fv;             // flattening coefficient (flattening only)
+    double fr0, fp0;  // FP64 base (flattening only)
     int s, fl;
 };
 
 template <typename T, bool DISS, bool FLAT>
-__device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, const T *div, const T *flat,
-                                       long nc, long row,
+__device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, const T *div, const double *r064,
+                                       const double *p064, long nc, long row,
                                        int nx, int bc, int i, XIn<T> &o)
 {
     using AI = AxisInfo<0>;
@@ -852,7 +852,15 @@ __device__ __forceinline__ void x_load(const T *in, const T *rho0, const T *p0, 
     o.r0 = bld<T>(rsrc(rho0 + row, nx), s);
     o.pb = bld<T>(rsrc(p0 + row, nx), s);
     if constexpr (DISS) o.dv = bld<T>(rsrc(div + row, nx), s);
-    if constexpr (FLAT) o.fv = bld<T>(rsrc(flat + row, nx), s);
+    if constexpr (FLAT) {
+        if constexpr (sizeof(T) == 8) {
+            o.fr0 = o.r0;
+            o.fp0 = o.pb;
+        } else {
+            o.fr0 = bld<double>(rsrc(r064 + row, nx), s);
+            o.fp0 = bld<double>(rsrc(p064 + row, nx), s);
+        }
+    }
 }
 
 // One wave walks whole x-rows, 56-cell segment by segment, at least
@@ -916,7 +924,7 @@ __device__ __forceinline__ void x_wave(const BatchArgs<T> &b, const BlockMap m, 
     rowi = next_row(it0 / nseg, rx0, rns);
     XIn<T> cur;
     if (rowi < rend)
-        x_load<T, DISS, FLAT>(a.in, a.rho0, a.p0, a.div, a.flat, nc, (long)rowi * g.px, nx, bc, rx0 - NG + lane,
+        x_load<T, DISS, FLAT>(a.in, a.rho0, a.p0, a.div, a.r064, a.p064, nc, (long)rowi * g.px, nx, bc, rx0 - NG + lane,
                               cur);
     // settle the first loads, so that the loop's waits count only the
     // memory operations of the loop itself
@@ -950,8 +958,11 @@ __device__ __forceinline__ void x_wave(const BatchArgs<T> &b, const BlockMap m, 
         const T r0 = fresh(cur.r0), pb = fresh(cur.pb);
         T dv = T(0);
         if constexpr (DISS) dv = fresh(cur.dv);
-        T fk = T(0);
-        if constexpr (FLAT) fk = fresh(cur.fv);
+        double fr0 = 0.0, fp0 = 0.0;
+        if constexpr (FLAT) {
+            fr0 = fresh(cur.fr0);
+            fp0 = fresh(cur.fp0);
+        }
         __builtin_amdgcn_sched_barrier(0);
         {
             // the next item: this row's next segment, else the next row's
@@ -959,7 +970,7 @@ __device__ __forceinline__ void x_wave(const BatchArgs<T> &b, const BlockMap m, 
             const bool more = seg + 1 < rns;
             const int ni = more ? rx0 + (seg + 1) * kXOut : (nrow < rend ? nx0 : rx0 + seg * kXOut);
             const long nr = more ? row : (nrow < rend ? (long)nrow * g.px : row);
-            x_load<T, DISS, FLAT>(a.in, a.rho0, a.p0, a.div, a.flat, nc, nr, nx, bc, ni - NG + lane, cur);
+            x_load<T, DISS, FLAT>(a.in, a.rho0, a.p0, a.div, a.r064, a.p064, nc, nr, nx, bc, ni - NG + lane, cur);
         }
         const T xd = ox + (T(s) + T(0.5)) * dxT;
         const T gv = fl * gravity_now<T>(&B.g, 0, xd, rtt + xd * xd);
@@ -974,6 +985,22 @@ __device__ __forceinline__ void x_wave(const BatchArgs<T> &b, const BlockMap m, 
         q[4] = gm1 * (cu[4] - T(0.5) * (cu[1] * q[1] + cu[2] * q[2] + cu[3] * q[3]));
         T c, ic;
         sound(gam * (pb + q[4]) * ir, c, ic);
+        T fk = T(0);
+        if constexpr (FLAT) {
+            // the flattening coefficient of this lane's cell (the same FP64
+            // formulas as the flattening kernels): pressures three cells
+            // each side and velocities two, inside the segment for every
+            // cell whose parabola an owned cell's update uses (the normal
+            // momentum of a wall image is flipped already)
+            double p, u;
+            flat_pu(fr0, fp0, (double)cu[0], (double)cu[1], (double)cu[2], (double)cu[3], (double)cu[4], g.gamma,
+                    0, 1.0, p, u);
+            const double pm1 = from_left(p), pp1 = from_right(p);
+            const double pm2 = from_left(pm1), pp2 = from_right(pp1);
+            const double um1 = from_left(u), up1 = from_right(u);
+            const double r = flat_raw(pm2, pm1, pp1, pp2, um1, up1);
+            fk = T(flat_pick(pm1, pp1, from_left(r), r, from_right(r)));
+        }
 
         // (2) face values at i+1/2, second differences, limited slopes
         T qf[5], d2[5], sm[5], flm[5];

@@ -80,9 +80,14 @@ def test_flattened_steps_match_oracle_fp64(case, diss):
     compare(S.get_conserved(), O.get_conserved())
 
 
+# the x pass has two kernels: lanes along x (which evaluates the
+# coefficients of its own segment) and the marching kernel (which reads
+# those of the flattening kernel)
 @pytest.mark.parametrize("case", ["blast", "ragged"])
-@pytest.mark.parametrize("axis", [0, 1, 2])
-def test_single_flattened_pass_matches_oracle_fp64(axis, case):
+@pytest.mark.parametrize("axis,xshape", [(0, "lanes"), (0, "march"), (1, "lanes"), (2, "lanes")])
+def test_single_flattened_pass_matches_oracle_fp64(axis, xshape, case, monkeypatch):
+    if xshape == "march":
+        monkeypatch.setenv("PPMB_X_MARCH", "1")
     prob = pr.blast(20) if case == "blast" else ragged((1, 0, 1))
     S, O = setup(prob, False)
     O.run(3, 0.8)                        # a developed blast, then one pass each
