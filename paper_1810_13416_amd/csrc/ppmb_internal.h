@@ -45,6 +45,15 @@ int pass_blocks(const Geom &g, int axis, const PassShape &sh);
 // blocks longest first, so that the short ones fill the end of a launch.
 double pass_block_cost(const Geom &g, int axis, const PassShape &sh, int local);
 
+// Event counters (limiter, unsmooth, Riemann) are spread over slots a
+// cache line apart, one for each residue of the block index, so that the
+// waves' atomic adds (one per wave and counter) do not all queue on one
+// address; readers sum the slots.  Element 3 of slot 0 is the Courant-check
+// flag, which no pass adds to.
+constexpr int kCntSlots = 64;
+constexpr int kCntStride = 16;                      // words per slot: 128 bytes
+constexpr int kCntWords = kCntSlots * kCntStride;
+
 // Fused 1-D pass along `axis` for the bricks whose blocks are
 // map[0 .. nblocks): one launch, every brick's pencils.  With `cfl` set the
 // pass also folds the signal speed of the fluid cells it writes into the
@@ -55,22 +64,15 @@ double pass_block_cost(const Geom &g, int axis, const PassShape &sh, int local);
 // whenever that maximum reaches the edge; base64 is the FP64 base arena.
 // With dissk > 0 the shock dissipation is added at every face between fluid
 // cells from `div` (launch_divergence of the pass input or of the state at
-// the start of the step).  With `flat` (launch_flattening of the pass input
-// along `axis`) every parabola is flattened by its cell's coefficient.
+// the start of the step).  With `flat` every parabola is flattened by its
+// cell's coefficient: the marching kernel reads it from `flat`
+// (launch_flattening of the pass input along `axis`), the lanes-along-x
+// kernel evaluates it itself.
 // With `skip` (solid cells hold the same values in `in` and `out`) the
 // pass neither loads nor writes solid cells farther than the stencil reach
 // from a fluid cell: a wave of pencils marches over the union of their
 // fluid intervals, the x pass visits only the 56-cell segments holding
 // fluid cells.
-// Event counters (limiter, unsmooth, Riemann) are spread over slots a
-// cache line apart, one for each residue of the block index, so that the
-// waves' atomic adds (one per wave and counter) do not all queue on one
-// address; readers sum the slots.  Element 3 of slot 0 is the Courant-check
-// flag, which no pass adds to.
-constexpr int kCntSlots = 64;
-constexpr int kCntStride = 16;                      // words per slot: 128 bytes
-constexpr int kCntWords = kCntSlots * kCntStride;
-
 template <typename T>
 hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, const BlockMap *map,
                         int nblocks, const T *in, T *out, const T *base, const double *dt,
