@@ -518,10 +518,12 @@ static ppmb_status enqueue_pass(ppmb_ctx *c, int axis, int heat, int b0, int b1,
         const int g0 = c->ffirst[axis][b0], g1 = c->ffirst[axis][b1];
         if (c->prec == PPMB_FP64)
             HIPCHK(c, launch_flattening<double>(axis, c->db, c->fmap[axis] + g0, g1 - g0, arena<double>(c, from),
-                                                c->base64, static_cast<double *>(c->flatbuf), c->stream));
+                                                c->base64, static_cast<double *>(c->flatbuf), c->skip_on ? 1 : 0,
+                                                c->stream));
         else
             HIPCHK(c, launch_flattening<float>(axis, c->db, c->fmap[axis] + g0, g1 - g0, arena<float>(c, from),
-                                               c->base64, static_cast<float *>(c->flatbuf), c->stream));
+                                               c->base64, static_cast<float *>(c->flatbuf), c->skip_on ? 1 : 0,
+                                               c->stream));
     }
     const int f0 = c->pfirst[axis][b0], f1 = c->pfirst[axis][b1];
     ppmb_ctx::Timed tm{ nullptr, nullptr, axis };
@@ -569,10 +571,12 @@ static ppmb_status enqueue_divergence(ppmb_ctx *c, int b0, int b1, int from)
     const int f0 = c->dfirst[b0], f1 = c->dfirst[b1];
     if (c->prec == PPMB_FP64)
         HIPCHK(c, launch_divergence<double>(c->db, c->dmap + f0, f1 - f0, arena<double>(c, from), c->base64,
-                                            static_cast<double *>(c->divbuf), c->stream));
+                                            static_cast<double *>(c->divbuf), c->skip_on ? 1 : 0,
+                                            c->stream));
     else
         HIPCHK(c, launch_divergence<float>(c->db, c->dmap + f0, f1 - f0, arena<float>(c, from), c->base64,
-                                           static_cast<float *>(c->divbuf), c->stream));
+                                           static_cast<float *>(c->divbuf), c->skip_on ? 1 : 0,
+                                           c->stream));
     return PPMB_OK;
 }
 
@@ -1338,6 +1342,9 @@ ppmb_status ppmb_set_shock_dissipation(ppmb_ctx *c, double k)
             c->divbuf = nullptr;
             return fail(c, PPMB_ERR_NOMEM, "divergence field");
         }
+        // cells the divergence kernel leaves out (solid, skipped) hold a
+        // finite value from the start
+        HIPCHK(c, hipMemsetAsync(c->divbuf, 0, bytes, c->stream));
     }
     c->dissk = k;
     free_graph(c);                       // captured steps hold the previous setting
@@ -1353,6 +1360,9 @@ ppmb_status ppmb_set_flattening(ppmb_ctx *c, int on)
             c->flatbuf = nullptr;
             return fail(c, PPMB_ERR_NOMEM, "flattening field");
         }
+        // cells the flattening kernels leave out (solid, skipped) hold a
+        // coefficient in [0, 1] from the start
+        HIPCHK(c, hipMemsetAsync(c->flatbuf, 0, bytes, c->stream));
     }
     c->flat_on = on != 0;
     free_graph(c);                       // captured steps hold the previous setting

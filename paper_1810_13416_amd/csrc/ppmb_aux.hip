@@ -489,7 +489,7 @@ __device__ __forceinline__ void div_load(const T *S, long fs, const double *rho0
 
 template <typename T>
 __global__ __launch_bounds__(256) void divergence_kernel(const Brick *bricks, const BlockMap *map,
-                                                         const T *arena, const double *base64, T *div)
+                                                         const T *arena, const double *base64, T *div, int skip)
 {
     __shared__ double su[2][kDivTy][kDivTx + 2];            // u at (x0 - 1 + i, y0 + j)
     __shared__ double sv[2][kDivTy + 2][kDivTx];            // v at (x0 + i, y0 - 1 + j)
@@ -506,8 +506,28 @@ __global__ __launch_bounds__(256) void divergence_kernel(const Brick *bricks, co
     const int tx = (nx + kDivTx - 1) / kDivTx, ty = (ny + kDivTy - 1) / kDivTy;
     const int x0 = (m.local % tx) * kDivTx;
     const int y0 = ((m.local / tx) % ty) * kDivTy;
-    const int z0 = (m.local / (tx * ty)) * kDivTz;
-    const int z1 = min(z0 + kDivTz, nz);
+    int z0 = (m.local / (tx * ty)) * kDivTz;
+    int z1 = min(z0 + kDivTz, nz);
+    if (skip && g.sphere) {
+        // the fluid cells of the tile's columns lie where z^2 < t - (x^2 +
+        // y^2) <= t - q, q the least x^2 + y^2 over the tile's cell centres:
+        // only those planes (2 more each side, past any rounding) are
+        // written (the same for every thread of the block)
+        auto least = [&](int axis, int a, int b) {
+            const double ca = centre(g, axis, a), cb = centre(g, axis, b);
+            return (ca <= 0.0 && cb >= 0.0) ? 0.0 : fmin(fabs(ca), fabs(cb));
+        };
+        const double lx = least(0, x0, min(x0 + kDivTx, nx) - 1);
+        const double ly = least(1, y0, min(y0 + kDivTy, ny) - 1);
+        const double h2 = g.sphere_t - (lx * lx + ly * ly);
+        if (!(h2 > 0.0)) return;                           // no fluid cell in the tile's columns
+        const double h = sqrt(h2);
+        const int ka = (int)floor((-h - g.origin[2]) / g.dx - 0.5) - 2;
+        const int kb = (int)ceil((h - g.origin[2]) / g.dx - 0.5) + 2;
+        z0 = max(z0, ka);
+        z1 = min(z1, kb + 1);
+        if (z0 >= z1) return;
+    }
     const int lane = threadIdx.x & 63;
     const int wy = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     auto elem = [&](int i, int j, int k) { return (long)i + (long)j * g.px + (long)k * g.plane; };
@@ -634,11 +654,11 @@ __global__ __launch_bounds__(256) void divergence_kernel(const Brick *bricks, co
 
 template <typename T>
 hipError_t launch_divergence(const Brick *bricks, const BlockMap *map, int nblocks, const T *state,
-                             const double *base64, T *div, hipStream_t st)
+                             const double *base64, T *div, int skip, hipStream_t st)
 {
     if (nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL((divergence_kernel<T>), dim3(nblocks), dim3(kDivTx * kDivTy), 0, st, bricks, map, state,
-                       base64, div);
+                       base64, div, skip);
     return hipGetLastError();
 }
 
@@ -714,7 +734,7 @@ int flat_blocks(const Geom &g, int axis)
 // x), windows of p (5 cells), u (4) and the raw coefficient (3).
 template <typename T, int D>
 __global__ __launch_bounds__(256) void flat_march_kernel(const Brick *bricks, const BlockMap *map, const T *arena,
-                                                         const double *base64, T *flat)
+                                                         const double *base64, T *flat, int skip)
 {
     constexpr int CB = 3 - D;
     const BlockMap m = map[blockIdx.x];
@@ -728,9 +748,33 @@ __global__ __launch_bounds__(256) void flat_march_kernel(const Brick *bricks, co
     const int tx = (nx + 63) / 64, tb = (ncb + 3) / 4;
     const int x = (m.local % tx) * 64 + (int)(threadIdx.x & 63);
     const int b = ((m.local / tx) % tb) * 4 + (int)(threadIdx.x >> 6);
-    const int c0 = (m.local / (tx * tb)) * kFlatChunk;
-    if (x >= nx || b >= ncb) return;
-    const int c1 = min(c0 + kFlatChunk, n);
+    int c0 = (m.local / (tx * tb)) * kFlatChunk;
+    int c1 = min(c0 + kFlatChunk, n);
+    const bool valid = x < nx && b < ncb;
+    if (skip && g.sphere) {
+        // the chunk's cells within kFlatReach of a fluid cell of one of the
+        // wave's pencils (their union, so that every load is still a row)
+        int lo = n, hi = -1;
+        if (valid) {
+            double xt[3];
+            xt[0] = centre(g, 0, x);
+            xt[CB] = centre(g, CB, b);
+            xt[D] = 0.0;
+            int flo, fhi;
+            fluid_interval(g, D, xt, flo, fhi);
+            if (flo <= fhi) {
+                lo = max(c0, flo - kFlatReach);
+                hi = min(c1 - 1, fhi + kFlatReach);
+            }
+        }
+        for (int off = 1; off < 64; off <<= 1) {
+            lo = min(lo, __shfl_xor(lo, off));
+            hi = max(hi, __shfl_xor(hi, off));
+        }
+        c0 = lo;
+        c1 = hi + 1;
+    }
+    if (!valid || c0 >= c1) return;
     const long sd = D == 1 ? g.px : g.plane, sb = CB == 1 ? g.px : g.plane;
     const long base = (long)x + (long)b * sb;
     double P[5] = { 0.0, 0.0, 0.0, 0.0, 0.0 }, U[4] = { 0.0, 0.0, 0.0, 0.0 }, R[3] = { 0.0, 0.0, 0.0 };
@@ -785,7 +829,7 @@ __device__ __forceinline__ double right_of(double v) { return aux_dpp<0x130>(v);
 // neighbours by DPP shifts taken on every lane.
 template <typename T>
 __global__ __launch_bounds__(256) void flat_x_kernel(const Brick *bricks, const BlockMap *map, const T *arena,
-                                                     const double *base64, T *flat)
+                                                     const double *base64, T *flat, int skip)
 {
     const BlockMap m = map[blockIdx.x];
     const Brick &B = bricks[m.brick];
@@ -822,17 +866,18 @@ __global__ __launch_bounds__(256) void flat_x_kernel(const Brick *bricks, const 
 
 template <typename T>
 hipError_t launch_flattening(int axis, const Brick *bricks, const BlockMap *map, int nblocks, const T *state,
-                             const double *base64, T *flat, hipStream_t st)
+                             const double *base64, T *flat, int skip, hipStream_t st)
 {
     if (nblocks <= 0) return hipSuccess;
     if (axis == 0)
-        hipLaunchKernelGGL((flat_x_kernel<T>), dim3(nblocks), dim3(256), 0, st, bricks, map, state, base64, flat);
+        hipLaunchKernelGGL((flat_x_kernel<T>), dim3(nblocks), dim3(256), 0, st, bricks, map, state, base64, flat,
+                           skip);
     else if (axis == 1)
         hipLaunchKernelGGL((flat_march_kernel<T, 1>), dim3(nblocks), dim3(256), 0, st, bricks, map, state, base64,
-                           flat);
+                           flat, skip);
     else
         hipLaunchKernelGGL((flat_march_kernel<T, 2>), dim3(nblocks), dim3(256), 0, st, bricks, map, state, base64,
-                           flat);
+                           flat, skip);
     return hipGetLastError();
 }
 
@@ -877,9 +922,9 @@ hipError_t launch_zero_u64(unsigned long long *dst, int count, hipStream_t st)
                                              const double *, unsigned long long *, unsigned long long *, \
                                              double, double *, hipStream_t);                              \
     template hipError_t launch_divergence<T>(const Brick *, const BlockMap *, int, const T *,          \
-                                             const double *, T *, hipStream_t);                      \
+                                             const double *, T *, int, hipStream_t);                 \
     template hipError_t launch_flattening<T>(int, const Brick *, const BlockMap *, int, const T *,     \
-                                             const double *, T *, hipStream_t);
+                                             const double *, T *, int, hipStream_t);
 PPMB_INST(float)
 PPMB_INST(double)
 

@@ -83,20 +83,27 @@ hipError_t launch_sweep(int axis, const PassShape &sh, const Brick *bricks, cons
 // Undivided velocity divergence of every cell of the bricks whose blocks
 // are map[0 .. nblocks) (div_blocks(g) blocks per brick; FP64 arithmetic,
 // stored in the working precision): field of brick B at div + B.boff / 2,
-// pitched like the state; 0 in solid cells.
+// pitched like the state; 0 in solid cells.  With `skip` a sphere's tiles
+// write only the planes that can hold fluid cells of their columns (the
+// passes read the divergence of fluid cells only); the others keep what
+// they held.
 int div_blocks(const Geom &g);
 template <typename T>
 hipError_t launch_divergence(const Brick *bricks, const BlockMap *map, int nblocks, const T *state,
-                             const double *base64, T *div, hipStream_t st);
+                             const double *base64, T *div, int skip, hipStream_t st);
 
 // Flattening coefficients (Colella & Woodward 1984, Sec. 4) of every cell
 // of the bricks whose blocks are map[0 .. nblocks) (flat_blocks(g, axis)
 // per brick) for a pass along `axis`, from `state` (FP64 arithmetic, stored
-// in the working precision): field of brick B at flat + B.boff / 2.
+// in the working precision): field of brick B at flat + B.boff / 2.  With
+// `skip` a sphere's coefficients are written only within kFlatReach cells
+// of the fluid cells along the pass (a fluid cell's update uses the
+// parabolas of its two neighbours); the others keep what they held.
 int flat_blocks(const Geom &g, int axis);
+constexpr int kFlatReach = 4;
 template <typename T>
 hipError_t launch_flattening(int axis, const Brick *bricks, const BlockMap *map, int nblocks, const T *state,
-                             const double *base64, T *flat, hipStream_t st);
+                             const double *base64, T *flat, int skip, hipStream_t st);
 
 // hydrostatic base state: FP64 RK4 node table (one thread), then cell values
 hipError_t launch_base_state(const Geom &g, int kind, const double *params, double *table,
