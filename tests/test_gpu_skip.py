@@ -1,5 +1,6 @@
 """Solid cells beyond the stencil reach are skipped by the passes (they keep
-their values, which both state buffers hold alike).  Skipping must change
+their values, which both state buffers hold alike), and the divergence and
+flattening kernels leave out the cells no pass reads.  Skipping must change
 no bit: runs with it on and off are compared bitwise, in both precisions,
 with the shock handling on, under graph replay of a batch, after a state
 change in mid-run (the next pass writes every cell again), and the solid
@@ -40,6 +41,19 @@ def test_skipping_changes_no_bit(prec, shock):
     diffs = [(q, int(np.count_nonzero(a[q] != b[q])), float(np.max(np.abs(a[q] - b[q]))),
               float(np.max(np.abs(b[q])))) for q in range(15)]
     print("skip vs no skip (field, cells differing, max |diff|, max |value|):", diffs)
+    for q in range(15):
+        assert np.array_equal(a[q], b[q]), q
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_skipping_changes_no_bit_with_the_marching_x_pass(prec, monkeypatch):
+    # the x pass by the marching kernel reads its flattening coefficients
+    # and the divergence from their kernels, which leave the far solid
+    # cells out as well
+    monkeypatch.setenv("PPMB_X_MARCH", "1")
+    prob = pr.config3(n=40)
+    a, _, _ = _run(prob, prec, True, 4, True)
+    b, _, _ = _run(prob, prec, False, 4, True)
     for q in range(15):
         assert np.array_equal(a[q], b[q]), q
 
